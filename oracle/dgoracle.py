@@ -1,0 +1,574 @@
+"""CPU oracle for the dissipative-WENO-stabilised RKDG scheme.
+
+TEST INFRASTRUCTURE ONLY.  This module is the slow, plain reference that the
+HIP library is checked against.  Only the test suite, the smoke check and the
+CPU-baseline leg of the benchmark may import it; the product path never does.
+It shares no code, tables or constants with the HIP library: Gauss rules,
+Legendre polynomials, shifts and semi-norms are all derived here, from their
+definitions, independently.
+
+Paper: J. Vedral, "Dissipative WENO stabilization of high-order discontinuous
+Galerkin methods for hyperbolic problems" (arXiv 2309.12019).
+
+What is computed, in the paper's order and notation (all FP64, PyTorch CPU ops,
+vectorised over cells only; no blocking, fusion or reordering):
+
+* Sec. 2, eq. (weak2): the semi-discrete DG operator
+      M dU/dt = R(U),
+      R_i = int_K grad(phi_i) . F(U_h) dx - int_dK phi_i H(U^-, U^+, n) ds
+  with the local Lax-Friedrichs flux H of Sec. 2 and the maximal wave speed
+  s^+ = max_{w in [0,1]} |F'(w U^- + (1-w) U^+) . n|.
+* Sec. 3, eqs. (lostab), (visc), (astab): the element-local dissipation
+      s_i = gamma_e nu_e int_K grad(phi_i) . grad(U_h) dx,
+      nu_e = lambda_e h_e / (2p),  lambda_e = ||F'(U_h)||_{L^inf(K_e)}.
+  Mode DG uses gamma_e = 0, mode LO gamma_e = 1, mode WENO the sensor below.
+* Sec. 4, eqs. (sensor), (gensensor) and the scaled Sobolev semi-norm:
+      gamma_e = min(1, ||U - U*||_e / ||U||_e)^q   (0 below the threshold b),
+      ||v||_e^2 = sum_{1<=|k|<=p} h^{2|k|-d} int_K |D^k v|^2 dx,
+  with the Hermite-WENO reconstruction U* = sum_l omega_l U_l and the linear
+  weights of Sec. 5 (omega~_0 = 1 - m_e w, omega~_l = w).
+* Sec. 2, eq. (ssp): the three-stage SSP Runge-Kutta step.
+
+Readings where the paper is silent (they are listed again, with reasons, in the
+project's design notes):
+* Candidates U_l: the polynomial of face neighbour l, continued into K_e and
+  L2-projected onto V_p(K_e), with its mean replaced by the mean of U_h on K_e.
+  The stencil is the face neighbours that exist (periodic wrap counts).
+* Smoothness indicators beta_l = ||U_l||_e^2 (the same semi-norm); nonlinear
+  weights alpha_l = omega~_l / (eps + beta_l)^r, omega_l = alpha_l / sum alpha.
+* ||U - U*||_e = 0 gives ratio 0; ||U||_e = 0 < ||U - U*||_e gives ratio inf.
+* lambda_e is the maximum of ||F'(u_h)||_2 over the volume Gauss nodes, unless
+  an override is given (the paper fixes lambda_e by hand for one test).
+* Basis: tensor Legendre polynomials on the reference cell [-1,1]^d; the
+  method is basis-independent (Sec. 2).
+* Non-periodic faces see a fixed exterior state through the same LLF flux.
+
+Pins (tests/test_oracle_*.py): Gauss rules, Legendre polynomials, mass and
+stiffness matrices and the semi-norm against closed forms; the operator, sensor
+and wave speed against a brute-force evaluation of the integrals in physical
+coordinates; conservation, zero sensor on reproduced data, symmetries and the
+RK3 amplification polynomial; Table 1 and Table 2 of Sec. 5 (DG and LO
+columns); the reverse mode against finite differences.  The Hermite candidates
+and nonlinear weights are a reading (the paper defers them to another
+reference): against the paper's WENO columns they are parity unpinned, and only
+the stated behaviour (optimal rates; WENO equal to DG with a threshold) is
+checked.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+import math
+from fractions import Fraction
+from typing import List, Optional, Sequence, Tuple
+
+import torch
+
+DTYPE = torch.float64
+
+LINADV = 0   # F(u) = v(x) u, v(x) = (vx - omega (y - cy), vy + omega (x - cx))
+BURGERS = 1  # F(u) = a u^2 / 2, a = (vx, vy)
+
+MODE_DG, MODE_LO, MODE_WENO = 0, 1, 2   # labels of Sec. 5
+
+
+# --------------------------------------------------------------------------
+# Problem description
+# --------------------------------------------------------------------------
+@dataclasses.dataclass
+class Problem:
+    """Scalar conservation law on a uniform Cartesian mesh of square cells.
+
+    Sec. 2: U_t + div F(U) = 0 on Omega, U(.,0) = U_0; discretised with the
+    broken space V_p (P_p in 1D, tensor Q_p in 2D).
+    """
+    dim: int = 1
+    nx: int = 64
+    ny: int = 1
+    x0: float = 0.0
+    x1: float = 1.0
+    y0: float = 0.0
+    y1: float = 1.0
+    periodic_x: bool = True
+    periodic_y: bool = True
+    p: int = 2
+    flux: int = LINADV
+    vx: float = 1.0
+    vy: float = 0.0
+    omega: float = 0.0
+    cx: float = 0.5
+    cy: float = 0.5
+    bc_value: float = 0.0
+    mode: int = MODE_WENO
+    q: float = 1.0
+    b: float = 0.0
+    w_nb: float = 1e-2
+    eps: float = 1e-6
+    r: float = 2.0
+    lambda_override: float = 0.0
+    quad_vol: int = 0
+    quad_face: int = 0
+    quad_proj: int = 0
+
+    # -- derived ---------------------------------------------------------
+    @property
+    def n1(self) -> int:
+        return self.p + 1
+
+    @property
+    def nloc(self) -> int:
+        return self.n1 ** self.dim
+
+    @property
+    def ncells(self) -> int:
+        return self.nx * (self.ny if self.dim == 2 else 1)
+
+    @property
+    def h(self) -> float:
+        return (self.x1 - self.x0) / self.nx
+
+    def validate(self) -> None:
+        if self.dim not in (1, 2):
+            raise ValueError("dim must be 1 or 2")
+        if not 1 <= self.p <= 4:
+            raise ValueError("p must be in 1..4")
+        if self.nx < 1 or (self.dim == 2 and self.ny < 1):
+            raise ValueError("empty mesh")
+        if self.dim == 2:
+            hy = (self.y1 - self.y0) / self.ny
+            if abs(hy - self.h) > 1e-12 * abs(self.h):
+                raise ValueError("2D cells must be square")
+
+    def qv(self) -> int:
+        """Volume Gauss points per axis (exact for the polynomial part)."""
+        if self.quad_vol:
+            return self.quad_vol
+        if self.flux == LINADV:
+            return self.p + 1
+        if self.dim == 1:
+            return -(-3 * self.p // 2)
+        return -(-(3 * self.p + 1) // 2)
+
+    def qf(self) -> int:
+        if self.quad_face:
+            return self.quad_face
+        return self.qv()
+
+    def qp(self) -> int:
+        return self.quad_proj if self.quad_proj else self.p + 2
+
+
+# --------------------------------------------------------------------------
+# One-dimensional building blocks, from their definitions
+# --------------------------------------------------------------------------
+def legendre_poly(a: int) -> List[Fraction]:
+    """Monomial coefficients of the Legendre polynomial P_a (Bonnet recursion
+    (k+1) P_{k+1} = (2k+1) x P_k - k P_{k-1}), exact rationals."""
+    prev, cur = [Fraction(1)], [Fraction(0), Fraction(1)]
+    if a == 0:
+        return prev
+    for k in range(1, a):
+        nxt = [Fraction(0)] * (k + 2)
+        for i, c in enumerate(cur):
+            nxt[i + 1] += Fraction(2 * k + 1, k + 1) * c
+        for i, c in enumerate(prev):
+            nxt[i] -= Fraction(k, k + 1) * c
+        prev, cur = cur, nxt
+    return cur
+
+
+def poly_deriv(c: Sequence[Fraction], k: int = 1) -> List[Fraction]:
+    c = list(c)
+    for _ in range(k):
+        c = [i * c[i] for i in range(1, len(c))] or [Fraction(0)]
+    return c
+
+
+def poly_eval(c: Sequence[Fraction], x: torch.Tensor) -> torch.Tensor:
+    out = torch.zeros_like(x)
+    for coef in reversed(c):
+        out = out * x + float(coef)
+    return out
+
+
+def gauss_legendre(Q: int) -> Tuple[torch.Tensor, torch.Tensor]:
+    """Gauss-Legendre nodes/weights on [-1,1]: roots of P_Q by Newton's
+    method, weights 2 / ((1 - x^2) P_Q'(x)^2)."""
+    xs, ws = [], []
+    for i in range(Q):
+        x = math.cos(math.pi * (i + 0.75) / (Q + 0.5))
+        for _ in range(100):
+            p0, p1 = 1.0, x
+            for k in range(2, Q + 1):
+                p0, p1 = p1, ((2 * k - 1) * x * p1 - (k - 1) * p0) / k
+            if Q == 1:
+                p0, p1 = 1.0, x
+            dp = Q * (x * p1 - p0) / (x * x - 1.0)
+            dx = p1 / dp
+            x -= dx
+            if abs(dx) < 1e-17:
+                break
+        p0, p1 = 1.0, x
+        for k in range(2, Q + 1):
+            p0, p1 = p1, ((2 * k - 1) * x * p1 - (k - 1) * p0) / k
+        dp = Q * (x * p1 - p0) / (x * x - 1.0)
+        xs.append(x)
+        ws.append(2.0 / ((1.0 - x * x) * dp * dp))
+    order = sorted(range(Q), key=lambda i: xs[i])
+    return (torch.tensor([xs[i] for i in order], dtype=DTYPE),
+            torch.tensor([ws[i] for i in order], dtype=DTYPE))
+
+
+# --------------------------------------------------------------------------
+# Basis on the reference cell [-1,1]^d
+# --------------------------------------------------------------------------
+class Basis:
+    """phi_j(xi) = prod_i P_{a_i}(xi_i) with j = a_0 + (p+1) a_1 (x fastest)."""
+
+    def __init__(self, dim: int, p: int):
+        self.dim, self.p, self.n1 = dim, p, p + 1
+        self.modes = [(j % self.n1, j // self.n1) if dim == 2 else (j,)
+                      for j in range(self.n1 ** dim)]
+        self.polys = [legendre_poly(a) for a in range(self.n1)]
+
+    def eval(self, pts: torch.Tensor, k: Sequence[int] = None) -> torch.Tensor:
+        """D^k phi_j at reference points pts [N, d] -> [N, nloc]."""
+        if k is None:
+            k = (0,) * self.dim
+        cols = []
+        for mode in self.modes:
+            v = torch.ones(pts.shape[0], dtype=DTYPE)
+            for ax in range(self.dim):
+                v = v * poly_eval(poly_deriv(self.polys[mode[ax]], k[ax]), pts[:, ax])
+            cols.append(v)
+        return torch.stack(cols, dim=1)
+
+
+def tensor_rule(dim: int, Q: int) -> Tuple[torch.Tensor, torch.Tensor]:
+    """Tensor Gauss rule on [-1,1]^d: points [Q^d, d] (x fastest), weights."""
+    x, w = gauss_legendre(Q)
+    if dim == 1:
+        return x[:, None].clone(), w.clone()
+    X = x.repeat(Q)                 # x fastest
+    Y = x.repeat_interleave(Q)
+    W = w.repeat(Q) * w.repeat_interleave(Q)
+    return torch.stack([X, Y], dim=1), W
+
+
+def face_rule(dim: int, Q: int, axis: int, side: int):
+    """Points on the face xi_axis = side of [-1,1]^d and their weights."""
+    if dim == 1:
+        return torch.tensor([[float(side)]], dtype=DTYPE), torch.ones(1, dtype=DTYPE)
+    t, w = gauss_legendre(Q)
+    pts = torch.empty(Q, 2, dtype=DTYPE)
+    pts[:, axis] = float(side)
+    pts[:, 1 - axis] = t
+    return pts, w
+
+
+def multi_indices(dim: int, p: int) -> List[Tuple[int, ...]]:
+    """The index set 1 <= |k| <= p of the scaled Sobolev semi-norm (Sec. 4)."""
+    if dim == 1:
+        return [(k,) for k in range(1, p + 1)]
+    return [(k1, s - k1) for s in range(1, p + 1) for k1 in range(s, -1, -1)]
+
+
+# --------------------------------------------------------------------------
+# The discretisation
+# --------------------------------------------------------------------------
+class Oracle:
+    """Plain evaluation of the paper's semi-discrete operator and time step."""
+
+    def __init__(self, prob: Problem):
+        prob.validate()
+        self.P = P = prob
+        d, p = P.dim, P.p
+        self.basis = B = Basis(d, p)
+        h = P.h
+        self.h = h
+        self.J = (h / 2.0) ** d            # dx = J dxi
+        self.Jf = (h / 2.0) ** (d - 1)     # ds = Jf ds_ref
+        self.g = 2.0 / h                   # d/dx = g d/dxi
+
+        # volume rule
+        self.vpts, self.vw = tensor_rule(d, P.qv())
+        self.V = B.eval(self.vpts)
+        self.DV = [B.eval(self.vpts, tuple(1 if i == ax else 0 for i in range(d)))
+                   for ax in range(d)]
+        # faces: (axis, side) for side in (-1, +1)
+        self.faces = [(ax, s) for ax in range(d) for s in (-1, 1)]
+        self.fpts, self.fw, self.FV, self.FVopp = [], [], [], []
+        for ax, s in self.faces:
+            pts, w = face_rule(d, P.qf(), ax, s)
+            opp = pts.clone()
+            opp[:, ax] = -float(s)      # the same physical points seen from the neighbour
+            self.fpts.append(pts)
+            self.fw.append(w)
+            self.FV.append(B.eval(pts))
+            self.FVopp.append(B.eval(opp))
+
+        # exact rule (p+1 points per axis) for mass, stiffness, projections of
+        # continued neighbour polynomials and the semi-norm
+        self.epts, self.ew = tensor_rule(d, p + 1)
+        E = B.eval(self.epts)
+        self.M = self.J * (E.T * self.ew) @ E                     # int phi_i phi_j dx
+        self.Minv = torch.linalg.inv(self.M)
+        DE = [B.eval(self.epts, tuple(1 if i == ax else 0 for i in range(d)))
+              for ax in range(d)]
+        self.K = sum(self.J * self.g ** 2 * (D.T * self.ew) @ D for D in DE)  # int grad.grad
+        # continuation of the side-s neighbour along `axis` into this cell:
+        # u_nb(xi - 2 s e_axis) projected onto V_p with the exact rule
+        Mref = (E.T * self.ew) @ E
+        self.cont = {}
+        for ax, s in self.faces:
+            shifted = self.epts.clone()
+            shifted[:, ax] -= 2.0 * s
+            Es = B.eval(shifted)
+            self.cont[(ax, s)] = torch.linalg.solve(Mref, (E.T * self.ew) @ Es)
+        # semi-norm: D^k phi at the exact nodes and the physical scale factors
+        self.sn_terms = []
+        for k in multi_indices(d, p):
+            kk = sum(k)
+            scale = h ** (2 * kk - d) * self.g ** (2 * kk) * self.J
+            self.sn_terms.append((scale, B.eval(self.epts, k)))
+
+        # mesh geometry and face-neighbour table (-1 = no neighbour)
+        ny = P.ny if d == 2 else 1
+        ix = torch.arange(P.nx).repeat(ny)
+        iy = torch.arange(ny).repeat_interleave(P.nx)
+        self.xc = P.x0 + (ix.to(DTYPE) + 0.5) * h
+        self.yc = P.y0 + (iy.to(DTYPE) + 0.5) * h
+        self.nbr = []
+        for ax, s in self.faces:
+            if ax == 0:
+                jx, jy, n, per = ix + s, iy, P.nx, P.periodic_x
+                j = jx
+            else:
+                jx, jy, n, per = ix, iy + s, ny, P.periodic_y
+                j = jy
+            if per:
+                jx, jy = jx % P.nx, jy % ny
+                idx = jx + P.nx * jy
+            else:
+                idx = torch.where((j >= 0) & (j < n), jx + P.nx * jy,
+                                  torch.full_like(jx, -1))
+            self.nbr.append(idx)
+
+    # ------------------------------------------------------------------
+    def phys(self, ref: torch.Tensor):
+        """Physical coordinates [E, N] of reference points ref [N, d]."""
+        x = self.xc[:, None] + 0.5 * self.h * ref[None, :, 0]
+        if self.P.dim == 1:
+            return x, None
+        y = self.yc[:, None] + 0.5 * self.h * ref[None, :, 1]
+        return x, y
+
+    def velocity(self, x, y):
+        """v(x) of the linear flux; (a_x, a_y) direction of the Burgers flux."""
+        P = self.P
+        if P.dim == 1:
+            return (torch.full_like(x, P.vx),)
+        vx = P.vx - P.omega * (y - P.cy)
+        vy = P.vy + P.omega * (x - P.cx)
+        return vx, vy
+
+    def flux(self, u, x, y):
+        """Components of F(u) at points."""
+        P = self.P
+        if P.flux == LINADV:
+            return [v * u for v in self.velocity(x, y)]
+        a = (P.vx,) if P.dim == 1 else (P.vx, P.vy)
+        return [ai * 0.5 * u * u for ai in a]
+
+    def dflux(self, u, x, y):
+        """Components of F'(u) at points."""
+        P = self.P
+        if P.flux == LINADV:
+            return [v + 0.0 * u for v in self.velocity(x, y)]
+        a = (P.vx,) if P.dim == 1 else (P.vx, P.vy)
+        return [ai * u for ai in a]
+
+    def llf(self, um, up, axis, side, x, y):
+        """Local Lax-Friedrichs flux H(U^-, U^+, n), n = side * e_axis (Sec. 2).
+        F'(w U^- + (1-w) U^+) . n is affine in w for both fluxes, so the
+        maximum of its modulus over [0,1] is attained at an end point."""
+        Fm = self.flux(um, x, y)[axis] * side
+        Fp = self.flux(up, x, y)[axis] * side
+        sm = torch.abs(self.dflux(um, x, y)[axis] * side)
+        sp = torch.abs(self.dflux(up, x, y)[axis] * side)
+        s_plus = torch.maximum(sm, sp)
+        return 0.5 * (Fm + Fp) - 0.5 * s_plus * (up - um)
+
+    # ------------------------------------------------------------------
+    def galerkin_residual(self, U: torch.Tensor) -> torch.Tensor:
+        """R(U) of eq. (weak2): volume term minus face-flux term."""
+        P, d = self.P, self.P.dim
+        x, y = self.phys(self.vpts)
+        uq = U @ self.V.T
+        F = self.flux(uq, x, y)
+        R = torch.zeros_like(U)
+        for ax in range(d):
+            R = R + self.J * self.g * (F[ax] * self.vw) @ self.DV[ax]
+        for f, (ax, s) in enumerate(self.faces):
+            xf, yf = self.phys(self.fpts[f])
+            um = U @ self.FV[f].T
+            nb = self.nbr[f]
+            has = nb >= 0
+            Unb = U[nb.clamp(min=0)]
+            up_in = Unb @ self.FVopp[f].T
+            up = torch.where(has[:, None], up_in, torch.full_like(up_in, P.bc_value))
+            H = self.llf(um, up, ax, s, xf, yf)
+            R = R - self.Jf * (H * self.fw[f]) @ self.FV[f]
+        return R
+
+    def seminorm2(self, C: torch.Tensor) -> torch.Tensor:
+        """||v||_e^2 for coefficient rows C [..., nloc] (Sec. 4)."""
+        out = torch.zeros(C.shape[:-1], dtype=DTYPE)
+        for scale, Dk in self.sn_terms:
+            vals = C @ Dk.T
+            out = out + scale * (vals * vals * self.ew).sum(-1)
+        return out
+
+    def candidates(self, U: torch.Tensor):
+        """Hermite candidates U_l (l = 0 own, then one per face): [E, 1+2d, nloc]
+        and a mask of which exist."""
+        P = self.P
+        cands, exists = [U], [torch.ones(U.shape[0], dtype=torch.bool)]
+        for f, (ax, s) in enumerate(self.faces):
+            nb = self.nbr[f]
+            has = nb >= 0
+            Cl = U[nb.clamp(min=0)] @ self.cont[(ax, s)].T
+            Cl = torch.cat([U[:, :1], Cl[:, 1:]], dim=1)   # mean := own mean
+            cands.append(Cl)
+            exists.append(has)
+        return torch.stack(cands, dim=1), torch.stack(exists, dim=1)
+
+    def sensor(self, U: torch.Tensor, details: bool = False):
+        """gamma_e of eqs. (sensor)/(gensensor) with the HWENO reconstruction."""
+        P = self.P
+        C, ex = self.candidates(U)
+        m_e = ex[:, 1:].sum(1).to(DTYPE)
+        lin = torch.full(ex.shape, P.w_nb, dtype=DTYPE)
+        lin[:, 0] = 1.0 - m_e * P.w_nb
+        beta = self.seminorm2(C)
+        alpha = torch.where(ex, lin / (P.eps + beta) ** P.r, torch.zeros_like(beta))
+        omega = alpha / alpha.sum(1, keepdim=True)
+        Ustar = (omega[:, :, None] * C).sum(1)
+        num2 = self.seminorm2(U - Ustar)
+        den2 = beta[:, 0]
+        one = torch.ones_like(num2)
+        # square roots taken only of positive arguments (keeps reverse mode finite)
+        num = torch.sqrt(torch.where(num2 > 0, num2, one))
+        den = torch.sqrt(torch.where(den2 > 0, den2, one))
+        ratio = torch.where(num2 > 0,
+                            torch.where(den2 > 0, num / den, torch.full_like(num, math.inf)),
+                            torch.zeros_like(num2))
+        gam = torch.clamp(ratio, max=1.0) ** P.q
+        gam = torch.where(ratio >= P.b, gam, torch.zeros_like(gam))
+        if details:
+            return gam, dict(beta=beta, omega=omega, ratio=ratio, Ustar=Ustar,
+                             cands=C, exists=ex, lin=lin)
+        return gam
+
+    def gamma(self, U: torch.Tensor) -> torch.Tensor:
+        P = self.P
+        if P.mode == MODE_DG:
+            return torch.zeros(U.shape[0], dtype=DTYPE)
+        if P.mode == MODE_LO:
+            return torch.ones(U.shape[0], dtype=DTYPE)
+        return self.sensor(U)
+
+    def max_speed(self, U: torch.Tensor) -> torch.Tensor:
+        """lambda_e = max over the volume nodes of ||F'(u_h)||_2 (eq. visc)."""
+        P = self.P
+        if P.lambda_override > 0:
+            return torch.full((U.shape[0],), P.lambda_override, dtype=DTYPE)
+        x, y = self.phys(self.vpts)
+        dF = self.dflux(U @ self.V.T, x, y)
+        if len(dF) == 1:
+            return torch.abs(dF[0]).amax(dim=1)
+        n2 = sum(c * c for c in dF)
+        pos = n2 > 0
+        return torch.where(pos, torch.sqrt(torch.where(pos, n2, torch.ones_like(n2))),
+                           torch.zeros_like(n2)).amax(dim=1)
+
+    def dissipation(self, U: torch.Tensor, gam=None) -> torch.Tensor:
+        """s_i = gamma_e nu_e int grad(phi_i) . grad(U_h) (eqs. visc, astab)."""
+        if gam is None:
+            gam = self.gamma(U)
+        nu = self.max_speed(U) * self.h / (2.0 * self.P.p)
+        return (gam * nu)[:, None] * (U @ self.K.T)
+
+    def rhs(self, U: torch.Tensor, with_gamma: bool = False):
+        """dU/dt = M^{-1} (R(U) - s(U))."""
+        gam = self.gamma(U)
+        L = (self.galerkin_residual(U) - self.dissipation(U, gam)) @ self.Minv.T
+        return (L, gam) if with_gamma else L
+
+    def step(self, U: torch.Tensor, dt: float) -> torch.Tensor:
+        """Eq. (ssp): the optimal third-order SSP Runge-Kutta step."""
+        U1 = U + dt * self.rhs(U)
+        U2 = 0.75 * U + 0.25 * U1 + 0.25 * dt * self.rhs(U1)
+        return U / 3.0 + (2.0 / 3.0) * U2 + (2.0 / 3.0) * dt * self.rhs(U2)
+
+    def run(self, U: torch.Tensor, dt: float, nsteps: int) -> torch.Tensor:
+        for _ in range(nsteps):
+            U = self.step(U, dt)
+        return U
+
+    # ------------------------------------------------------------------
+    def nodes(self, Q: int) -> torch.Tensor:
+        """Physical coordinates [E, Q^d, d] of the Q-point tensor Gauss nodes."""
+        ref, _ = tensor_rule(self.P.dim, Q)
+        x, y = self.phys(ref)
+        return x[..., None] if y is None else torch.stack([x, y], dim=-1)
+
+    def proj_nodes(self) -> torch.Tensor:
+        return self.nodes(self.P.qp())
+
+    def project(self, u_at_nodes: torch.Tensor, Q: Optional[int] = None) -> torch.Tensor:
+        """L2 projection c = M^{-1} int phi u0 dx with the Q-point rule."""
+        Q = Q or self.P.qp()
+        ref, w = tensor_rule(self.P.dim, Q)
+        Phi = self.basis.eval(ref)
+        b = self.J * (u_at_nodes * w) @ Phi
+        return b @ self.Minv.T
+
+    def evaluate(self, U: torch.Tensor, Q: int):
+        """u_h at the Q-point nodes of every cell, and the node weights (dx)."""
+        ref, w = tensor_rule(self.P.dim, Q)
+        return U @ self.basis.eval(ref).T, self.J * w
+
+    def l1_error(self, U: torch.Tensor, exact_at_nodes: torch.Tensor, Q: int) -> float:
+        uh, w = self.evaluate(U, Q)
+        return float((torch.abs(uh - exact_at_nodes) * w).sum())
+
+    def mass(self, U: torch.Tensor) -> float:
+        """int u_h dx over the mesh."""
+        uh, w = self.evaluate(U, self.P.p + 1)
+        return float((uh * w).sum())
+
+    def window_functional(self, U: torch.Tensor, wx: Tuple[float, float],
+                          wy: Tuple[float, float]) -> torch.Tensor:
+        """J(U) = int_W u_h^2 dx over an axis-aligned window W made of whole cells."""
+        uh, w = self.evaluate(U, self.P.p + 1)
+        inside = (self.xc > wx[0]) & (self.xc < wx[1])
+        if self.P.dim == 2:
+            inside = inside & (self.yc > wy[0]) & (self.yc < wy[1])
+        return ((uh * uh * w).sum(1) * inside.to(DTYPE)).sum()
+
+    # ------------------------------------------------------------------
+    def step_vjp(self, U: torch.Tensor, dt: float, lam: torch.Tensor) -> torch.Tensor:
+        """Discrete adjoint of one step: (d step / d U)^T lam, by reverse-mode
+        differentiation of `step` (exact up to rounding)."""
+        Ur = U.detach().clone().requires_grad_(True)
+        out = self.step(Ur, dt)
+        (g,) = torch.autograd.grad(out, Ur, lam)
+        return g
+
+    def run_grad(self, U0: torch.Tensor, dt: float, nsteps: int, objective) -> torch.Tensor:
+        """Gradient of objective(U^N) with respect to U^0 (reverse mode)."""
+        Ur = U0.detach().clone().requires_grad_(True)
+        Jv = objective(self.run(Ur, dt, nsteps))
+        (g,) = torch.autograd.grad(Jv, Ur)
+        return g

@@ -1,0 +1,269 @@
+"""Seeded synthetic workloads: problem descriptions and initial data.
+
+This module holds no arithmetic of the method itself.  It describes problems
+(mesh, degree, flux, sensor settings, time step, step count) and evaluates
+initial data at whatever points a caller provides.  The HIP binding and the CPU
+oracle both consume it; neither is imported here.
+
+Workload shapes follow the paper's scalar test problems (Sec. 5): 1D linear
+advection of a smooth wave plus a square pulse, solid-body rotation of a smooth
+hump and a slotted cylinder, and inviscid Burgers with smooth data that steepens
+into shocks.  Random centres, radii, Fourier modes and problem mixes are drawn
+from numpy's default_rng(seed).
+"""
+
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Callable, List, Optional
+
+import numpy as np
+
+LINADV, BURGERS = 0, 1
+MODE_DG, MODE_LO, MODE_WENO = 0, 1, 2
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str = "adv1d"
+    dim: int = 1
+    nx: int = 64
+    ny: int = 1
+    x0: float = 0.0
+    x1: float = 1.0
+    y0: float = 0.0
+    y1: float = 1.0
+    periodic_x: bool = True
+    periodic_y: bool = True
+    p: int = 2
+    flux: int = LINADV
+    vx: float = 1.0
+    vy: float = 0.0
+    omega: float = 0.0
+    cx: float = 0.5
+    cy: float = 0.5
+    bc_value: float = 0.0
+    mode: int = MODE_WENO
+    q: float = 1.0
+    b: float = 0.0
+    w_nb: float = 1e-2
+    eps: float = 1e-6
+    r: float = 2.0
+    lambda_override: float = 0.0
+    cfl: float = 0.1
+    steps: int = 100
+    ic: Optional[Callable] = None      # ic(x) in 1D, ic(x, y) in 2D (numpy)
+    umax: float = 1.0                  # bound on |u0| used for the time step
+
+    @property
+    def h(self) -> float:
+        return (self.x1 - self.x0) / self.nx
+
+    @property
+    def ncells(self) -> int:
+        return self.nx * (self.ny if self.dim == 2 else 1)
+
+    @property
+    def nloc(self) -> int:
+        return (self.p + 1) ** self.dim
+
+    @property
+    def ndof(self) -> int:
+        return self.ncells * self.nloc
+
+    def max_speed(self) -> float:
+        """Upper bound of ||F'(u)||_2 over the domain for the initial data."""
+        if self.flux == LINADV:
+            if self.dim == 1:
+                return abs(self.vx)
+            far = max(math.hypot(x - self.cx, y - self.cy)
+                      for x in (self.x0, self.x1) for y in (self.y0, self.y1))
+            return math.hypot(abs(self.vx), abs(self.vy)) + abs(self.omega) * far
+        a = abs(self.vx) if self.dim == 1 else math.hypot(self.vx, self.vy)
+        return a * self.umax
+
+    def dt(self) -> float:
+        """Fixed step: dt = CFL h / ((2p+1) max speed)."""
+        return self.cfl * self.h / ((2 * self.p + 1) * self.max_speed())
+
+    def fields(self) -> dict:
+        """Plain field dictionary (everything but the initial-data callable)."""
+        d = dataclasses.asdict(self)
+        d.pop("ic")
+        return d
+
+    def eval_ic(self, pts: np.ndarray) -> np.ndarray:
+        """Initial data at points pts [..., dim]."""
+        pts = np.asarray(pts, dtype=np.float64)
+        if self.dim == 1:
+            return self.ic(pts[..., 0])
+        return self.ic(pts[..., 0], pts[..., 1])
+
+
+# ---------------------------------------------------------------------------
+# initial data
+# ---------------------------------------------------------------------------
+def sin_plus_pulse(x):
+    """sin(2 pi x) plus a unit square pulse on [0.3, 0.5]."""
+    x = np.asarray(x)
+    return np.sin(2 * np.pi * x) + ((x >= 0.3) & (x <= 0.5)).astype(np.float64)
+
+
+def cos_wave(x):
+    """cos(2 pi (x - 0.5)), the smooth advection datum of Sec. 5.1."""
+    return np.cos(2 * np.pi * (np.asarray(x) - 0.5))
+
+
+def sin_wave(x):
+    """sin(2 pi x), the Burgers datum of Sec. 5.2."""
+    return np.sin(2 * np.pi * np.asarray(x))
+
+
+def square_and_bump(x):
+    """Square wave on [0.15, 0.45] and a cos^2 bump on (0.55, 0.85) (Sec. 5.1)."""
+    x = np.asarray(x)
+    sq = ((x >= 0.15) & (x <= 0.45)).astype(np.float64)
+    bump = np.where((x > 0.55) & (x < 0.85), np.cos(10 * np.pi / 3 * (x - 0.7)) ** 2, 0.0)
+    return sq + bump
+
+
+class HumpAndCylinder:
+    """A smooth cosine hump and a slotted cylinder with seeded centres and radii.
+
+    Hump: (1 + cos(pi rho / r)) / 4 for rho <= r.  Cylinder: height 1, a slot of
+    half-width r/6 cut from the side facing the domain centre up to 2r/3 past
+    the cylinder centre (the paper's shape, Sec. 5.3, scaled by r/0.15).
+    Radii uniform in [0.1, 0.2]; centres at polar radius in [0.15, 0.48 - r]
+    about (0.5, 0.5), non-overlapping (rejection sampling)."""
+
+    def __init__(self, seed: int):
+        rng = np.random.default_rng(seed)
+        while True:
+            shapes = []
+            for _ in range(2):
+                r = rng.uniform(0.1, 0.2)
+                rad = rng.uniform(0.15, 0.48 - r)
+                ang = rng.uniform(0.0, 2 * np.pi)
+                shapes.append((0.5 + rad * np.cos(ang), 0.5 + rad * np.sin(ang), r))
+            (x1, y1, r1), (x2, y2, r2) = shapes
+            if math.hypot(x1 - x2, y1 - y2) > r1 + r2 + 1e-3:
+                break
+        self.hump, self.cyl = shapes
+
+    def __call__(self, x, y):
+        x, y = np.asarray(x), np.asarray(y)
+        hx, hy, hr = self.hump
+        rho = np.hypot(x - hx, y - hy)
+        u = np.where(rho <= hr, 0.25 * (1 + np.cos(np.pi * rho / hr)), 0.0)
+        cx, cy, cr = self.cyl
+        ox, oy = cx - 0.5, cy - 0.5
+        on = math.hypot(ox, oy)
+        ex, ey = ox / on, oy / on                 # outward radial unit vector
+        s = (x - cx) * ex + (y - cy) * ey         # along the radial direction
+        t = -(x - cx) * ey + (y - cy) * ex        # across it
+        inside = np.hypot(x - cx, y - cy) <= cr
+        slot = (np.abs(t) < cr / 6) & (s < 2 * cr / 3)
+        return u + np.where(inside & ~slot, 1.0, 0.0)
+
+
+class FourierModes:
+    """u0 = sum_j a_j cos(2 pi k_j . x + phi_j): 16 modes, integer wave vectors
+    with 1 <= |k| <= 8 drawn uniformly, a_j ~ N(0,1)/|k_j|^2, phi_j ~ U[0, 2pi)."""
+
+    def __init__(self, seed: int, nmodes: int = 16, kmax: int = 8, dim: int = 2):
+        rng = np.random.default_rng(seed)
+        if dim == 2:
+            cand = [(i, j) for i in range(-kmax, kmax + 1) for j in range(-kmax, kmax + 1)
+                    if 1 <= math.hypot(i, j) <= kmax]
+        else:
+            cand = [(i, 0) for i in range(-kmax, kmax + 1) if 1 <= abs(i) <= kmax]
+        idx = rng.integers(0, len(cand), size=nmodes)
+        self.k = np.array([cand[i] for i in idx], dtype=np.float64)
+        kn = np.hypot(self.k[:, 0], self.k[:, 1])
+        self.a = rng.standard_normal(nmodes) / kn ** 2
+        self.phi = rng.uniform(0.0, 2 * np.pi, size=nmodes)
+        self.dim = dim
+
+    def __call__(self, x, y=None):
+        x = np.asarray(x)
+        y = np.zeros_like(x) if y is None else np.asarray(y)
+        arg = 2 * np.pi * (x[..., None] * self.k[:, 0] + y[..., None] * self.k[:, 1]) + self.phi
+        return (self.a * np.cos(arg)).sum(-1)
+
+    def bound(self) -> float:
+        return float(np.abs(self.a).sum())
+
+    def shock_time(self, n: int = 1024) -> float:
+        """t_c = 1 / max(-(d/dx + d/dy) u0) for u_t + (u^2/2)_x + (u^2/2)_y = 0,
+        evaluated on an n x n sample."""
+        g = (np.arange(n) + 0.5) / n
+        X, Y = np.meshgrid(g, g, indexing="xy")
+        arg = 2 * np.pi * (X[..., None] * self.k[:, 0] + Y[..., None] * self.k[:, 1]) + self.phi
+        ksum = self.k[:, 0] + (self.k[:, 1] if self.dim == 2 else 0.0)
+        du = (-self.a * 2 * np.pi * ksum * np.sin(arg)).sum(-1)
+        return 1.0 / float(np.max(-du))
+
+
+# ---------------------------------------------------------------------------
+# the benchmark workloads
+# ---------------------------------------------------------------------------
+def adv1d(nx: int = 64, p: int = 2, mode: int = MODE_WENO, steps: int = 100,
+          cfl: float = 0.1) -> Workload:
+    """1D u_t + u_x = 0 on periodic [0,1], sin(2 pi x) + square pulse."""
+    return Workload(name=f"adv1d_n{nx}_p{p}", dim=1, nx=nx, p=p, flux=LINADV, vx=1.0,
+                    mode=mode, steps=steps, cfl=cfl, ic=sin_plus_pulse, umax=2.0)
+
+
+def burgers1d(nx: int = 64, p: int = 2, mode: int = MODE_WENO, steps: int = 100,
+              cfl: float = 0.1) -> Workload:
+    """1D Burgers on periodic [0,1] with sin(2 pi x)."""
+    return Workload(name=f"burgers1d_n{nx}_p{p}", dim=1, nx=nx, p=p, flux=BURGERS, vx=1.0,
+                    mode=mode, steps=steps, cfl=cfl, ic=sin_wave, umax=1.0)
+
+
+def rot2d(n: int = 256, p: int = 2, seed: int = 0, mode: int = MODE_WENO,
+          steps: int = 200, cfl: float = 0.1, ny: Optional[int] = None) -> Workload:
+    """Solid-body rotation v = (-(y-0.5), x-0.5) on [0,1] x [0, ny/n], zero
+    inflow state on every boundary face, seeded hump + slotted cylinder."""
+    ny = n if ny is None else ny
+    return Workload(name=f"rot2d_{n}x{ny}_p{p}_s{seed}", dim=2, nx=n, ny=ny,
+                    y1=ny / n, periodic_x=False, periodic_y=False, p=p, flux=LINADV,
+                    vx=0.0, vy=0.0, omega=1.0, cx=0.5, cy=0.5, bc_value=0.0, mode=mode,
+                    steps=steps, cfl=cfl, ic=HumpAndCylinder(seed), umax=1.0)
+
+
+def burgers2d(n: int = 1024, p: int = 2, seed: int = 0, mode: int = MODE_WENO,
+              steps: Optional[int] = None, cfl: float = 0.1,
+              t_end_factor: float = 1.5, ny: Optional[int] = None) -> Workload:
+    """2D Burgers u_t + (u^2/2)_x + (u^2/2)_y = 0, periodic, seeded Fourier data.
+    Without an explicit step count it runs to t_end_factor times the shock time."""
+    ny = n if ny is None else ny
+    fm = FourierModes(seed)
+    w = Workload(name=f"burgers2d_{n}x{ny}_p{p}_s{seed}", dim=2, nx=n, ny=ny, y1=ny / n,
+                 p=p, flux=BURGERS, vx=1.0, vy=1.0, mode=mode, cfl=cfl, ic=fm,
+                 umax=fm.bound(), steps=1)
+    if steps is None:
+        steps = int(math.ceil(t_end_factor * fm.shock_time() / w.dt()))
+    w.steps = steps
+    return w
+
+
+def batch_mix(seed: int = 0, count: int = 512, steps: int = 100) -> List[Workload]:
+    """Independent problems: type uniform over {1D advection, 1D Burgers, 2D
+    rotation}; 1D cells log-uniform in [64, 4096]; 2D side log-uniform in
+    [32, 512]; degree uniform in 1..4."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        kind = int(rng.integers(0, 3))
+        p = int(rng.integers(1, 5))
+        if kind < 2:
+            n = int(round(math.exp(rng.uniform(math.log(64), math.log(4096)))))
+            w = adv1d(n, p, steps=steps) if kind == 0 else burgers1d(n, p, steps=steps)
+        else:
+            n = int(round(math.exp(rng.uniform(math.log(32), math.log(512)))))
+            w = rot2d(n, p, seed=seed * 100003 + i, steps=steps)
+        w.name = f"b{i}_{w.name}"
+        out.append(w)
+    return out

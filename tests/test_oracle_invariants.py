@@ -1,0 +1,170 @@
+"""Invariants the paper and the mathematics fix, checked on the oracle."""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+import torch
+
+from helpers import oracle_for, oracle_initial, oracle_problem
+from paper_2309_12019_amd import inputs
+
+
+def linear_operator(O):
+    """Matrix of the (linear) semi-discrete operator U -> dU/dt."""
+    n = O.P.ncells * O.P.nloc
+    I = torch.eye(n, dtype=torch.float64).reshape(n, O.P.ncells, O.P.nloc)
+    return torch.stack([O.rhs(I[k]).reshape(-1) for k in range(n)], 1).numpy()
+
+
+@pytest.mark.parametrize("make", [
+    lambda: inputs.adv1d(24, 2),
+    lambda: inputs.burgers1d(24, 3),
+    lambda: inputs.burgers2d(8, 2, steps=1),
+])
+def test_mass_conservation_periodic(make):
+    """Sec. 2: the LLF flux is conservative and the dissipation has a zero mean
+    row, so int u_h is constant for periodic problems."""
+    w = make()
+    O = oracle_for(w)
+    U = oracle_initial(w, O)
+    m0 = O.mass(U)
+    scale = O.mass(U.abs())
+    for _ in range(10):
+        U = O.step(U, w.dt())
+    assert abs(O.mass(U) - m0) <= 1e-13 * scale
+
+
+def test_dissipation_mean_row_is_zero():
+    w = inputs.rot2d(6, 3, mode=inputs.MODE_LO)
+    O = oracle_for(w)
+    U = torch.from_numpy(np.random.default_rng(0).standard_normal((w.ncells, w.nloc)))
+    assert torch.all(O.K[0] == 0) and torch.all(O.K[:, 0] == 0)
+    s = O.dissipation(U)
+    assert torch.all(s[:, 0] == 0)
+
+
+@pytest.mark.parametrize("dim,p", [(1, 1), (1, 2), (1, 3), (1, 4), (2, 1), (2, 2), (2, 3)])
+def test_reproduced_data_gives_zero_sensor(dim, p):
+    """A global polynomial of degree <= p plus an arbitrary constant per cell is
+    reproduced by every candidate, so U - U* has zero semi-norm and gamma = 0."""
+    rng = np.random.default_rng(p)
+    if dim == 1:
+        w = inputs.adv1d(9, p)
+        w.periodic_x = False
+        coef = rng.standard_normal(p + 1)
+        w.ic = lambda x: np.polynomial.polynomial.polyval(x, coef)
+    else:
+        w = inputs.rot2d(6, p)
+        C = rng.standard_normal((p + 1, p + 1))
+        w.ic = lambda x, y: np.polynomial.polynomial.polyval2d(x, y, C)
+    O = oracle_for(w)
+    U = oracle_initial(w, O)
+    U[:, 0] += torch.from_numpy(rng.standard_normal(w.ncells))
+    gam = O.sensor(U)
+    assert float(gam.max()) < 1e-12
+    wd = oracle_problem(w)
+    wd.mode = inputs.MODE_DG
+    Ld = type(O)(wd).rhs(U)
+    Lw = O.rhs(U)
+    assert float((Lw - Ld).abs().max()) <= 1e-13 * float(Ld.abs().max() + 1)
+
+
+def test_sensor_range_and_constant_shift():
+    w = inputs.rot2d(7, 2)
+    O = oracle_for(w)
+    U = torch.from_numpy(np.random.default_rng(5).standard_normal((w.ncells, w.nloc)))
+    g = O.sensor(U)
+    assert float(g.min()) >= 0.0 and float(g.max()) <= 1.0
+    assert (g > 0).all() and (g < 1).any()
+    U2 = U.clone()
+    U2[:, 0] += 3.7
+    assert torch.allclose(O.sensor(U2), g, rtol=1e-12, atol=1e-14)
+
+
+def test_sensor_threshold_b():
+    """eq. (gensensor): gamma^b equals gamma where the ratio reaches b, else 0."""
+    w = inputs.adv1d(30, 2)
+    O = oracle_for(w)
+    U = oracle_initial(w, O)
+    g0, det = O.sensor(U, details=True)
+    b = float(det["ratio"].median())
+    pb = oracle_problem(w)
+    pb.b = b
+    gb = type(O)(pb).sensor(U)
+    keep = det["ratio"] >= b
+    assert keep.any() and (~keep).any()
+    assert torch.equal(gb[keep], g0[keep]) and torch.all(gb[~keep] == 0)
+
+
+def test_sensor_q_exponent():
+    w = inputs.adv1d(30, 2)
+    O = oracle_for(w)
+    U = oracle_initial(w, O)
+    g1 = O.sensor(U)
+    pq = oracle_problem(w)
+    pq.q = 2.0
+    g2 = type(O)(pq).sensor(U)
+    assert torch.allclose(g2, g1 ** 2, rtol=1e-13, atol=1e-300)
+
+
+def test_mirror_symmetry_1d():
+    """Reflecting x -> -x maps c_a -> (-1)^a c_a and reverses the cells; the
+    sensor is geometric, so gamma is reflected too; advection with v -> -v
+    commutes with the reflection."""
+    w = inputs.adv1d(17, 3)
+    O = oracle_for(w)
+    U = torch.from_numpy(np.random.default_rng(2).standard_normal((w.ncells, w.nloc)))
+    sgn = torch.tensor([(-1.0) ** a for a in range(w.nloc)], dtype=torch.float64)
+    R = U.flip(0) * sgn
+    assert torch.allclose(O.sensor(R), O.sensor(U).flip(0), rtol=1e-12)
+    wm = inputs.adv1d(17, 3)
+    wm.vx = -1.0
+    Om = oracle_for(wm)
+    assert torch.allclose(Om.rhs(R), O.rhs(U).flip(0) * sgn, rtol=1e-12, atol=1e-11)
+
+
+@pytest.mark.parametrize("mode", [inputs.MODE_DG, inputs.MODE_LO])
+def test_ssp_rk3_is_the_cubic_taylor_polynomial(mode):
+    """Eq. (ssp) applied to a linear operator A equals I + dtA + (dtA)^2/2 + (dtA)^3/6."""
+    w = inputs.adv1d(12, 2, mode=mode)
+    O = oracle_for(w)
+    A = linear_operator(O)
+    dt = 0.37 * w.h
+    Z = dt * A
+    S = np.eye(A.shape[0]) + Z + Z @ Z / 2 + Z @ Z @ Z / 6
+    U = torch.from_numpy(np.random.default_rng(1).standard_normal((w.ncells, w.nloc)))
+    got = O.step(U, dt).reshape(-1).numpy()
+    assert np.allclose(got, S @ U.reshape(-1).numpy(), rtol=1e-13, atol=1e-13)
+
+
+def test_ssp_rk3_third_order_in_time():
+    w = inputs.adv1d(8, 1, mode=inputs.MODE_DG)
+    O = oracle_for(w)
+    A = linear_operator(O)
+    U0 = oracle_initial(w, O)
+    T = 0.25
+    ref = scipy.linalg.expm(T * A) @ U0.reshape(-1).numpy()
+    errs = []
+    for n in (20, 40):
+        errs.append(np.abs(O.run(U0, T / n, n).reshape(-1).numpy() - ref).max())
+    assert 7.0 < errs[0] / errs[1] < 9.0
+
+
+@pytest.mark.parametrize("p,limit", [(1, 0.409), (2, 0.209), (3, 0.130), (4, 0.089)])
+def test_dg_stability_limits(p, limit):
+    """The upwind DG operator with SSP-RK3 is linearly stable up to the known
+    Courant numbers dt |v| / h = 0.409, 0.209, 0.130, 0.089 (p = 1..4)."""
+    w = inputs.adv1d(40, p, mode=inputs.MODE_DG)
+    O = oracle_for(w)
+    lam = np.linalg.eigvals(linear_operator(O)) * w.h
+
+    def stable(c):
+        z = c * lam
+        return np.abs(1 + z + z * z / 2 + z ** 3 / 6).max() <= 1 + 1e-10
+
+    lo, hi = 0.01, 1.0
+    for _ in range(50):
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if stable(mid) else (lo, mid)
+    assert abs(lo - limit) < 0.002
