@@ -1,0 +1,152 @@
+/*
+ * dgweno.h - C ABI of the MI355X (gfx950) library for the dissipative-WENO
+ * stabilised Runge-Kutta discontinuous Galerkin scheme of
+ *   J. Vedral, "Dissipative WENO stabilization of high-order discontinuous
+ *   Galerkin methods for hyperbolic problems", arXiv 2309.12019.
+ *
+ * Problem (Sec. 2, eq. ivp): u_t + div F(u) = 0 for a scalar u on a uniform
+ * Cartesian mesh of square cells (1D or 2D), with
+ *   DG_FLUX_LINADV : F(u) = v(x) u,  v = (vel_x - omega (y - rot_cy),
+ *                                         vel_y + omega (x - rot_cx))
+ *   DG_FLUX_BURGERS: F(u) = a u^2 / 2, a = (vel_x, vel_y)
+ * discretised in the broken space V_p (Sec. 2): tensor Legendre polynomials
+ * of degree p per axis on every cell.  The library evaluates
+ *   dU/dt = M^{-1} (R(U) - s(U))
+ * where R is the DG residual of eq. (weak2) with the local Lax-Friedrichs
+ * flux (Sec. 2), s the dissipative term of eq. (astab) with
+ * nu_e = lambda_e h / (2p) (eq. visc), and gamma_e the WENO smoothness sensor
+ * of eqs. (sensor)/(gensensor) (Sec. 4); it advances U with the SSP-RK3 step
+ * of eq. (ssp).
+ *
+ * Data layout of a state U (caller-owned device memory, FP64, contiguous):
+ *   U[cell * n_loc + j], cell = ix + nx * iy (x fastest), n_loc = (p+1)^dim,
+ *   j = a + (p+1) * b where a is the x-degree and b the y-degree of the
+ *   Legendre product P_a(xi) P_b(eta) on the reference cell [-1,1]^dim.
+ *
+ * Conventions for every entry point:
+ *   - Return 0 on success, a negative DG_E* code on failure; the message of
+ *     the last failure on the calling thread is returned by dg_last_error().
+ *   - Argument errors are detected before any device work is queued.
+ *   - Pointers named "device" are device memory owned by the caller; the
+ *     library never frees them.  Work is queued on the context's stream
+ *     (dg_mesh_desc.stream, 0 = the default stream) and is asynchronous
+ *     unless stated otherwise.
+ *   - A context is not thread-safe; separate contexts are independent.
+ */
+#ifndef DGWENO_H
+#define DGWENO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum dg_status {
+  DG_OK = 0,
+  DG_EINVAL = -1,       /* invalid argument (checked on the host) */
+  DG_ENOMEM = -2,       /* device allocation failed */
+  DG_EDEVICE = -3,      /* a HIP runtime call failed */
+  DG_ENONFINITE = -4,   /* a state contained NaN or Inf (dg_check_finite) */
+  DG_EUNSUPPORTED = -5  /* valid but not built (e.g. an unsupported size) */
+};
+
+enum dg_flux { DG_FLUX_LINADV = 0, DG_FLUX_BURGERS = 1 };
+
+/* Scheme labels of Sec. 5: DG (no stabilisation), LO (gamma_e = 1 in
+ * eq. astab, i.e. the low-order operator of eq. lostab), WENO (gamma_e from
+ * the smoothness sensor). */
+enum dg_mode { DG_MODE_DG = 0, DG_MODE_LO = 1, DG_MODE_WENO = 2 };
+
+typedef struct dg_mesh_desc {
+  int32_t dim;               /* 1 or 2 */
+  int32_t nx, ny;            /* cells along x and y (ny ignored for dim 1) */
+  double x0, x1, y0, y1;     /* domain box; 2D cells must be square */
+  int32_t periodic_x, periodic_y;   /* 1: periodic wrap along that axis */
+  int32_t p;                 /* polynomial degree, 1..4 */
+  int32_t flux;              /* enum dg_flux */
+  double vel_x, vel_y;       /* constant velocity (LINADV) or direction a (BURGERS) */
+  double omega, rot_cx, rot_cy;     /* rotation part of the LINADV velocity (2D) */
+  double bc_value;           /* exterior state u^+ on non-periodic boundary faces */
+  int32_t mode;              /* enum dg_mode */
+  double q;                  /* sensor exponent q >= 1 (eq. sensor) */
+  double b;                  /* sensor threshold b in [0,1] (eq. gensensor) */
+  double w_nb;               /* linear weight of each neighbour candidate (Sec. 5) */
+  double weno_eps, weno_pow; /* alpha_l = w_l / (eps + beta_l)^pow */
+  double lambda_override;    /* > 0: lambda_e := this value in every cell */
+  void* stream;              /* hipStream_t the context queues work on (0 = default) */
+} dg_mesh_desc;
+
+typedef struct dg_ctx dg_ctx;   /* opaque, owned by the library */
+
+/* Fill a descriptor with the defaults: 1D, 64 cells on [0,1] periodic, p = 2,
+ * LINADV with vel_x = 1, mode WENO, q = 1, b = 0, w_nb = 0.01, eps = 1e-6,
+ * pow = 2, no lambda override, default stream.  Never fails. */
+void dg_default_desc(dg_mesh_desc* desc);
+
+/* Validate `desc` and create a context on the current HIP device: mesh,
+ * compile-time tables for degree p, and two stage buffers of
+ * n_cells * n_loc doubles (the only allocations the context makes).
+ * Errors: DG_EINVAL (bad field, null pointer, non-square 2D cells),
+ * DG_ENOMEM, DG_EDEVICE.  On failure *out is set to NULL. */
+int dg_init_mesh(const dg_mesh_desc* desc, dg_ctx** out);
+
+/* Release the context and its device buffers (synchronises its stream). */
+void dg_destroy(dg_ctx* ctx);
+
+/* Sizes of the discrete problem (host outputs; any may be NULL). */
+int dg_sizes(const dg_ctx* ctx, int64_t* n_cells, int32_t* n_loc, int32_t* n_proj_nodes);
+
+/* Physical coordinates of the projection nodes, written to host memory
+ * xy[cell][node][dim] (n_cells * n_proj_nodes * dim doubles): the
+ * (p+2)^dim tensor Gauss-Legendre nodes of every cell, x fastest. */
+int dg_proj_nodes(const dg_ctx* ctx, double* xy_host);
+
+/* L2 projection of initial data onto V_p (Sec. 2, eq. fesol):
+ * U_j = (int phi_j u0 dx) / (int phi_j^2 dx), the integral taken with the
+ * projection rule.  u_at_nodes (device, [cell][node]) holds u0 at the nodes
+ * from dg_proj_nodes; U (device) receives the coefficients. */
+int dg_project_ic(dg_ctx* ctx, const double* u_at_nodes, double* U);
+
+/* Semi-discrete operator (eq. weak2 plus eq. astab): dUdt = M^{-1}(R(U) - s(U)).
+ * U, dUdt: device [n_cells * n_loc]; gamma: device [n_cells] receiving
+ * gamma_e of every cell (0 for DG, 1 for LO), or NULL.  U and dUdt must not
+ * overlap. */
+int dg_rhs(dg_ctx* ctx, const double* U, double* dUdt, double* gamma);
+
+/* One SSP-RK3 step of size dt (eq. ssp), in place on U (device).
+ * gamma_e and lambda_e are re-evaluated in every stage (Sec. 3, the
+ * stabilisation is part of the semi-discrete operator).  dt must be finite
+ * and > 0. */
+int dg_step(dg_ctx* ctx, double* U, double dt);
+
+/* nsteps SSP-RK3 steps of size dt, in place on U.  The 3 * nsteps stage
+ * launches are recorded once into a HIP graph (cached for the same U, dt and
+ * chunk length) and replayed on the context stream.  nsteps >= 0. */
+int dg_run(dg_ctx* ctx, double* U, double dt, int32_t nsteps);
+
+/* Stable step for the fixed-step reading of "CFL": dt = cfl * h /
+ * ((2p+1) * lambda_max) where lambda_max is the largest lambda_e of U (device)
+ * over the mesh.  Synchronous; writes the host double *dt_host. */
+int dg_stable_dt(dg_ctx* ctx, const double* U, double cfl, double* dt_host);
+
+/* Check U (device) for NaN/Inf.  Synchronous.  Returns DG_OK, or
+ * DG_ENONFINITE and the number of non-finite entries in *count (may be NULL). */
+int dg_check_finite(dg_ctx* ctx, const double* U, int64_t* count);
+
+/* Launch shape of the stage kernel: tx * ty cells per workgroup (2D), tx cells
+ * (1D, ty ignored).  tx * ty must be a multiple of 64 and at most 1024.  Used
+ * by the tuner; the default is chosen at dg_init_mesh. */
+int dg_set_tile(dg_ctx* ctx, int32_t tx, int32_t ty);
+int dg_get_tile(const dg_ctx* ctx, int32_t* tx, int32_t* ty);
+
+/* Replace the stream the context queues work on. */
+int dg_set_stream(dg_ctx* ctx, void* stream);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char* dg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DGWENO_H */

@@ -1,0 +1,446 @@
+// C-ABI of the library (declared in include/dgweno.h): argument validation,
+// context and buffer ownership, kernel dispatch, graph capture of dg_run.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <tuple>
+#include <vector>
+
+#include "../../include/dgweno.h"
+#include "dg_launch.hpp"
+
+using dgk::LaunchFn;
+using dgk::LaunchReq;
+using dgk::StageArgs;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(DG_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+LaunchFn launcher(int dim, int p) {
+  static const LaunchFn tab[2][4] = {{dgk_launch_1_1, dgk_launch_1_2, dgk_launch_1_3, dgk_launch_1_4},
+                                     {dgk_launch_2_1, dgk_launch_2_2, dgk_launch_2_3, dgk_launch_2_4}};
+  return tab[dim - 1][p - 1];
+}
+
+struct GraphKey {
+  const double* U;
+  double dt;
+  int steps;
+  bool operator<(const GraphKey& o) const { return std::tie(U, dt, steps) < std::tie(o.U, o.dt, o.steps); }
+};
+
+}  // namespace
+
+struct dg_ctx {
+  dg_mesh_desc d;
+  int nl = 0;
+  long long ncells = 0;
+  int tx = 0, ty = 1;
+  int max_lds = 65536;
+  double h = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t capture = nullptr;  // private stream used only to record graphs
+  double* U1 = nullptr;
+  double* U2 = nullptr;
+  double* red = nullptr;          // per-block partial results of reductions
+  size_t red_len = 0;
+  LaunchFn launch = nullptr;
+  std::map<GraphKey, hipGraphExec_t> graphs;
+};
+
+namespace {
+
+StageArgs base_args(const dg_ctx* c) {
+  StageArgs A{};
+  const dg_mesh_desc& d = c->d;
+  A.nx = d.nx;
+  A.ny = d.dim == 2 ? d.ny : 1;
+  A.per_x = d.periodic_x != 0;
+  A.per_y = d.dim == 2 && d.periodic_y != 0;
+  A.h = c->h;
+  A.x0 = d.x0;
+  A.y0 = d.dim == 2 ? d.y0 : 0.0;
+  A.vx = d.vel_x;
+  A.vy = d.dim == 2 ? d.vel_y : 0.0;
+  A.omega = d.dim == 2 ? d.omega : 0.0;
+  A.cx = d.rot_cx;
+  A.cy = d.rot_cy;
+  A.anorm = d.dim == 2 ? std::hypot(d.vel_x, d.vel_y) : std::fabs(d.vel_x);
+  A.bc = d.bc_value;
+  A.q = d.q;
+  A.bthr = d.b;
+  A.wnb = d.w_nb;
+  A.eps = d.weno_eps;
+  A.wpow = d.weno_pow;
+  A.lam_over = d.lambda_override;
+  A.tx = c->tx;
+  A.ty = d.dim == 2 ? c->ty : 1;
+  A.lds_stride = dgk::stage_stride(d.dim, A.tx, A.ty);
+  return A;
+}
+
+size_t stage_lds_bytes(int dim, int nl, int tx, int ty) {
+  return sizeof(double) * (size_t)nl * (size_t)dgk::stage_stride(dim, tx, dim == 2 ? ty : 1);
+}
+
+// one stage: out = a*un + b*(uin + dt*L(uin)), or out = L(uin) when rhs_only
+int stage(dg_ctx* c, hipStream_t st, const double* uin, const double* un, double* out, double* gamma,
+          double a, double b, double dt, int rhs_only) {
+  LaunchReq r{};
+  r.kind = dgk::LAUNCH_STAGE;
+  r.flux = c->d.flux;
+  r.mode = c->d.mode;
+  r.args = base_args(c);
+  r.args.uin = uin;
+  r.args.un = un;
+  r.args.out = out;
+  r.args.gamma = gamma;
+  r.args.a = a;
+  r.args.b = b;
+  r.args.dt = dt;
+  r.args.rhs_only = rhs_only;
+  r.stream = st;
+  hipError_t e = c->launch(&r);
+  if (e != hipSuccess) return hip_fail(e, "stage kernel launch");
+  return DG_OK;
+}
+
+// eq. (ssp): U1 = U + dt L(U); U2 = 3/4 U + 1/4 (U1 + dt L(U1)); U = 1/3 U + 2/3 (U2 + dt L(U2))
+int rk3_step(dg_ctx* c, hipStream_t st, double* U, double dt) {
+  int rc;
+  if ((rc = stage(c, st, U, U, c->U1, nullptr, 0.0, 1.0, dt, 0))) return rc;
+  if ((rc = stage(c, st, c->U1, U, c->U2, nullptr, 0.75, 0.25, dt, 0))) return rc;
+  return stage(c, st, c->U2, U, U, nullptr, 1.0 / 3.0, 2.0 / 3.0, dt, 0);
+}
+
+int validate(const dg_mesh_desc* d) {
+  if (!d) return fail(DG_EINVAL, "desc is NULL");
+  if (d->dim != 1 && d->dim != 2) return fail(DG_EINVAL, "dim must be 1 or 2 (got %d)", d->dim);
+  if (d->p < 1 || d->p > 4) return fail(DG_EINVAL, "p must be in 1..4 (got %d)", d->p);
+  if (d->nx < 1) return fail(DG_EINVAL, "nx must be >= 1 (got %d)", d->nx);
+  if (d->dim == 2 && d->ny < 1) return fail(DG_EINVAL, "ny must be >= 1 (got %d)", d->ny);
+  if ((long long)d->nx * (d->dim == 2 ? d->ny : 1) > (1LL << 31) - 1)
+    return fail(DG_EINVAL, "mesh too large");
+  if (!(d->x1 > d->x0) || !std::isfinite(d->x0) || !std::isfinite(d->x1))
+    return fail(DG_EINVAL, "need x0 < x1 (finite)");
+  if (d->dim == 2) {
+    if (!(d->y1 > d->y0) || !std::isfinite(d->y0) || !std::isfinite(d->y1))
+      return fail(DG_EINVAL, "need y0 < y1 (finite)");
+    const double hx = (d->x1 - d->x0) / d->nx, hy = (d->y1 - d->y0) / d->ny;
+    if (std::fabs(hx - hy) > 1e-12 * hx) return fail(DG_EINVAL, "2D cells must be square (hx=%g hy=%g)", hx, hy);
+  }
+  if (d->flux != DG_FLUX_LINADV && d->flux != DG_FLUX_BURGERS) return fail(DG_EINVAL, "unknown flux %d", d->flux);
+  if (d->mode != DG_MODE_DG && d->mode != DG_MODE_LO && d->mode != DG_MODE_WENO)
+    return fail(DG_EINVAL, "unknown mode %d", d->mode);
+  if (!(d->q >= 1.0) || !std::isfinite(d->q)) return fail(DG_EINVAL, "q must be >= 1");
+  if (!(d->b >= 0.0 && d->b <= 1.0)) return fail(DG_EINVAL, "b must be in [0,1]");
+  const int m = 2 * d->dim;
+  if (!(d->w_nb > 0.0) || !(m * d->w_nb < 1.0)) return fail(DG_EINVAL, "need 0 < w_nb < 1/(2 dim)");
+  if (!(d->weno_eps > 0.0) || !std::isfinite(d->weno_eps)) return fail(DG_EINVAL, "weno_eps must be > 0");
+  if (!(d->weno_pow > 0.0) || !std::isfinite(d->weno_pow)) return fail(DG_EINVAL, "weno_pow must be > 0");
+  if (!std::isfinite(d->lambda_override) || d->lambda_override < 0)
+    return fail(DG_EINVAL, "lambda_override must be >= 0");
+  const double vals[] = {d->vel_x, d->vel_y, d->omega, d->rot_cx, d->rot_cy, d->bc_value};
+  for (double v : vals)
+    if (!std::isfinite(v)) return fail(DG_EINVAL, "non-finite flux parameter");
+  return DG_OK;
+}
+
+int check_tile(const dg_ctx* c, int tx, int ty) {
+  const int dim = c->d.dim;
+  if (dim == 1) ty = 1;
+  if (tx < 1 || ty < 1) return fail(DG_EINVAL, "tile sizes must be >= 1");
+  const long long thr = (long long)tx * ty;
+  if (thr % 64 != 0 || thr > 256) return fail(DG_EINVAL, "tile must hold a multiple of 64 cells, at most 256");
+  if (stage_lds_bytes(dim, c->nl, tx, ty) > (size_t)c->max_lds)
+    return fail(DG_EUNSUPPORTED, "tile %dx%d needs %zu bytes of LDS (limit %d)", tx, ty,
+                stage_lds_bytes(dim, c->nl, tx, ty), c->max_lds);
+  return DG_OK;
+}
+
+void drop_graphs(dg_ctx* c) {
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+}
+
+}  // namespace
+
+extern "C" {
+
+void dg_default_desc(dg_mesh_desc* d) {
+  if (!d) return;
+  std::memset(d, 0, sizeof(*d));
+  d->dim = 1;
+  d->nx = 64;
+  d->ny = 1;
+  d->x0 = 0.0;
+  d->x1 = 1.0;
+  d->y0 = 0.0;
+  d->y1 = 1.0;
+  d->periodic_x = 1;
+  d->periodic_y = 1;
+  d->p = 2;
+  d->flux = DG_FLUX_LINADV;
+  d->vel_x = 1.0;
+  d->rot_cx = 0.5;
+  d->rot_cy = 0.5;
+  d->mode = DG_MODE_WENO;
+  d->q = 1.0;
+  d->b = 0.0;
+  d->w_nb = 1e-2;
+  d->weno_eps = 1e-6;
+  d->weno_pow = 2.0;
+}
+
+const char* dg_last_error(void) { return g_err; }
+
+int dg_init_mesh(const dg_mesh_desc* desc, dg_ctx** out) {
+  g_err[0] = 0;
+  if (!out) return fail(DG_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate(desc);
+  if (rc) return rc;
+  dg_ctx* c = new (std::nothrow) dg_ctx();
+  if (!c) return fail(DG_ENOMEM, "host allocation failed");
+  c->d = *desc;
+  if (c->d.dim == 1) c->d.ny = 1;
+  c->nl = c->d.dim == 1 ? c->d.p + 1 : (c->d.p + 1) * (c->d.p + 1);
+  c->ncells = (long long)c->d.nx * c->d.ny;
+  c->h = (c->d.x1 - c->d.x0) / c->d.nx;
+  c->stream = static_cast<hipStream_t>(desc->stream);
+  c->launch = launcher(c->d.dim, c->d.p);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(e, "hipGetDevice");
+  }
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
+    c->max_lds = lds;
+  // default tile: 256 cells in 1D; 16x16 in 2D unless the halo tile exceeds LDS
+  if (c->d.dim == 1) {
+    c->tx = 256;
+    c->ty = 1;
+  } else {
+    c->tx = 16;
+    c->ty = 16;
+    if (stage_lds_bytes(2, c->nl, 16, 16) > (size_t)c->max_lds) c->ty = 8;
+    if (stage_lds_bytes(2, c->nl, c->tx, c->ty) > (size_t)c->max_lds) c->ty = 4;
+  }
+  const size_t bytes = sizeof(double) * (size_t)c->ncells * c->nl;
+  if ((e = hipMalloc(&c->U1, bytes)) != hipSuccess || (e = hipMalloc(&c->U2, bytes)) != hipSuccess) {
+    dg_destroy(c);
+    return fail(DG_ENOMEM, "stage buffers (%zu bytes each): %s", bytes, hipGetErrorString(e));
+  }
+  c->red_len = (size_t)((c->ncells + 255) / 256) + 1;
+  if ((e = hipMalloc(&c->red, sizeof(double) * c->red_len)) != hipSuccess) {
+    dg_destroy(c);
+    return fail(DG_ENOMEM, "reduction buffer: %s", hipGetErrorString(e));
+  }
+  if ((e = hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking)) != hipSuccess) {
+    dg_destroy(c);
+    return hip_fail(e, "hipStreamCreate");
+  }
+  *out = c;
+  return DG_OK;
+}
+
+void dg_destroy(dg_ctx* c) {
+  if (!c) return;
+  if (c->stream || c->U1) (void)hipStreamSynchronize(c->stream);
+  drop_graphs(c);
+  if (c->U1) (void)hipFree(c->U1);
+  if (c->U2) (void)hipFree(c->U2);
+  if (c->red) (void)hipFree(c->red);
+  if (c->capture) (void)hipStreamDestroy(c->capture);
+  delete c;
+}
+
+int dg_sizes(const dg_ctx* c, int64_t* n_cells, int32_t* n_loc, int32_t* n_proj_nodes) {
+  if (!c) return fail(DG_EINVAL, "ctx is NULL");
+  if (n_cells) *n_cells = c->ncells;
+  if (n_loc) *n_loc = c->nl;
+  if (n_proj_nodes) *n_proj_nodes = c->d.dim == 1 ? c->d.p + 2 : (c->d.p + 2) * (c->d.p + 2);
+  return DG_OK;
+}
+
+int dg_proj_nodes(const dg_ctx* c, double* xy) {
+  if (!c || !xy) return fail(DG_EINVAL, "NULL argument");
+  const int p = c->d.p, Q = p + 2;
+  double gx[8] = {0};
+  // projection rule: Q = p + 2 Gauss points (compile-time tables per degree)
+  switch (Q) {
+    case 3: { constexpr auto g = dgk::make_gauss<3>(); for (int i = 0; i < 3; ++i) gx[i] = g.x[i]; break; }
+    case 4: { constexpr auto g = dgk::make_gauss<4>(); for (int i = 0; i < 4; ++i) gx[i] = g.x[i]; break; }
+    case 5: { constexpr auto g = dgk::make_gauss<5>(); for (int i = 0; i < 5; ++i) gx[i] = g.x[i]; break; }
+    case 6: { constexpr auto g = dgk::make_gauss<6>(); for (int i = 0; i < 6; ++i) gx[i] = g.x[i]; break; }
+    default: return fail(DG_EUNSUPPORTED, "projection rule");
+  }
+  const double hh = 0.5 * c->h;
+  const int dim = c->d.dim;
+  size_t k = 0;
+  for (long long e = 0; e < c->ncells; ++e) {
+    const long long ix = e % c->d.nx, iy = e / c->d.nx;
+    const double xc = c->d.x0 + (ix + 0.5) * c->h;
+    const double yc = c->d.y0 + (iy + 0.5) * c->h;
+    if (dim == 1) {
+      for (int q = 0; q < Q; ++q) xy[k++] = xc + hh * gx[q];
+    } else {
+      for (int qy = 0; qy < Q; ++qy)
+        for (int qx = 0; qx < Q; ++qx) {
+          xy[k++] = xc + hh * gx[qx];
+          xy[k++] = yc + hh * gx[qy];
+        }
+    }
+  }
+  return DG_OK;
+}
+
+int dg_project_ic(dg_ctx* c, const double* u_at_nodes, double* U) {
+  if (!c || !u_at_nodes || !U) return fail(DG_EINVAL, "NULL argument");
+  LaunchReq r{};
+  r.kind = dgk::LAUNCH_PROJECT;
+  r.src = u_at_nodes;
+  r.dst = U;
+  r.ncells = c->ncells;
+  r.stream = c->stream;
+  hipError_t e = c->launch(&r);
+  return e == hipSuccess ? DG_OK : hip_fail(e, "projection launch");
+}
+
+int dg_rhs(dg_ctx* c, const double* U, double* dUdt, double* gamma) {
+  if (!c || !U || !dUdt) return fail(DG_EINVAL, "NULL argument");
+  if (U == dUdt) return fail(DG_EINVAL, "U and dUdt must not overlap");
+  return stage(c, c->stream, U, nullptr, dUdt, gamma, 0.0, 1.0, 0.0, 1);
+}
+
+int dg_step(dg_ctx* c, double* U, double dt) {
+  if (!c || !U) return fail(DG_EINVAL, "NULL argument");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite and > 0");
+  return rk3_step(c, c->stream, U, dt);
+}
+
+int dg_run(dg_ctx* c, double* U, double dt, int32_t nsteps) {
+  if (!c || !U) return fail(DG_EINVAL, "NULL argument");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite and > 0");
+  if (nsteps < 0) return fail(DG_EINVAL, "nsteps must be >= 0");
+  if (nsteps == 0) return DG_OK;
+  const int chunk = nsteps < 64 ? nsteps : 64;
+  GraphKey key{U, dt, chunk};
+  auto it = c->graphs.find(key);
+  hipGraphExec_t exec = nullptr;
+  if (it != c->graphs.end()) {
+    exec = it->second;
+  } else {
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    int rc = DG_OK;
+    for (int s = 0; s < chunk && rc == DG_OK; ++s) rc = rk3_step(c, c->capture, U, dt);
+    e = hipStreamEndCapture(c->capture, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    if (c->graphs.size() >= 16) drop_graphs(c);
+    c->graphs[key] = exec;
+  }
+  const int reps = nsteps / chunk, rest = nsteps % chunk;
+  for (int i = 0; i < reps; ++i) {
+    hipError_t e = hipGraphLaunch(exec, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  }
+  for (int s = 0; s < rest; ++s) {
+    int rc = rk3_step(c, c->stream, U, dt);
+    if (rc) return rc;
+  }
+  return DG_OK;
+}
+
+int dg_stable_dt(dg_ctx* c, const double* U, double cfl, double* dt_host) {
+  if (!c || !U || !dt_host) return fail(DG_EINVAL, "NULL argument");
+  if (!(cfl > 0.0) || !std::isfinite(cfl)) return fail(DG_EINVAL, "cfl must be finite and > 0");
+  LaunchReq r{};
+  r.kind = dgk::LAUNCH_LAMBDA;
+  r.flux = c->d.flux;
+  r.args = base_args(c);
+  r.src = U;
+  r.dst = c->red;
+  r.ncells = c->ncells;
+  r.stream = c->stream;
+  hipError_t e = c->launch(&r);
+  if (e != hipSuccess) return hip_fail(e, "lambda launch");
+  const size_t nb = (size_t)((c->ncells + 255) / 256);
+  std::vector<double> h(nb);
+  if ((e = hipMemcpyAsync(h.data(), c->red, nb * sizeof(double), hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
+      (e = hipStreamSynchronize(c->stream)) != hipSuccess)
+    return hip_fail(e, "lambda readback");
+  double lam = 0.0;
+  for (double v : h) lam = v > lam ? v : lam;
+  if (!(lam > 0.0) || !std::isfinite(lam)) return fail(DG_ENONFINITE, "maximal wave speed is %g", lam);
+  *dt_host = cfl * c->h / ((2 * c->d.p + 1) * lam);
+  return DG_OK;
+}
+
+int dg_check_finite(dg_ctx* c, const double* U, int64_t* count) {
+  if (!c || !U) return fail(DG_EINVAL, "NULL argument");
+  const size_t n = (size_t)c->ncells * c->nl;
+  std::vector<double> h(n);
+  hipError_t e;
+  if ((e = hipMemcpyAsync(h.data(), U, n * sizeof(double), hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
+      (e = hipStreamSynchronize(c->stream)) != hipSuccess)
+    return hip_fail(e, "state readback");
+  int64_t bad = 0;
+  for (double v : h) bad += !std::isfinite(v);
+  if (count) *count = bad;
+  return bad ? fail(DG_ENONFINITE, "%lld non-finite entries", (long long)bad) : DG_OK;
+}
+
+int dg_set_tile(dg_ctx* c, int32_t tx, int32_t ty) {
+  if (!c) return fail(DG_EINVAL, "ctx is NULL");
+  int rc = check_tile(c, tx, ty);
+  if (rc) return rc;
+  c->tx = tx;
+  c->ty = c->d.dim == 2 ? ty : 1;
+  drop_graphs(c);
+  return DG_OK;
+}
+
+int dg_get_tile(const dg_ctx* c, int32_t* tx, int32_t* ty) {
+  if (!c) return fail(DG_EINVAL, "ctx is NULL");
+  if (tx) *tx = c->tx;
+  if (ty) *ty = c->ty;
+  return DG_OK;
+}
+
+int dg_set_stream(dg_ctx* c, void* stream) {
+  if (!c) return fail(DG_EINVAL, "ctx is NULL");
+  c->stream = static_cast<hipStream_t>(stream);
+  c->d.stream = stream;
+  return DG_OK;
+}
+
+}  // extern "C"

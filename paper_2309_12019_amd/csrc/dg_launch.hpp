@@ -1,0 +1,33 @@
+// Interface between the C-ABI layer and the per-(dim, p) kernel objects.
+#pragma once
+
+#include "dg_kernels.hpp"
+
+namespace dgk {
+
+enum LaunchKind { LAUNCH_STAGE = 0, LAUNCH_PROJECT = 1, LAUNCH_LAMBDA = 2 };
+
+struct LaunchReq {
+  int kind;
+  int flux, mode;
+  StageArgs args;       // LAUNCH_STAGE, LAUNCH_LAMBDA
+  const double* src;    // LAUNCH_PROJECT: nodal values; LAUNCH_LAMBDA: state
+  double* dst;          // LAUNCH_PROJECT: coefficients; LAUNCH_LAMBDA: block maxima
+  long long ncells;
+  hipStream_t stream;
+};
+
+typedef hipError_t (*LaunchFn)(const LaunchReq*);
+
+}  // namespace dgk
+
+extern "C" {
+hipError_t dgk_launch_1_1(const dgk::LaunchReq*);
+hipError_t dgk_launch_1_2(const dgk::LaunchReq*);
+hipError_t dgk_launch_1_3(const dgk::LaunchReq*);
+hipError_t dgk_launch_1_4(const dgk::LaunchReq*);
+hipError_t dgk_launch_2_1(const dgk::LaunchReq*);
+hipError_t dgk_launch_2_2(const dgk::LaunchReq*);
+hipError_t dgk_launch_2_3(const dgk::LaunchReq*);
+hipError_t dgk_launch_2_4(const dgk::LaunchReq*);
+}

@@ -1,0 +1,214 @@
+"""Thin ctypes binding of libdgweno.so (include/dgweno.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  Device buffers are torch tensors (float64, contiguous, on the GPU);
+work is queued on the current torch stream.  If the library is missing the
+import fails loudly; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdgweno.so")
+
+DG_OK, DG_EINVAL, DG_ENOMEM, DG_EDEVICE, DG_ENONFINITE, DG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+FLUX_LINADV, FLUX_BURGERS = 0, 1
+MODE_DG, MODE_LO, MODE_WENO = 0, 1, 2
+
+
+class DGError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"dgweno error {code}: {msg}")
+        self.code = code
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("x0", ctypes.c_double), ("x1", ctypes.c_double),
+        ("y0", ctypes.c_double), ("y1", ctypes.c_double),
+        ("periodic_x", ctypes.c_int32), ("periodic_y", ctypes.c_int32),
+        ("p", ctypes.c_int32), ("flux", ctypes.c_int32),
+        ("vel_x", ctypes.c_double), ("vel_y", ctypes.c_double),
+        ("omega", ctypes.c_double), ("rot_cx", ctypes.c_double), ("rot_cy", ctypes.c_double),
+        ("bc_value", ctypes.c_double),
+        ("mode", ctypes.c_int32),
+        ("q", ctypes.c_double), ("b", ctypes.c_double), ("w_nb", ctypes.c_double),
+        ("weno_eps", ctypes.c_double), ("weno_pow", ctypes.c_double),
+        ("lambda_override", ctypes.c_double),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+EXPORTS = {
+    # name: (restype, argtypes)
+    "dg_default_desc": (None, [ctypes.POINTER(MeshDesc)]),
+    "dg_init_mesh": (ctypes.c_int, [ctypes.POINTER(MeshDesc), ctypes.POINTER(ctypes.c_void_p)]),
+    "dg_destroy": (None, [ctypes.c_void_p]),
+    "dg_sizes": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "dg_proj_nodes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "dg_project_ic": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "dg_rhs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "dg_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double]),
+    "dg_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int32]),
+    "dg_stable_dt": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                    ctypes.POINTER(ctypes.c_double)]),
+    "dg_check_finite": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "dg_set_tile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
+    "dg_get_tile": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                   ctypes.POINTER(ctypes.c_int32)]),
+    "dg_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "dg_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load the library (after torch, so one HIP runtime serves both)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2309_12019_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in EXPORTS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int) -> None:
+    if rc != DG_OK:
+        raise DGError(rc, _lib.dg_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor], n: int, name: str):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float64 GPU tensor")
+    if t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def desc_from_fields(f: dict) -> MeshDesc:
+    lib = load()
+    d = MeshDesc()
+    lib.dg_default_desc(ctypes.byref(d))
+    d.dim, d.nx, d.ny = f["dim"], f["nx"], f.get("ny", 1)
+    d.x0, d.x1, d.y0, d.y1 = f["x0"], f["x1"], f["y0"], f["y1"]
+    d.periodic_x, d.periodic_y = int(f["periodic_x"]), int(f["periodic_y"])
+    d.p, d.flux = f["p"], f["flux"]
+    d.vel_x, d.vel_y = f["vx"], f["vy"]
+    d.omega, d.rot_cx, d.rot_cy = f["omega"], f["cx"], f["cy"]
+    d.bc_value = f["bc_value"]
+    d.mode = f["mode"]
+    d.q, d.b, d.w_nb = f["q"], f["b"], f["w_nb"]
+    d.weno_eps, d.weno_pow = f["eps"], f["r"]
+    d.lambda_override = f["lambda_override"]
+    return d
+
+
+class DG:
+    """One discretised problem on the current GPU (owns a dg_ctx)."""
+
+    def __init__(self, desc: MeshDesc, stream: Optional[torch.cuda.Stream] = None):
+        lib = load()
+        self.lib = lib
+        st = stream if stream is not None else torch.cuda.current_stream()
+        desc.stream = ctypes.c_void_p(st.cuda_stream)
+        self.desc = desc
+        h = ctypes.c_void_p()
+        _check(lib.dg_init_mesh(ctypes.byref(desc), ctypes.byref(h)))
+        self.h = h
+        nc, nl, nq = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib.dg_sizes(h, ctypes.byref(nc), ctypes.byref(nl), ctypes.byref(nq)))
+        self.ncells, self.nloc, self.nproj = nc.value, nl.value, nq.value
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    @classmethod
+    def from_workload(cls, w, stream=None) -> "DG":
+        return cls(desc_from_fields(w.fields()), stream)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def shape(self) -> Tuple[int, int]:
+        return (self.ncells, self.nloc)
+
+    def empty(self) -> torch.Tensor:
+        return torch.empty(self.shape, dtype=torch.float64, device=self.device)
+
+    def proj_nodes(self) -> np.ndarray:
+        dim = self.desc.dim
+        out = np.empty((self.ncells, self.nproj, dim), dtype=np.float64)
+        _check(self.lib.dg_proj_nodes(self.h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def project_ic(self, u_at_nodes: torch.Tensor, U: Optional[torch.Tensor] = None) -> torch.Tensor:
+        U = self.empty() if U is None else U
+        _check(self.lib.dg_project_ic(self.h, _ptr(u_at_nodes, self.ncells * self.nproj, "u_at_nodes"),
+                                      _ptr(U, self.ncells * self.nloc, "U")))
+        return U
+
+    def rhs(self, U: torch.Tensor, out: Optional[torch.Tensor] = None, with_gamma: bool = False):
+        out = self.empty() if out is None else out
+        gam = torch.empty(self.ncells, dtype=torch.float64, device=self.device) if with_gamma else None
+        n = self.ncells * self.nloc
+        _check(self.lib.dg_rhs(self.h, _ptr(U, n, "U"), _ptr(out, n, "dUdt"), _ptr(gam, self.ncells, "gamma")))
+        return (out, gam) if with_gamma else out
+
+    def step(self, U: torch.Tensor, dt: float) -> torch.Tensor:
+        _check(self.lib.dg_step(self.h, _ptr(U, self.ncells * self.nloc, "U"), float(dt)))
+        return U
+
+    def run(self, U: torch.Tensor, dt: float, nsteps: int) -> torch.Tensor:
+        _check(self.lib.dg_run(self.h, _ptr(U, self.ncells * self.nloc, "U"), float(dt), int(nsteps)))
+        return U
+
+    def stable_dt(self, U: torch.Tensor, cfl: float) -> float:
+        out = ctypes.c_double()
+        _check(self.lib.dg_stable_dt(self.h, _ptr(U, self.ncells * self.nloc, "U"), float(cfl),
+                                     ctypes.byref(out)))
+        return out.value
+
+    def count_nonfinite(self, U: torch.Tensor) -> int:
+        cnt = ctypes.c_int64()
+        rc = self.lib.dg_check_finite(self.h, _ptr(U, self.ncells * self.nloc, "U"), ctypes.byref(cnt))
+        if rc not in (DG_OK, DG_ENONFINITE):
+            _check(rc)
+        return cnt.value
+
+    def set_tile(self, tx: int, ty: int = 1) -> None:
+        _check(self.lib.dg_set_tile(self.h, int(tx), int(ty)))
+
+    def tile(self) -> Tuple[int, int]:
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        _check(self.lib.dg_get_tile(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def initial_state(self, w) -> torch.Tensor:
+        """Project the workload's initial data with the library's projection."""
+        pts = self.proj_nodes()
+        vals = torch.from_numpy(np.ascontiguousarray(w.eval_ic(pts))).to(self.device)
+        return self.project_ic(vals.reshape(-1).contiguous())

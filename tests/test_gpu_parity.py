@@ -1,0 +1,207 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Single-operator checks use meshes that span several workgroup tiles with a
+ragged edge; run checks follow the SSP-RK3 step for 100 steps.  Tolerances:
+one application of the operator <= 1e-12 relative L-inf (a few rounding
+errors per term), 100 steps <= 1e-11 relative L-inf.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from helpers import oracle_for, oracle_initial, oracle_problem
+from paper_2309_12019_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _dg():
+    from paper_2309_12019_amd import dgweno
+    return dgweno
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def relinf(a, b):
+    return float((a - b).abs().max() / b.abs().max().clamp_min(1e-300))
+
+
+def _mesh(kind, p, mode, n1=600, n2=(40, 36)):
+    if kind == "adv1d":
+        w = inputs.adv1d(n1, p, mode=mode)
+    elif kind == "burgers1d":
+        w = inputs.burgers1d(n1, p, mode=mode)
+    elif kind == "rot2d":
+        w = inputs.rot2d(n2[0], p, mode=mode, ny=n2[1])
+        w.cy = 0.45  # keeps v.n single-signed on every face (y = 0.45 is a grid line)
+    elif kind == "burgers2d":
+        w = inputs.burgers2d(n2[0], p, mode=mode, ny=n2[1], steps=1)
+    else:
+        raise ValueError(kind)
+    return w
+
+
+def _state(w, O, seed):
+    U = oracle_initial(w, O)
+    rng = np.random.default_rng(seed)
+    return U + 0.01 * torch.from_numpy(rng.standard_normal(U.shape)) * U.abs().max()
+
+
+KINDS = ["adv1d", "burgers1d", "rot2d", "burgers2d"]
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_rhs_parity(kind, p, mode):
+    _note(f"[rhs parity] {kind} p={p} mode={mode}")
+    w = _mesh(kind, p, mode)
+    O = oracle_for(w)
+    U = _state(w, O, 11)
+    Lo, go = O.rhs(U, with_gamma=True)
+    g = _dg().DG.from_workload(w)
+    Ud = U.cuda().contiguous()
+    Lg, gg = g.rhs(Ud, with_gamma=True)
+    torch.cuda.synchronize()
+    assert relinf(Lg.cpu(), Lo) <= 1e-12
+    assert float((gg.cpu() - go).abs().max()) <= 1e-12
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_projection_parity(kind, p):
+    _note(f"[projection parity] {kind} p={p}")
+    w = _mesh(kind, p, 2)
+    w.ic = (lambda x: np.exp(np.sin(2 * np.pi * x))) if w.dim == 1 else \
+        (lambda x, y: np.cos(3 * x - 2 * y) + x * y)
+    O = oracle_for(w)
+    Uo = oracle_initial(w, O)
+    g = _dg().DG.from_workload(w)
+    Ug = g.initial_state(w)
+    torch.cuda.synchronize()
+    assert relinf(Ug.cpu(), Uo) <= 1e-13
+
+
+def _run_parity(w, U0, steps, tol=1e-11, O=None):
+    O = O or oracle_for(w)
+    ref = O.run(U0, w.dt(), steps)
+    g = _dg().DG.from_workload(w)
+    U = U0.cuda().contiguous()
+    g.run(U, w.dt(), steps)
+    torch.cuda.synchronize()
+    err = relinf(U.cpu(), ref)
+    _note(f"    rel Linf after {steps} steps = {err:.3e}")
+    assert err <= tol
+    return U, ref
+
+
+def test_config_1d_advection_100_steps():
+    """1D u_t + u_x = 0, 64 cells, P2, sin(2 pi x) + square pulse, WENO, CFL 0.1."""
+    _note("[run parity] adv1d 64 cells P2 WENO 100 steps")
+    w = inputs.adv1d(64, 2, steps=100)
+    O = oracle_for(w)
+    _run_parity(w, oracle_initial(w, O), 100, O=O)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("kind", ["adv1d", "burgers1d"])
+def test_1d_100_steps_ragged(kind, p):
+    _note(f"[run parity] {kind} 300 cells P{p} WENO 100 steps")
+    w = inputs.adv1d(300, p) if kind == "adv1d" else inputs.burgers1d(300, p)
+    O = oracle_for(w)
+    _run_parity(w, oracle_initial(w, O), 100, O=O)
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_rotation_100_steps(p):
+    """Solid-body rotation (hump + slotted cylinder), 48 x 40 cells, P2/P3."""
+    _note(f"[run parity] rot2d 48x40 P{p} WENO 100 steps")
+    w = inputs.rot2d(48, p, seed=3, ny=40)
+    w.cy = 0.5  # 0.5 = 20 h is a grid line
+    O = oracle_for(w)
+    _run_parity(w, oracle_initial(w, O), 100, O=O)
+
+
+def test_burgers2d_100_steps_after_shock():
+    """2D Burgers with seeded Fourier data: the oracle first runs past the shock
+    time, then both sides advance 100 steps from that state."""
+    _note("[run parity] burgers2d 40x40 P2 WENO, 100 steps from a post-shock state")
+    w = inputs.burgers2d(40, 2, seed=0)
+    O = oracle_for(w)
+    U0 = O.run(oracle_initial(w, O), w.dt(), w.steps)
+    _run_parity(w, U0, 100, O=O)
+
+
+def test_run_equals_repeated_step_bitwise():
+    _note("[determinism] dg_run vs dg_step")
+    w = inputs.rot2d(40, 2, ny=36)
+    g = _dg().DG.from_workload(w)
+    U0 = g.initial_state(w)
+    A = U0.clone()
+    B = U0.clone()
+    g.run(A, w.dt(), 70)          # one 64-step graph + 6 eager steps
+    for _ in range(70):
+        g.step(B, w.dt())
+    torch.cuda.synchronize()
+    assert torch.equal(A, B)
+    C = U0.clone()
+    g.run(C, w.dt(), 70)
+    torch.cuda.synchronize()
+    assert torch.equal(A, C)
+
+
+@pytest.mark.parametrize("kind", ["rot2d", "burgers2d", "adv1d"])
+def test_tile_shape_independence(kind):
+    """Per-cell arithmetic does not depend on the workgroup tile."""
+    _note(f"[tiles] {kind}")
+    w = _mesh(kind, 2, 2, n1=1000, n2=(72, 40))
+    g = _dg().DG.from_workload(w)
+    U0 = g.initial_state(w)
+    outs = []
+    tiles = [(256, 1), (64, 1), (128, 1)] if w.dim == 1 else [(16, 16), (8, 8), (32, 8), (64, 4), (16, 4)]
+    for tx, ty in tiles:
+        g.set_tile(tx, ty)
+        U = U0.clone()
+        g.run(U, w.dt(), 5)
+        L = g.rhs(U)
+        outs.append((U, L))
+    torch.cuda.synchronize()
+    for U, L in outs[1:]:
+        assert torch.equal(U, outs[0][0]) and torch.equal(L, outs[0][1])
+
+
+def test_stable_dt_and_finite_check():
+    _note("[stable dt]")
+    w = inputs.burgers2d(48, 2, ny=40, steps=1)
+    O = oracle_for(w)
+    U0 = oracle_initial(w, O)
+    g = _dg().DG.from_workload(w)
+    U = U0.cuda().contiguous()
+    dt = g.stable_dt(U, 0.1)
+    lam = float(O.max_speed(U0).max())
+    assert abs(dt - 0.1 * w.h / (5 * lam)) <= 1e-13 * dt
+    assert g.count_nonfinite(U) == 0
+    U[3, 2] = float("nan")
+    U[7, 0] = float("inf")
+    assert g.count_nonfinite(U) == 2
+
+
+def test_invalid_arguments_through_the_binding():
+    dgweno = _dg()
+    w = inputs.adv1d(64, 2)
+    g = dgweno.DG.from_workload(w)
+    U = g.initial_state(w)
+    with pytest.raises(dgweno.DGError):
+        g.step(U, -1.0)
+    with pytest.raises(dgweno.DGError):
+        g.run(U, float("nan"), 3)
+    with pytest.raises(dgweno.DGError):
+        g.set_tile(100, 1)
+    with pytest.raises(ValueError):
+        g.rhs(U.float())
