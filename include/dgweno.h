@@ -134,9 +134,11 @@ int dg_stable_dt(dg_ctx* ctx, const double* U, double cfl, double* dt_host);
  * DG_ENONFINITE and the number of non-finite entries in *count (may be NULL). */
 int dg_check_finite(dg_ctx* ctx, const double* U, int64_t* count);
 
-/* Launch shape of the stage kernel: tx * ty cells per workgroup (2D), tx cells
- * (1D, ty ignored).  tx * ty must be a multiple of 64 and at most 1024.  Used
- * by the tuner; the default is chosen at dg_init_mesh. */
+/* Launch shape of the stage kernel: cells per workgroup, one of the compiled
+ * tiles: 1D tx in {256, 64} (ty ignored), 2D (tx, ty) in {(16,16), (8,8)}.
+ * The result does not depend on the tile (per-cell arithmetic is identical).
+ * Default at dg_init_mesh: 256 (1D), 16x16 (2D; 8x8 if 16x16 exceeds LDS).
+ * Errors: DG_EINVAL for another shape, DG_EUNSUPPORTED if it exceeds LDS. */
 int dg_set_tile(dg_ctx* ctx, int32_t tx, int32_t ty);
 int dg_get_tile(const dg_ctx* ctx, int32_t* tx, int32_t* ty);
 

@@ -93,12 +93,11 @@ StageArgs base_args(const dg_ctx* c) {
   A.lam_over = d.lambda_override;
   A.tx = c->tx;
   A.ty = d.dim == 2 ? c->ty : 1;
-  A.lds_stride = dgk::stage_stride(d.dim, A.tx, A.ty);
   return A;
 }
 
 size_t stage_lds_bytes(int dim, int nl, int tx, int ty) {
-  return sizeof(double) * (size_t)nl * (size_t)dgk::stage_stride(dim, tx, dim == 2 ? ty : 1);
+  return sizeof(double) * (size_t)dgk::tile_lds_doubles(dim, nl, tx, dim == 2 ? ty : 1);
 }
 
 // one stage: out = a*un + b*(uin + dt*L(uin)), or out = L(uin) when rhs_only
@@ -166,10 +165,16 @@ int validate(const dg_mesh_desc* d) {
 
 int check_tile(const dg_ctx* c, int tx, int ty) {
   const int dim = c->d.dim;
-  if (dim == 1) ty = 1;
-  if (tx < 1 || ty < 1) return fail(DG_EINVAL, "tile sizes must be >= 1");
-  const long long thr = (long long)tx * ty;
-  if (thr % 64 != 0 || thr > 256) return fail(DG_EINVAL, "tile must hold a multiple of 64 cells, at most 256");
+  bool ok = false;
+  if (dim == 1) {
+    for (int t : dgk::kTiles1D) ok |= tx == t;
+    ty = 1;
+  } else {
+    for (auto& t : dgk::kTiles2D) ok |= tx == t[0] && ty == t[1];
+  }
+  if (!ok)
+    return fail(DG_EINVAL, dim == 1 ? "1D tile must be 256 or 64 cells (got %d)"
+                                     : "2D tile must be 16x16 or 8x8 (got %dx%d)", tx, ty);
   if (stage_lds_bytes(dim, c->nl, tx, ty) > (size_t)c->max_lds)
     return fail(DG_EUNSUPPORTED, "tile %dx%d needs %zu bytes of LDS (limit %d)", tx, ty,
                 stage_lds_bytes(dim, c->nl, tx, ty), c->max_lds);
@@ -243,8 +248,7 @@ int dg_init_mesh(const dg_mesh_desc* desc, dg_ctx** out) {
   } else {
     c->tx = 16;
     c->ty = 16;
-    if (stage_lds_bytes(2, c->nl, 16, 16) > (size_t)c->max_lds) c->ty = 8;
-    if (stage_lds_bytes(2, c->nl, c->tx, c->ty) > (size_t)c->max_lds) c->ty = 4;
+    if (stage_lds_bytes(2, c->nl, 16, 16) > (size_t)c->max_lds) c->tx = c->ty = 8;
   }
   const size_t bytes = sizeof(double) * (size_t)c->ncells * c->nl;
   if ((e = hipMalloc(&c->U1, bytes)) != hipSuccess || (e = hipMalloc(&c->U2, bytes)) != hipSuccess) {

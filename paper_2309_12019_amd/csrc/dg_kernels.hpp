@@ -41,28 +41,71 @@ struct StageArgs {
   double anorm;                  // ||(vx, vy)||_2 (BURGERS wave speed factor)
   double bc;                     // exterior state at non-periodic faces
   double q, bthr, wnb, eps, wpow, lam_over;
-  int tx, ty;                    // tile (ty = 1 in 1D)
-  int lds_stride;                // doubles between coefficient planes in LDS
+  int tx, ty;                    // tile (one of the compiled shapes; ty = 1 in 1D)
 };
 
-// number of LDS doubles a tile needs
-__host__ __device__ inline int stage_slots(int dim, int tx, int ty) {
-  return dim == 1 ? tx + 2 : (tx + 2) * (ty + 2);
-}
-__host__ __device__ inline int stage_stride(int dim, int tx, int ty) {
-  int s = stage_slots(dim, tx, ty);
-  return s | 1;  // odd: consecutive coefficient planes start in different banks
+// Tile geometry: TX x TY cells per workgroup (TY = 1 in 1D) plus a one-cell
+// face halo.  LDS holds the tile coefficient-major: plane j (one per basis
+// function) stores coefficient j of every slot; the plane stride is odd so
+// lanes reading consecutive slots of one plane hit consecutive banks.
+template <int DIM, int TX, int TY>
+struct TileGeom {
+  static constexpr int W = TX + 2;                  // slots per row
+  static constexpr int H = DIM == 2 ? TY + 2 : 1;   // slot rows
+  static constexpr int NS = W * H;
+  static constexpr int S = NS | 1;                  // plane stride (doubles)
+  static constexpr int NT = DIM == 2 ? TX * TY : TX;
+};
+
+// supported tiles (all multiples of 64 cells)
+constexpr int kTiles1D[2] = {256, 64};
+constexpr int kTiles2D[2][2] = {{16, 16}, {8, 8}};
+
+__host__ __device__ inline int tile_lds_doubles(int dim, int nl, int tx, int ty) {
+  const int ns = dim == 1 ? tx + 2 : (tx + 2) * (ty + 2);
+  return nl * (ns | 1);
 }
 
-// Per-cell arithmetic.  `lds` holds the tile, coefficient-major; `sc` is the
-// slot of this cell, `W` the slot-row width.
-template <int DIM, int P, int FLUX, int MODE>
+// x mod n for x in [-1, n + tile]: cheap for the common single wrap
+__device__ inline int wrap_index(int x, int n) {
+  if (x < 0) return x + n;
+  while (x >= n) x -= n;
+  return x;
+}
+
+// 1/x to near full precision: hardware estimate and two Newton steps
+__device__ inline double rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// general powers (cold paths: exponents other than the defaults)
+__device__ __noinline__ double pow_cold(double x, double y) { return pow(x, y); }
+
+// sqrt(x) for x > 0: hardware estimate and one Newton correction
+__device__ inline double sqrt_pos(double x) {
+  const double s = __builtin_amdgcn_sqrt(x);
+  const double e = fma(-s, s, x);
+  return fma(0.5 * rcp(s), e, s);
+}
+
+// Per-cell arithmetic.  `b` points at this cell's slot in LDS plane 0;
+// coefficient j of the cell sits at b[j*S], of its face neighbour f at
+// b[j*S + off(f)] with off = -1, +1, -W, +W (faces -x, +x, -y, +y).
+// Non-periodic boundary slots hold the constant exterior state, so the
+// face traces need no special case.
+template <int DIM, int P, int FLUX, int MODE, int S, int W>
 struct Cell {
   using TB = Tables<DIM, P, FLUX>;
   static constexpr int N = P + 1;
   static constexpr int NL = TB::NL;
   static constexpr int Q = TB::Q;
   static constexpr int NF = 2 * DIM;
+
+  __device__ static constexpr int off(int f) { return f == 0 ? -1 : f == 1 ? 1 : f == 2 ? -W : W; }
 
   // c^T B c with the sensor's quadratic form (zero entries skipped at compile time)
   __device__ static inline double qform(const double (&v)[NL]) {
@@ -74,7 +117,8 @@ struct Cell {
 #pragma unroll
       for (int j = i; j < NL; ++j) {
         if (TB::sn.B[i][j] != 0.0) {
-          ri = fma((j == i ? 1.0 : 2.0) * TB::sn.B[i][j], v[j], ri);
+          ri = any ? fma((j == i ? 1.0 : 2.0) * TB::sn.B[i][j], v[j], ri)
+                   : ((j == i ? 1.0 : 2.0) * TB::sn.B[i][j]) * v[j];
           any = true;
         }
       }
@@ -83,11 +127,12 @@ struct Cell {
     return acc;
   }
 
-  // neighbour on face f (0: -x, 1: +x, 2: -y, 3: +y), continued into this cell
-  // and expanded in this cell's basis: P_a(xi -/+ 2) = sum_b T[s][a][b] P_b(xi)
+  // neighbour f continued into this cell, in this cell's basis (non-constant
+  // coefficients only): P_a(xi -/+ 2) = sum_b T[s][a][b] P_b(xi)
   template <int F>
-  __device__ static inline void candidate(const double (&cn)[NL], double (&cd)[NL]) {
+  __device__ static inline void candidate(const double* b, double (&cd)[NL]) {
     constexpr int si = F & 1;
+    constexpr int o = off(F);
 #pragma unroll
     for (int j = 0; j < NL; ++j) cd[j] = 0.0;
     if constexpr (DIM == 1 || F < 2) {
@@ -95,138 +140,114 @@ struct Cell {
 #pragma unroll
       for (int e = 0; e < R; ++e)
 #pragma unroll
-        for (int a = 0; a < N; ++a)
+        for (int a = 0; a < N; ++a) {
+          const double cn = b[(a + N * e) * S + o];
 #pragma unroll
-          for (int b = 0; b <= a; ++b)
-            if (TB::dg.T[si][a][b] != 0.0)
-              cd[b + N * e] = fma(TB::dg.T[si][a][b], cn[a + N * e], cd[b + N * e]);
+          for (int c = 0; c <= a; ++c)
+            if (TB::dg.T[si][a][c] != 0.0 && (c + N * e) != 0)
+              cd[c + N * e] = fma(TB::dg.T[si][a][c], cn, cd[c + N * e]);
+        }
     } else {
 #pragma unroll
       for (int e = 0; e < N; ++e)
 #pragma unroll
-        for (int a = 0; a < N; ++a)
+        for (int a = 0; a < N; ++a) {
+          const double cn = b[(a + N * e) * S + o];
 #pragma unroll
-          for (int b = 0; b <= e; ++b)
-            if (TB::dg.T[si][e][b] != 0.0)
-              cd[a + N * b] = fma(TB::dg.T[si][e][b], cn[a + N * e], cd[a + N * b]);
+          for (int c = 0; c <= e; ++c)
+            if (TB::dg.T[si][e][c] != 0.0 && (a + N * c) != 0)
+              cd[a + N * c] = fma(TB::dg.T[si][e][c], cn, cd[a + N * c]);
+        }
     }
   }
 
-  __device__ static inline void load(const double* lds, int S, int slot, double (&v)[NL]) {
-#pragma unroll
-    for (int j = 0; j < NL; ++j) v[j] = lds[j * S + slot];
+  template <int F>
+  __device__ static inline void cand_any(int f, const double* b, double (&cd)[NL]) {
+    if constexpr (F < NF) {
+      if (f == F)
+        candidate<F>(b, cd);
+      else
+        cand_any<F + 1>(f, b, cd);
+    }
   }
 
-  __device__ static inline double weight_fn(const StageArgs& A, double beta) {
+  __device__ static inline double weight(const StageArgs& A, double beta) {
     const double t = A.eps + beta;
     if (A.wpow == 2.0) {
-      const double r = 1.0 / t;
+      const double r = rcp(t);
       return r * r;
     }
-    return pow(t, -A.wpow);
+    return pow_cold(t, -A.wpow);
   }
 
   // gamma_e of eqs. (sensor)/(gensensor) with the HWENO reconstruction
-  __device__ static inline double sensor(const StageArgs& A, const double* lds, int S,
-                                         const int (&nbs)[NF], const bool (&has)[NF],
+  __device__ static inline double sensor(const StageArgs& A, const double* b, const bool (&has)[NF],
                                          const double (&c)[NL]) {
-    double beta[NF + 1];
-    beta[0] = qform(c);
+    double beta0 = qform(c);
+    double al[NF];
+    double cd[NL];
     int m = 0;
-    double cn[NL], cd[NL];
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-      beta[f + 1] = 0.0;
-      if (has[f]) {
-        ++m;
-        load(lds, S, nbs[f], cn);
-        if (f == 0) candidate<0>(cn, cd);
-        if (f == 1) candidate<1>(cn, cd);
-        if constexpr (DIM == 2) {
-          if (f == 2) candidate<2>(cn, cd);
-          if (f == 3) candidate<3>(cn, cd);
-        }
-        beta[f + 1] = qform(cd);
-      }
+      cand_any<0>(f, b, cd);
+      const double bl = qform(cd);
+      al[f] = has[f] ? A.wnb * weight(A, bl) : 0.0;
+      m += has[f];
     }
-    double al[NF + 1];
-    al[0] = (1.0 - m * A.wnb) * weight_fn(A, beta[0]);
-    double asum = al[0];
+    const double a0 = (1.0 - m * A.wnb) * weight(A, beta0);
+    double asum = a0;
 #pragma unroll
-    for (int f = 0; f < NF; ++f) {
-      al[f + 1] = has[f] ? A.wnb * weight_fn(A, beta[f + 1]) : 0.0;
-      asum += al[f + 1];
-    }
-    const double inv = 1.0 / asum;
-    // U* = sum_l omega_l U_l ; only the non-constant coefficients matter
+    for (int f = 0; f < NF; ++f) asum += al[f];
+    const double inv = rcp(asum);
+    // c - c* = c - sum_l omega_l c^(l), non-constant coefficients
     double cs[NL];
-    const double w0 = al[0] * inv;
+    const double w0 = a0 * inv;
 #pragma unroll
     for (int j = 0; j < NL; ++j) cs[j] = w0 * c[j];
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-      if (has[f]) {
-        const double wl = al[f + 1] * inv;
-        load(lds, S, nbs[f], cn);
-        if (f == 0) candidate<0>(cn, cd);
-        if (f == 1) candidate<1>(cn, cd);
-        if constexpr (DIM == 2) {
-          if (f == 2) candidate<2>(cn, cd);
-          if (f == 3) candidate<3>(cn, cd);
-        }
+      cand_any<0>(f, b, cd);
+      const double wl = al[f] * inv;
 #pragma unroll
-        for (int j = 1; j < NL; ++j) cs[j] = fma(wl, cd[j], cs[j]);
-      }
+      for (int j = 1; j < NL; ++j) cs[j] = fma(wl, cd[j], cs[j]);
     }
 #pragma unroll
     for (int j = 0; j < NL; ++j) cs[j] = c[j] - cs[j];
     const double num2 = qform(cs);
-    const double den2 = beta[0];
     double ratio;
     if (num2 == 0.0)
       ratio = 0.0;
-    else if (den2 == 0.0)
+    else if (beta0 == 0.0)
       ratio = __builtin_inf();
     else
-      ratio = sqrt(num2) / sqrt(den2);
+      ratio = sqrt_pos(num2 * rcp(beta0));
     if (!(ratio >= A.bthr)) return 0.0;
     const double r1 = fmin(1.0, ratio);
-    return A.q == 1.0 ? r1 : pow(r1, A.q);
+    return A.q == 1.0 ? r1 : pow_cold(r1, A.q);
   }
 
-  // numerical flux H(um, up, n) for n = s e_axis at a face point (Sec. 2, LLF)
-  __device__ static inline double llf(const StageArgs& A, int axis, double s, double um,
-                                      double up, double x, double y) {
+  // numerical flux H(um, up, n), n = s e_axis, v = normal velocity component
+  __device__ static inline double llf(const StageArgs& A, double s, double vax, double um, double up) {
     if constexpr (FLUX == FLUX_LINADV) {
-      double v;
-      if constexpr (DIM == 1) {
-        v = A.vx;
-      } else {
-        v = axis == 0 ? A.vx - A.omega * (y - A.cy) : A.vy + A.omega * (x - A.cx);
-      }
-      const double vn = s * v;
+      const double vn = s * vax;
       return 0.5 * vn * (um + up) - 0.5 * fabs(vn) * (up - um);
     } else {
-      const double an = s * (axis == 0 ? A.vx : A.vy);
+      const double an = s * vax;
       const double sp = fabs(an) * fmax(fabs(um), fabs(up));
       return 0.25 * an * (um * um + up * up) - 0.5 * sp * (up - um);
     }
   }
 
-  // dU/dt of one cell (and gamma_e, lambda_e)
-  __device__ static inline void rhs(const StageArgs& A, const double* lds, int S, int sc, int W,
-                                    int ix, int iy, double (&L)[NL], double& gam_out) {
+  // dU/dt of one cell and gamma_e
+  __device__ static inline void rhs(const StageArgs& A, const double* b, int ix, int iy, double (&L)[NL],
+                                    double& gam_out) {
     double c[NL];
-    load(lds, S, sc, c);
-    int nbs[NF];
+#pragma unroll
+    for (int j = 0; j < NL; ++j) c[j] = b[j * S];
     bool has[NF];
-    nbs[0] = sc - 1;
-    nbs[1] = sc + 1;
     has[0] = A.per_x || ix > 0;
     has[1] = A.per_x || ix < A.nx - 1;
     if constexpr (DIM == 2) {
-      nbs[2] = sc - W;
-      nbs[3] = sc + W;
       has[2] = A.per_y || iy > 0;
       has[3] = A.per_y || iy < A.ny - 1;
     }
@@ -236,7 +257,7 @@ struct Cell {
     else if constexpr (MODE == MODE_LO)
       gam = 1.0;
     else
-      gam = sensor(A, lds, S, nbs, has, c);
+      gam = sensor(A, b, has, c);
     gam_out = gam;
 
     const double hh = 0.5 * A.h;
@@ -245,105 +266,127 @@ struct Cell {
     double R[NL];
 #pragma unroll
     for (int j = 0; j < NL; ++j) R[j] = 0.0;
-    double smax = 0.0;  // max |u| (BURGERS) or max |v|^2 (LINADV) over volume nodes
+    double lam;
 
-    // ---- volume integral  int grad(phi) . F(u_h)
     if constexpr (DIM == 1) {
+      // ---- volume
+      double umax = 0.0;
 #pragma unroll
       for (int qn = 0; qn < Q; ++qn) {
-        double u = 0.0;
+        double u = c[0];
 #pragma unroll
-        for (int a = 0; a < N; ++a) u = fma(c[a], TB::nd.L[a][qn], u);
+        for (int a = 1; a < N; ++a) u = fma(c[a], TB::nd.L[a][qn], u);
         double F;
         if constexpr (FLUX == FLUX_LINADV) {
           F = A.vx * u;
         } else {
-          F = A.vx * 0.5 * u * u;
-          smax = fmax(smax, fabs(u));
+          F = A.vx * (0.5 * u * u);
+          umax = fmax(umax, fabs(u));
         }
         const double wF = TB::nd.w[qn] * F;
 #pragma unroll
         for (int a = 1; a < N; ++a) R[a] = fma(TB::nd.D[a][qn], wF, R[a]);
       }
-    } else {
-#pragma unroll
-      for (int qx = 0; qx < Q; ++qx) {
-        double s1[N];  // s1[b] = sum_a c[a + N b] P_a(x_qx)
-#pragma unroll
-        for (int b = 0; b < N; ++b) {
-          double t = 0.0;
-#pragma unroll
-          for (int a = 0; a < N; ++a) t = fma(c[a + N * b], TB::nd.L[a][qx], t);
-          s1[b] = t;
-        }
-        double gx[N], gy[N];
-#pragma unroll
-        for (int b = 0; b < N; ++b) gx[b] = gy[b] = 0.0;
-        const double xq = xc + hh * TB::nd.x[qx];
-#pragma unroll
-        for (int qy = 0; qy < Q; ++qy) {
-          double u = 0.0;
-#pragma unroll
-          for (int b = 0; b < N; ++b) u = fma(s1[b], TB::nd.L[b][qy], u);
-          double Fx, Fy;
-          if constexpr (FLUX == FLUX_LINADV) {
-            const double yq = yc + hh * TB::nd.x[qy];
-            const double vxq = A.vx - A.omega * (yq - A.cy);
-            const double vyq = A.vy + A.omega * (xq - A.cx);
-            Fx = vxq * u;
-            Fy = vyq * u;
-            smax = fmax(smax, vxq * vxq + vyq * vyq);
-          } else {
-            const double hu2 = 0.5 * u * u;
-            Fx = A.vx * hu2;
-            Fy = A.vy * hu2;
-            smax = fmax(smax, fabs(u));
-          }
-          const double wFx = TB::nd.w[qy] * Fx, wFy = TB::nd.w[qy] * Fy;
-#pragma unroll
-          for (int b = 0; b < N; ++b) {
-            gx[b] = fma(TB::nd.L[b][qy], wFx, gx[b]);
-            if (b > 0) gy[b] = fma(TB::nd.D[b][qy], wFy, gy[b]);
-          }
-        }
-        const double wq = TB::nd.w[qx];
-#pragma unroll
-        for (int b = 0; b < N; ++b)
-#pragma unroll
-          for (int a = 0; a < N; ++a) {
-            double t = R[a + N * b];
-            if (a > 0) t = fma(wq * TB::nd.D[a][qx], gx[b], t);
-            if (b > 0) t = fma(wq * TB::nd.L[a][qx], gy[b], t);
-            R[a + N * b] = t;
-          }
-      }
-    }
-
-    // ---- face integrals  - int_dK phi H(u^-, u^+, n)
-    if constexpr (DIM == 1) {
+      lam = FLUX == FLUX_LINADV ? fabs(A.vx) : A.anorm * umax;
+      // ---- faces
 #pragma unroll
       for (int f = 0; f < 2; ++f) {
-        const double s = f ? 1.0 : -1.0;
-        double um = 0.0;
+        double um = 0.0, up = 0.0;
 #pragma unroll
-        for (int a = 0; a < N; ++a) um = fma(f ? 1.0 : TB::dg.sgn[a], c[a], um);
-        double up = A.bc;
-        if (has[f]) {
-          up = 0.0;
-#pragma unroll
-          for (int a = 0; a < N; ++a) up = fma(f ? TB::dg.sgn[a] : 1.0, lds[a * S + nbs[f]], up);
+        for (int a = 0; a < N; ++a) {
+          const double so = f ? 1.0 : TB::dg.sgn[a];  // P_a(s)
+          const double sn = f ? TB::dg.sgn[a] : 1.0;  // P_a(-s)
+          um = fma(so, c[a], um);
+          up = fma(sn, b[a * S + off(f)], up);
         }
-        const double H = llf(A, 0, s, um, up, xc + s * hh, 0.0);
+        const double H = llf(A, f ? 1.0 : -1.0, A.vx, um, up);
 #pragma unroll
         for (int a = 0; a < N; ++a) R[a] = fma(f ? -1.0 : -TB::dg.sgn[a], H, R[a]);
       }
     } else {
+      // normal velocity components along the node lines (linear flux):
+      // v_x depends on y only, v_y on x only
+      double vxl[Q], vyl[Q];
+      if constexpr (FLUX == FLUX_LINADV) {
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          vxl[k] = A.vx - A.omega * (fma(hh, TB::nd.x[k], yc) - A.cy);
+          vyl[k] = A.vy + A.omega * (fma(hh, TB::nd.x[k], xc) - A.cx);
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          vxl[k] = A.vx;
+          vyl[k] = A.vy;
+        }
+      }
+      // ---- volume  int grad(phi) . F(u_h), sum factorised over x nodes
+      double umax = 0.0;
+#pragma unroll
+      for (int qx = 0; qx < Q; ++qx) {
+        double s1[N];
+#pragma unroll
+        for (int bb = 0; bb < N; ++bb) {
+          double t = c[N * bb];
+#pragma unroll
+          for (int a = 1; a < N; ++a) t = fma(c[a + N * bb], TB::nd.L[a][qx], t);
+          s1[bb] = t;
+        }
+        double gx[N], gy[N];
+#pragma unroll
+        for (int qy = 0; qy < Q; ++qy) {
+          double u = s1[0];
+#pragma unroll
+          for (int bb = 1; bb < N; ++bb) u = fma(s1[bb], TB::nd.L[bb][qy], u);
+          double Fx, Fy;
+          if constexpr (FLUX == FLUX_LINADV) {
+            Fx = vxl[qy] * u;
+            Fy = vyl[qx] * u;
+          } else {
+            const double hu2 = 0.5 * u * u;
+            Fx = A.vx * hu2;
+            Fy = A.vy * hu2;
+            umax = fmax(umax, fabs(u));
+          }
+#pragma unroll
+          for (int bb = 0; bb < N; ++bb) {
+            const double cxw = TB::nd.w[qy] * TB::nd.L[bb][qy];
+            gx[bb] = qy == 0 ? cxw * Fx : fma(cxw, Fx, gx[bb]);
+            if (bb > 0) {
+              const double cyw = TB::nd.w[qy] * TB::nd.D[bb][qy];
+              gy[bb] = qy == 0 ? cyw * Fy : fma(cyw, Fy, gy[bb]);
+            }
+          }
+        }
+        const double wq = TB::nd.w[qx];
+#pragma unroll
+        for (int bb = 0; bb < N; ++bb)
+#pragma unroll
+          for (int a = 0; a < N; ++a) {
+            double t = R[a + N * bb];
+            if (a > 0) t = fma(wq * TB::nd.D[a][qx], gx[bb], t);
+            if (bb > 0) t = fma(wq * TB::nd.L[a][qx], gy[bb], t);
+            R[a + N * bb] = t;
+          }
+      }
+      if constexpr (FLUX == FLUX_LINADV) {
+        // |v|^2 = v_x(y)^2 + v_y(x)^2 separates over the node grid
+        double mx = 0.0, my = 0.0;
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          mx = fmax(mx, vxl[k] * vxl[k]);
+          my = fmax(my, vyl[k] * vyl[k]);
+        }
+        lam = sqrt_pos(mx + my);
+      } else {
+        lam = A.anorm * umax;
+      }
+      // ---- faces  - int_dK phi H(u^-, u^+, n)
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
         const int axis = f >> 1;
         const bool plus = f & 1;
         const double s = plus ? 1.0 : -1.0;
-        // trace coefficients along the face (index runs over the other axis)
         double tm[N], tp[N];
 #pragma unroll
         for (int k = 0; k < N; ++k) {
@@ -351,32 +394,30 @@ struct Cell {
 #pragma unroll
           for (int i = 0; i < N; ++i) {
             const int j = axis == 0 ? i + N * k : k + N * i;
-            const double so = plus ? 1.0 : TB::dg.sgn[i];  // P_i(s)
-            const double sn = plus ? TB::dg.sgn[i] : 1.0;  // P_i(-s)
+            const double so = plus ? 1.0 : TB::dg.sgn[i];
+            const double sn = plus ? TB::dg.sgn[i] : 1.0;
             t = fma(so, c[j], t);
-            if (has[f]) tn = fma(sn, lds[j * S + nbs[f]], tn);
+            tn = fma(sn, b[j * S + off(f)], tn);
           }
           tm[k] = t;
           tp[k] = tn;
         }
         double g[N];
 #pragma unroll
-        for (int k = 0; k < N; ++k) g[k] = 0.0;
-#pragma unroll
         for (int r = 0; r < Q; ++r) {
-          double um = 0.0, up = 0.0;
+          double um = tm[0], up = tp[0];
 #pragma unroll
-          for (int k = 0; k < N; ++k) {
+          for (int k = 1; k < N; ++k) {
             um = fma(tm[k], TB::nd.L[k][r], um);
             up = fma(tp[k], TB::nd.L[k][r], up);
           }
-          if (!has[f]) up = A.bc;
-          const double t = hh * TB::nd.x[r];
-          const double xf = axis == 0 ? xc + s * hh : xc + t;
-          const double yf = axis == 0 ? yc + t : yc + s * hh;
-          const double wH = TB::nd.w[r] * llf(A, axis, s, um, up, xf, yf);
+          const double vax = axis == 0 ? vxl[r] : vyl[r];
+          const double H = llf(A, s, vax, um, up);
 #pragma unroll
-          for (int k = 0; k < N; ++k) g[k] = fma(TB::nd.L[k][r], wH, g[k]);
+          for (int k = 0; k < N; ++k) {
+            const double cw = TB::nd.w[r] * TB::nd.L[k][r];
+            g[k] = r == 0 ? cw * H : fma(cw, H, g[k]);
+          }
         }
 #pragma unroll
         for (int k = 0; k < N; ++k)
@@ -389,16 +430,9 @@ struct Cell {
       }
     }
 
-    // ---- lambda_e, dissipation gamma nu int grad(phi) . grad(u_h), M^-1
-    double lam;
-    if (A.lam_over > 0.0) {
-      lam = A.lam_over;
-    } else if constexpr (FLUX == FLUX_LINADV) {
-      lam = DIM == 1 ? fabs(A.vx) : sqrt(smax);
-    } else {
-      lam = A.anorm * smax;
-    }
-    // L = (2/h) Mhat^{-1} [ vol - face - (gamma lambda / p) Khat c ]
+    // ---- dissipation gamma nu int grad(phi).grad(u_h) and M^-1:
+    // L = (2/h) Mhat^-1 [ vol - face - (gamma lambda / p) Khat c ]
+    if (A.lam_over > 0.0) lam = A.lam_over;
     const double kd = gam * lam * (1.0 / P);
     const double g2h = 2.0 / A.h;
     if constexpr (DIM == 1) {
@@ -412,99 +446,128 @@ struct Cell {
       }
     } else {
 #pragma unroll
-      for (int b = 0; b < N; ++b)
+      for (int bb = 0; bb < N; ++bb)
 #pragma unroll
         for (int a = 0; a < N; ++a) {
           double kc = 0.0;
 #pragma unroll
           for (int a2 = 0; a2 < N; ++a2)
-            if (TB::dg.S[a][a2] != 0.0) kc = fma(TB::dg.S[a][a2] * TB::dg.mhat[b], c[a2 + N * b], kc);
+            if (TB::dg.S[a][a2] != 0.0) kc = fma(TB::dg.S[a][a2] * TB::dg.mhat[bb], c[a2 + N * bb], kc);
 #pragma unroll
           for (int b2 = 0; b2 < N; ++b2)
-            if (TB::dg.S[b][b2] != 0.0) kc = fma(TB::dg.S[b][b2] * TB::dg.mhat[a], c[a + N * b2], kc);
-          L[a + N * b] = (g2h * TB::dg.minv[a] * TB::dg.minv[b]) * fma(-kd, kc, R[a + N * b]);
+            if (TB::dg.S[bb][b2] != 0.0) kc = fma(TB::dg.S[bb][b2] * TB::dg.mhat[a], c[a + N * b2], kc);
+          L[a + N * bb] = (g2h * TB::dg.minv[a] * TB::dg.minv[bb]) * fma(-kd, kc, R[a + N * bb]);
         }
     }
   }
 };
 
-// The fused stage kernel.  Grid: (ceil(nx/tx), ceil(ny/ty)); block: tx*ty
-// threads; dynamic LDS: NL * lds_stride doubles.
-template <int DIM, int P, int FLUX, int MODE>
-__global__ void __launch_bounds__(256) stage_kernel(const StageArgs A) {
-  using C = Cell<DIM, P, FLUX, MODE>;
-  constexpr int NL = C::NL;
-  extern __shared__ double lds[];
-  const int tx = A.tx;
-  const int ty = DIM == 2 ? A.ty : 1;
-  const int W = tx + 2;
-  const int nslots = DIM == 2 ? W * (ty + 2) : W;
-  const int S = A.lds_stride;
-  const int ix0 = blockIdx.x * tx;
-  const int iy0 = DIM == 2 ? blockIdx.y * ty : 0;
+// Global cell index of slot (gx, gy) relative to the mesh, with periodic wrap;
+// false if the slot lies outside a non-periodic boundary.
+template <int DIM>
+__device__ inline bool slot_cell(const StageArgs& A, int gx, int gy, size_t& cell) {
   const int nx = A.nx, ny = DIM == 2 ? A.ny : 1;
-
-  for (int idx = threadIdx.x; idx < nslots * NL; idx += blockDim.x) {
-    const int s = idx / NL;
-    const int j = idx - s * NL;
-    const int sy = DIM == 2 ? s / W : 0;
-    const int sx = s - sy * W;
-    int gx = ix0 - 1 + sx;
-    int gy = DIM == 2 ? iy0 - 1 + sy : 0;
-    bool ok = true;
-    if (gx < 0 || gx >= nx) {
-      if (A.per_x)
-        gx = ((gx % nx) + nx) % nx;
-      else
-        ok = false;
-    }
-    if (DIM == 2 && (gy < 0 || gy >= ny)) {
-      if (A.per_y)
-        gy = ((gy % ny) + ny) % ny;
-      else
-        ok = false;
-    }
-    lds[j * S + s] = ok ? A.uin[((size_t)gy * nx + gx) * NL + j] : 0.0;
+  if ((unsigned)gx >= (unsigned)nx) {
+    if (!A.per_x) return false;
+    gx = wrap_index(gx, nx);
   }
-  __syncthreads();
+  if (DIM == 2 && (unsigned)gy >= (unsigned)ny) {
+    if (!A.per_y) return false;
+    gy = wrap_index(gy, ny);
+  }
+  cell = (size_t)gy * nx + gx;
+  return true;
+}
+
+// Load one slot (a cell's NL coefficients, or the constant exterior state
+// outside a non-periodic boundary) into the coefficient-major LDS tile.
+template <int DIM, int NL, int S>
+__device__ inline void load_slot(const StageArgs& A, double* lds, int slot, int gx, int gy) {
+  size_t cell;
+  double v[NL];
+  if (slot_cell<DIM>(A, gx, gy, cell)) {
+    const double* src = A.uin + cell * NL;
+#pragma unroll
+    for (int j = 0; j < NL; ++j) v[j] = src[j];
+  } else {
+#pragma unroll
+    for (int j = 0; j < NL; ++j) v[j] = j == 0 ? A.bc : 0.0;
+  }
+#pragma unroll
+  for (int j = 0; j < NL; ++j) lds[j * S + slot] = v[j];
+}
+
+// The fused stage kernel.  Grid: (ceil(nx/TX), ceil(ny/TY)); block: TX*TY
+// threads, one per cell; dynamic LDS: NL * S doubles (the tile with its face
+// halo, coefficient-major).  Each thread loads its own cell's coefficients
+// (one base address, compile-time offsets; a wave covers a contiguous span),
+// the first threads also load the halo ring, and each thread writes its own
+// results, so the kernel has a single barrier.
+template <int DIM, int P, int FLUX, int MODE, int TX, int TY>
+__global__ void __launch_bounds__(DIM == 2 ? TX * TY : TX) stage_kernel(const StageArgs A) {
+  using G = TileGeom<DIM, TX, TY>;
+  using C = Cell<DIM, P, FLUX, MODE, G::S, G::W>;
+  constexpr int NL = C::NL;
+  constexpr int S = G::S, W = G::W;
+  extern __shared__ double lds[];
+  const int ix0 = blockIdx.x * TX;
+  const int iy0 = DIM == 2 ? blockIdx.y * TY : 0;
+  const int nx = A.nx, ny = DIM == 2 ? A.ny : 1;
+  const bool comb = !A.rhs_only && A.a != 0.0;
 
   const int t = threadIdx.x;
-  const int lx = t % tx, ly = t / tx;
+  const int lx = DIM == 2 ? t % TX : t, ly = DIM == 2 ? t / TX : 0;
   const int ix = ix0 + lx, iy = iy0 + ly;
-  const bool active = ly < ty && ix < nx && iy < ny;
+  const bool active = ix < nx && iy < ny;
   const int sc = DIM == 2 ? (ly + 1) * W + lx + 1 : lx + 1;
-  double res[NL];
-  if (active) {
-    double L[NL], gam;
-    C::rhs(A, lds, S, sc, W, ix, iy, L, gam);
-    if (A.gamma) A.gamma[(size_t)iy * nx + ix] = gam;
-    if (A.rhs_only) {
+  const size_t cell = (size_t)iy * nx + ix;
+
+  // U^n of this cell (RK combination), issued together with the tile loads
+  double un[NL];
+  if (comb && active) {
 #pragma unroll
-      for (int j = 0; j < NL; ++j) res[j] = L[j];
-    } else {
-#pragma unroll
-      for (int j = 0; j < NL; ++j) res[j] = A.b * fma(A.dt, L[j], lds[j * S + sc]);
+    for (int j = 0; j < NL; ++j) un[j] = A.un[cell * NL + j];
+  }
+  // interior slots (cells past a ragged edge hold the wrapped or exterior state)
+  load_slot<DIM, NL, S>(A, lds, sc, ix, iy);
+  // halo ring: no corners (the stencil has face neighbours only)
+  if constexpr (DIM == 1) {
+    if (t < 2) load_slot<DIM, NL, S>(A, lds, t == 0 ? 0 : TX + 1, t == 0 ? ix0 - 1 : ix0 + TX, 0);
+  } else {
+    if (t < 2 * TX + 2 * TY) {
+      int sx, sy;
+      if (t < TX) {
+        sx = t + 1;
+        sy = 0;
+      } else if (t < 2 * TX) {
+        sx = t - TX + 1;
+        sy = TY + 1;
+      } else if (t < 2 * TX + TY) {
+        sx = 0;
+        sy = t - 2 * TX + 1;
+      } else {
+        sx = TX + 1;
+        sy = t - 2 * TX - TY + 1;
+      }
+      load_slot<DIM, NL, S>(A, lds, sy * W + sx, ix0 - 1 + sx, iy0 - 1 + sy);
     }
   }
   __syncthreads();
-  if (active) {
+  if (!active) return;
+
+  double L[NL], gam;
+  C::rhs(A, lds + sc, ix, iy, L, gam);
+  if (A.gamma) A.gamma[cell] = gam;
+  double* dst = A.out + cell * NL;
+  if (A.rhs_only) {
 #pragma unroll
-    for (int j = 0; j < NL; ++j) lds[j * S + sc] = res[j];
-  }
-  __syncthreads();
-  const bool comb = !A.rhs_only && A.a != 0.0;
-  for (int idx = threadIdx.x; idx < tx * ty * NL; idx += blockDim.x) {
-    const int cl = idx / NL;
-    const int j = idx - cl * NL;
-    const int cyl = cl / tx;
-    const int cxl = cl - cyl * tx;
-    const int gx = ix0 + cxl, gy = iy0 + cyl;
-    if (gx < nx && gy < ny) {
-      const size_t g = ((size_t)gy * nx + gx) * NL + j;
-      const int slot = DIM == 2 ? (cyl + 1) * W + cxl + 1 : cxl + 1;
-      double v = lds[j * S + slot];
-      if (comb) v = fma(A.a, A.un[g], v);
-      A.out[g] = v;
+    for (int j = 0; j < NL; ++j) dst[j] = L[j];
+  } else {
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+      double v = A.b * fma(A.dt, L[j], lds[j * S + sc]);
+      if (comb) v = fma(A.a, un[j], v);
+      dst[j] = v;
     }
   }
 }

@@ -13,25 +13,40 @@
 namespace dgk {
 namespace {
 
-template <int FLUX, int MODE>
-hipError_t launch_stage_fm(const StageArgs& A, dim3 grid, dim3 block, size_t lds, hipStream_t st) {
-  auto k = stage_kernel<DGK_DIM, DGK_P, FLUX, MODE>;
+template <int FLUX, int MODE, int TX, int TY>
+hipError_t launch_tile(const StageArgs& A, hipStream_t st) {
+  constexpr int NL = DGK_DIM == 1 ? DGK_P + 1 : (DGK_P + 1) * (DGK_P + 1);
+  auto k = stage_kernel<DGK_DIM, DGK_P, FLUX, MODE, TX, TY>;
+  const size_t lds = sizeof(double) * (size_t)tile_lds_doubles(DGK_DIM, NL, TX, TY);
   if (lds > 65536) {
     // tiles above 64 KB of LDS: raise the per-kernel limit to what this launch needs
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
+  dim3 grid((A.nx + TX - 1) / TX, DGK_DIM == 2 ? (A.ny + TY - 1) / TY : 1);
+  dim3 block(DGK_DIM == 2 ? TX * TY : TX);
   hipLaunchKernelGGL(k, grid, block, lds, st, A);
   return hipGetLastError();
 }
 
+template <int FLUX, int MODE>
+hipError_t launch_stage_fm(const StageArgs& A, hipStream_t st) {
+  if constexpr (DGK_DIM == 1) {
+    if (A.tx == 64) return launch_tile<FLUX, MODE, 64, 1>(A, st);
+    return launch_tile<FLUX, MODE, 256, 1>(A, st);
+  } else {
+    if (A.tx == 8) return launch_tile<FLUX, MODE, 8, 8>(A, st);
+    return launch_tile<FLUX, MODE, 16, 16>(A, st);
+  }
+}
+
 template <int FLUX>
-hipError_t launch_stage_f(int mode, const StageArgs& A, dim3 g, dim3 b, size_t l, hipStream_t s) {
+hipError_t launch_stage_f(int mode, const StageArgs& A, hipStream_t s) {
   switch (mode) {
-    case MODE_DG: return launch_stage_fm<FLUX, MODE_DG>(A, g, b, l, s);
-    case MODE_LO: return launch_stage_fm<FLUX, MODE_LO>(A, g, b, l, s);
-    default: return launch_stage_fm<FLUX, MODE_WENO>(A, g, b, l, s);
+    case MODE_DG: return launch_stage_fm<FLUX, MODE_DG>(A, s);
+    case MODE_LO: return launch_stage_fm<FLUX, MODE_LO>(A, s);
+    default: return launch_stage_fm<FLUX, MODE_WENO>(A, s);
   }
 }
 
@@ -47,13 +62,8 @@ extern "C" hipError_t DGK_CAT(dgk_launch, DGK_DIM, DGK_P)(const LaunchReq* r) {
   const StageArgs& A = r->args;
   switch (r->kind) {
     case LAUNCH_STAGE: {
-      const int tx = A.tx, ty = DGK_DIM == 2 ? A.ty : 1;
-      dim3 grid((A.nx + tx - 1) / tx, DGK_DIM == 2 ? (A.ny + ty - 1) / ty : 1);
-      dim3 block(tx * ty);
-      constexpr int NL = DGK_DIM == 1 ? DGK_P + 1 : (DGK_P + 1) * (DGK_P + 1);
-      size_t lds = sizeof(double) * NL * (size_t)A.lds_stride;
-      if (r->flux == FLUX_LINADV) return launch_stage_f<FLUX_LINADV>(r->mode, A, grid, block, lds, r->stream);
-      return launch_stage_f<FLUX_BURGERS>(r->mode, A, grid, block, lds, r->stream);
+      if (r->flux == FLUX_LINADV) return launch_stage_f<FLUX_LINADV>(r->mode, A, r->stream);
+      return launch_stage_f<FLUX_BURGERS>(r->mode, A, r->stream);
     }
     case LAUNCH_PROJECT: {
       const long long n = r->ncells;
