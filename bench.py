@@ -97,6 +97,56 @@ def cpu_baseline(w, budget_s=15.0):
                       f"PyTorch CPU fp64, {t:.1f} s"}
 
 
+def bench_batch(steps=100, seed=0, count=512):
+    """512 independent problems (1D advection / Burgers, 2D rotation, degrees
+    1..4, seeded sizes) for `steps` SSP-RK3 steps each with its own dt: the
+    batched graph-captured path against the same kernels launched one problem
+    and one stage at a time (no graph), from the same initial state."""
+    import torch
+    from paper_2309_12019_amd import dgweno, inputs
+    ws = inputs.batch_mix(seed, count, steps)
+    B = dgweno.Batch.from_workloads(ws)
+    arena = B.empty()
+    for w, v in zip(ws, B.views(arena)):
+        g = dgweno.DG.from_workload(w)
+        pts = torch.from_numpy(g.proj_nodes()).to(g.device)
+        g.project_ic(w.eval_ic(pts).reshape(-1).contiguous(), v)
+        g.close()
+    torch.cuda.synchronize()
+    U0 = arena.clone()
+    dts = [w.dt() for w in ws]
+    report = B.tune(U0, dts, reps=3)
+    st = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    B.run(arena, dts, steps)          # records the graph (untimed)
+    torch.cuda.synchronize()
+    arena.copy_(U0)
+    torch.cuda.synchronize()
+    ev[0].record(st)
+    B.run(arena, dts, steps)
+    ev[1].record(st)
+    torch.cuda.synchronize()
+    seq = U0.clone()
+    torch.cuda.synchronize()
+    ev[2].record(st)
+    B.run_sequential(seq, dts, steps)
+    ev[3].record(st)
+    torch.cuda.synchronize()
+    tb = ev[0].elapsed_time(ev[1]) / 1e3
+    ts = ev[2].elapsed_time(ev[3]) / 1e3
+    ndof = sum(w.ndof for w in ws)
+    upd = 3.0 * steps * ndof
+    return {"workload": f"{count} problems: 1D advection/Burgers 64-4096 cells, 2D rotation 32^2-512^2, "
+                        f"p 1..4, seed {seed}, {steps} SSP-RK3 steps each",
+            "problems": count, "dofs": ndof, "classes": B.num_classes(),
+            "value": upd / tb, "unit": "DOF-updates/s",
+            "one_launch_per_problem_value": upd / ts,
+            "speedup_vs_one_launch_per_problem": ts / tb,
+            "batched_s": tb, "one_launch_per_problem_s": ts,
+            "max_abs_diff_vs_one_launch_per_problem": float((arena - seq).abs().max()),
+            "tuned_schedule": [B.schedule(c) for c in range(B.num_classes())]}
+
+
 def traffic_for(wname):
     """HBM bytes per stage launch from the committed rocprofv3 counter summary,
     if one exists for this workload (else None)."""
@@ -119,6 +169,8 @@ def main():
     ap.add_argument("--extra", default="rot2d_256_p3,burgers2d_1024_p2",
                     help="comma-separated workloads reported alongside (no cpu baseline)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=100)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -174,6 +226,8 @@ def main():
                        "hbm_frac": bpd * we.ndof / (s_ / (3 * k)) / 1e9 / HBM_PEAK_GBS}
     if extra:
         line["extra"] = extra
+    if not args.no_batch:
+        line["batched"] = bench_batch(args.batch_steps)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(line), flush=True)

@@ -148,6 +148,66 @@ int dg_set_stream(dg_ctx* ctx, void* stream);
 /* Message of the last failure on the calling thread ("" if none). */
 const char* dg_last_error(void);
 
+/* Host-side validation of a descriptor (the checks dg_init_mesh performs
+ * before any device call).  DG_OK or DG_EINVAL. */
+int dg_validate_desc(const dg_mesh_desc* desc);
+
+/* ------------------------------------------------------------------------
+ * Batched execution of independent problems.
+ *
+ * Many problems of uneven mesh size and degree advance together: problems
+ * are grouped into kernel classes (dim, p, flux, mode); every RK stage of a
+ * class is one persistent launch that walks the class's tile list, and a run
+ * of N steps is one HIP graph in which the classes form independent chains on
+ * up to four concurrent branches.  Each problem's arithmetic is that of the
+ * single-problem path (same per-cell code, same tables), so a problem's
+ * result does not depend on the batch it is part of.
+ * ------------------------------------------------------------------------ */
+typedef struct dg_batch dg_batch;
+
+/* Create a batch from `count` descriptors (each validated as for
+ * dg_init_mesh; all work runs on descs[0].stream).  Allocates the problem
+ * table, tile lists and two stage arenas of the batch's total size. */
+int dg_batch_create(const dg_mesh_desc* descs, int32_t count, dg_batch** out);
+void dg_batch_destroy(dg_batch* batch);
+
+/* Layout of the caller-owned state arena: problem i occupies doubles
+ * [offsets[i], offsets[i+1]) in the single-problem layout.  offsets: host
+ * array of count+1 int64 (may be NULL); total: host int64 (may be NULL). */
+int dg_batch_layout(const dg_batch* batch, int64_t* offsets, int64_t* total);
+
+/* nsteps SSP-RK3 steps of every problem, problem i with step dts[i] (host
+ * array of count doubles, each finite and > 0), in place on the arena
+ * (device).  The graph is recorded once per (arena, dts, nsteps) and
+ * replayed. */
+int dg_batch_run(dg_batch* batch, double* arena, const double* dts, int32_t nsteps);
+
+/* Reference schedule for comparisons: the same steps with the plain stage
+ * kernel, one launch per problem per RK stage, problems in order, on the
+ * batch stream, no graph.  Arguments as for dg_batch_run. */
+int dg_batch_run_sequential(dg_batch* batch, double* arena, const double* dts, int32_t nsteps);
+
+/* Schedule of class `cls` (0 <= cls < number of classes): tile shape (as in
+ * dg_set_tile), persistent grid of grid_per_cu workgroups per compute unit
+ * (1..64), and tile order (0: problems by decreasing size, 1: increasing,
+ * 2: problems interleaved round robin). */
+int dg_batch_num_classes(const dg_batch* batch, int32_t* n);
+int dg_batch_set_schedule(dg_batch* batch, int32_t cls, int32_t tx, int32_t ty, int32_t grid_per_cu,
+                          int32_t order);
+/* info[10] = {dim, p, flux, mode, problems, tx, ty, grid_per_cu, order, branch} */
+int dg_batch_get_schedule(const dg_batch* batch, int32_t cls, int32_t* info);
+/* Number of concurrent graph branches (1..4); classes are assigned to them
+ * longest-first onto the least loaded branch. */
+int dg_batch_set_branches(dg_batch* batch, int32_t branches);
+
+/* Autotuner: for every class, time `reps` stage launches (reading the arena,
+ * writing only internal buffers: the state is not modified) for every tile
+ * shape, grid size and tile order, keep the fastest; then choose the branch
+ * count from timed stages.  Synchronous.  dts as for dg_batch_run.  report
+ * (host, may be NULL) receives a text summary of at most report_len bytes. */
+int dg_batch_tune(dg_batch* batch, double* arena, const double* dts, int32_t reps, char* report,
+                  int32_t report_len);
+
 #ifdef __cplusplus
 }
 #endif

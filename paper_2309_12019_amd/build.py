@@ -51,9 +51,10 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
             objs.append(o)
             steps.append([cc, *FLAGS, f"-DDGK_DIM={dim}", f"-DDGK_P={p}", "-c",
                           os.path.join(CSRC, "dg_stage.hip"), "-o", o])
-    o = os.path.join(BUILD, "dg_api.o")
-    objs.append(o)
-    steps.append([cc, *FLAGS, "-c", os.path.join(CSRC, "dg_api.hip"), "-o", o])
+    for name in ("dg_api", "dg_batch"):
+        o = os.path.join(BUILD, f"{name}.o")
+        objs.append(o)
+        steps.append([cc, *FLAGS, "-c", os.path.join(CSRC, f"{name}.hip"), "-o", o])
     jobs = jobs or min(9, os.cpu_count() or 4)
     with concurrent.futures.ThreadPoolExecutor(jobs) as ex:
         for out in ex.map(_run, steps):

@@ -217,6 +217,13 @@ void dg_default_desc(dg_mesh_desc* d) {
 
 const char* dg_last_error(void) { return g_err; }
 
+int dgk_fail(int code, const char* msg) { return fail(code, "%s", msg); }
+
+int dg_validate_desc(const dg_mesh_desc* desc) {
+  g_err[0] = 0;
+  return validate(desc);
+}
+
 int dg_init_mesh(const dg_mesh_desc* desc, dg_ctx** out) {
   g_err[0] = 0;
   if (!out) return fail(DG_EINVAL, "out is NULL");

@@ -63,7 +63,8 @@ constexpr int kTiles2D[2][2] = {{16, 16}, {8, 8}};
 
 __host__ __device__ inline int tile_lds_doubles(int dim, int nl, int tx, int ty) {
   const int ns = dim == 1 ? tx + 2 : (tx + 2) * (ty + 2);
-  return nl * (ns | 1);
+  const int nt = dim == 1 ? tx : tx * ty;
+  return nl * (ns | 1) + nl * nt;   // halo tile + U^n of the tile's cells
 }
 
 // x mod n for x in [-1, n + tile]: cheap for the common single wrap
@@ -497,21 +498,18 @@ __device__ inline void load_slot(const StageArgs& A, double* lds, int slot, int 
   for (int j = 0; j < NL; ++j) lds[j * S + slot] = v[j];
 }
 
-// The fused stage kernel.  Grid: (ceil(nx/TX), ceil(ny/TY)); block: TX*TY
-// threads, one per cell; dynamic LDS: NL * S doubles (the tile with its face
-// halo, coefficient-major).  Each thread loads its own cell's coefficients
-// (one base address, compile-time offsets; a wave covers a contiguous span),
-// the first threads also load the halo ring, and each thread writes its own
-// results, so the kernel has a single barrier.
+// One tile of the fused stage: TX*TY threads, one per cell.  LDS: NL * S
+// doubles (the tile with its face halo, coefficient-major) + NL * TX*TY
+// doubles (U^n of the tile's cells).  Each thread loads its own cell's
+// coefficients (one base address, compile-time offsets; a wave covers a
+// contiguous span), the first threads also load the halo ring, and each
+// thread writes its own results; one barrier separates loads from arithmetic.
 template <int DIM, int P, int FLUX, int MODE, int TX, int TY>
-__global__ void __launch_bounds__(DIM == 2 ? TX * TY : TX) stage_kernel(const StageArgs A) {
+__device__ inline void stage_tile(const StageArgs& A, double* lds, int ix0, int iy0) {
   using G = TileGeom<DIM, TX, TY>;
   using C = Cell<DIM, P, FLUX, MODE, G::S, G::W>;
   constexpr int NL = C::NL;
   constexpr int S = G::S, W = G::W;
-  extern __shared__ double lds[];
-  const int ix0 = blockIdx.x * TX;
-  const int iy0 = DIM == 2 ? blockIdx.y * TY : 0;
   const int nx = A.nx, ny = DIM == 2 ? A.ny : 1;
   const bool comb = !A.rhs_only && A.a != 0.0;
 
@@ -522,11 +520,15 @@ __global__ void __launch_bounds__(DIM == 2 ? TX * TY : TX) stage_kernel(const St
   const int sc = DIM == 2 ? (ly + 1) * W + lx + 1 : lx + 1;
   const size_t cell = (size_t)iy * nx + ix;
 
-  // U^n of this cell (RK combination), issued together with the tile loads
-  double un[NL];
+  // U^n of this cell (RK combination), issued together with the tile loads and
+  // parked in LDS so it holds no registers during the cell arithmetic
+  double* lds_un = lds + NL * S;
   if (comb && active) {
+    double un[NL];
 #pragma unroll
     for (int j = 0; j < NL; ++j) un[j] = A.un[cell * NL + j];
+#pragma unroll
+    for (int j = 0; j < NL; ++j) lds_un[j * G::NT + t] = un[j];
   }
   // interior slots (cells past a ragged edge hold the wrapped or exterior state)
   load_slot<DIM, NL, S>(A, lds, sc, ix, iy);
@@ -553,22 +555,72 @@ __global__ void __launch_bounds__(DIM == 2 ? TX * TY : TX) stage_kernel(const St
     }
   }
   __syncthreads();
-  if (!active) return;
-
-  double L[NL], gam;
-  C::rhs(A, lds + sc, ix, iy, L, gam);
-  if (A.gamma) A.gamma[cell] = gam;
-  double* dst = A.out + cell * NL;
-  if (A.rhs_only) {
+  if (active) {
+    double L[NL], gam;
+    C::rhs(A, lds + sc, ix, iy, L, gam);
+    if (A.gamma) A.gamma[cell] = gam;
+    double* dst = A.out + cell * NL;
+    if (A.rhs_only) {
 #pragma unroll
-    for (int j = 0; j < NL; ++j) dst[j] = L[j];
-  } else {
+      for (int j = 0; j < NL; ++j) dst[j] = L[j];
+    } else {
 #pragma unroll
-    for (int j = 0; j < NL; ++j) {
-      double v = A.b * fma(A.dt, L[j], lds[j * S + sc]);
-      if (comb) v = fma(A.a, un[j], v);
-      dst[j] = v;
+      for (int j = 0; j < NL; ++j) {
+        double v = A.b * fma(A.dt, L[j], lds[j * S + sc]);
+        if (comb) v = fma(A.a, lds_un[j * G::NT + t], v);
+        dst[j] = v;
+      }
     }
+  }
+}
+
+// The fused stage kernel.  Grid: (ceil(nx/TX), ceil(ny/TY)), one tile each.
+template <int DIM, int P, int FLUX, int MODE, int TX, int TY>
+__global__ void __launch_bounds__(DIM == 2 ? TX * TY : TX) stage_kernel(const StageArgs A) {
+  extern __shared__ double lds[];
+  stage_tile<DIM, P, FLUX, MODE, TX, TY>(A, lds, blockIdx.x * TX, DIM == 2 ? blockIdx.y * TY : 0);
+}
+
+// ---------------------------------------------------------------------------
+// Batched stage: many independent problems of one kernel class (dimension,
+// degree, flux, mode, tile) in one persistent launch.  Each workgroup walks
+// the tile list with a grid stride (the list order is the schedule); a tile
+// names its problem, whose entry holds the problem's parameters and the
+// offset of its state in the batch arena.
+// ---------------------------------------------------------------------------
+struct BatchProblem {
+  long long off;   // first double of the problem's state in the arena
+  StageArgs args;  // mesh, flux, sensor parameters and dt (pointers unused)
+};
+struct BatchTile {
+  int prob, ix0, iy0, pad;
+};
+struct BatchStageArgs {
+  const BatchProblem* probs;
+  const BatchTile* tiles;
+  int ntiles;
+  const double* uin;
+  const double* un;
+  double* out;
+  double a, b;
+};
+
+template <int DIM, int P, int FLUX, int MODE, int TX, int TY>
+__global__ void __launch_bounds__(DIM == 2 ? TX * TY : TX) batch_stage_kernel(const BatchStageArgs B) {
+  extern __shared__ double lds[];
+  for (int k = blockIdx.x; k < B.ntiles; k += gridDim.x) {
+    const BatchTile tl = B.tiles[k];
+    StageArgs A = B.probs[tl.prob].args;
+    const long long off = B.probs[tl.prob].off;
+    A.uin = B.uin + off;
+    A.un = B.un + off;
+    A.out = B.out + off;
+    A.gamma = nullptr;
+    A.a = B.a;
+    A.b = B.b;
+    A.rhs_only = 0;
+    stage_tile<DIM, P, FLUX, MODE, TX, TY>(A, lds, tl.ix0, tl.iy0);
+    __syncthreads();  // the next tile reuses LDS
   }
 }
 

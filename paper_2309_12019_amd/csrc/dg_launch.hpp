@@ -5,7 +5,7 @@
 
 namespace dgk {
 
-enum LaunchKind { LAUNCH_STAGE = 0, LAUNCH_PROJECT = 1, LAUNCH_LAMBDA = 2 };
+enum LaunchKind { LAUNCH_STAGE = 0, LAUNCH_PROJECT = 1, LAUNCH_LAMBDA = 2, LAUNCH_BATCH = 3 };
 
 struct LaunchReq {
   int kind;
@@ -15,6 +15,7 @@ struct LaunchReq {
   double* dst;          // LAUNCH_PROJECT: coefficients; LAUNCH_LAMBDA: block maxima
   long long ncells;
   hipStream_t stream;
+  BatchStageArgs batch;  // LAUNCH_BATCH (tile shape in args.tx/args.ty, grid in ncells)
 };
 
 typedef hipError_t (*LaunchFn)(const LaunchReq*);

@@ -41,6 +41,41 @@ hipError_t launch_stage_fm(const StageArgs& A, hipStream_t st) {
   }
 }
 
+template <int FLUX, int MODE, int TX, int TY>
+hipError_t launch_batch_tile(const BatchStageArgs& B, int grid, hipStream_t st) {
+  constexpr int NL = DGK_DIM == 1 ? DGK_P + 1 : (DGK_P + 1) * (DGK_P + 1);
+  auto k = batch_stage_kernel<DGK_DIM, DGK_P, FLUX, MODE, TX, TY>;
+  const size_t lds = sizeof(double) * (size_t)tile_lds_doubles(DGK_DIM, NL, TX, TY);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k, dim3(grid), dim3(DGK_DIM == 2 ? TX * TY : TX), lds, st, B);
+  return hipGetLastError();
+}
+
+template <int FLUX, int MODE>
+hipError_t launch_batch_fm(const LaunchReq* r) {
+  const int grid = (int)r->ncells;
+  if constexpr (DGK_DIM == 1) {
+    if (r->args.tx == 64) return launch_batch_tile<FLUX, MODE, 64, 1>(r->batch, grid, r->stream);
+    return launch_batch_tile<FLUX, MODE, 256, 1>(r->batch, grid, r->stream);
+  } else {
+    if (r->args.tx == 8) return launch_batch_tile<FLUX, MODE, 8, 8>(r->batch, grid, r->stream);
+    return launch_batch_tile<FLUX, MODE, 16, 16>(r->batch, grid, r->stream);
+  }
+}
+
+template <int FLUX>
+hipError_t launch_batch_f(const LaunchReq* r) {
+  switch (r->mode) {
+    case MODE_DG: return launch_batch_fm<FLUX, MODE_DG>(r);
+    case MODE_LO: return launch_batch_fm<FLUX, MODE_LO>(r);
+    default: return launch_batch_fm<FLUX, MODE_WENO>(r);
+  }
+}
+
 template <int FLUX>
 hipError_t launch_stage_f(int mode, const StageArgs& A, hipStream_t s) {
   switch (mode) {
@@ -64,6 +99,10 @@ extern "C" hipError_t DGK_CAT(dgk_launch, DGK_DIM, DGK_P)(const LaunchReq* r) {
     case LAUNCH_STAGE: {
       if (r->flux == FLUX_LINADV) return launch_stage_f<FLUX_LINADV>(r->mode, A, r->stream);
       return launch_stage_f<FLUX_BURGERS>(r->mode, A, r->stream);
+    }
+    case LAUNCH_BATCH: {
+      if (r->flux == FLUX_LINADV) return launch_batch_f<FLUX_LINADV>(r);
+      return launch_batch_f<FLUX_BURGERS>(r);
     }
     case LAUNCH_PROJECT: {
       const long long n = r->ncells;

@@ -66,6 +66,19 @@ EXPORTS = {
                                    ctypes.POINTER(ctypes.c_int32)]),
     "dg_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "dg_last_error": (ctypes.c_char_p, []),
+    "dg_validate_desc": (ctypes.c_int, [ctypes.POINTER(MeshDesc)]),
+    "dg_batch_create": (ctypes.c_int, [ctypes.POINTER(MeshDesc), ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
+    "dg_batch_destroy": (None, [ctypes.c_void_p]),
+    "dg_batch_layout": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "dg_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]),
+    "dg_batch_run_sequential": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]),
+    "dg_batch_num_classes": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
+    "dg_batch_set_schedule": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.c_int32, ctypes.c_int32]),
+    "dg_batch_get_schedule": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "dg_batch_set_branches": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "dg_batch_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                     ctypes.c_char_p, ctypes.c_int32]),
 }
 
 _lib = None
@@ -212,3 +225,93 @@ class DG:
         pts = self.proj_nodes()
         vals = torch.from_numpy(np.ascontiguousarray(w.eval_ic(pts))).to(self.device)
         return self.project_ic(vals.reshape(-1).contiguous())
+
+
+class Batch:
+    """Many independent problems advanced together (dg_batch_*).
+
+    The states live in one arena tensor; `views()` returns per-problem views
+    of shape (n_cells, n_loc)."""
+
+    def __init__(self, descs, stream: Optional[torch.cuda.Stream] = None):
+        lib = load()
+        self.lib = lib
+        st = stream if stream is not None else torch.cuda.current_stream()
+        arr = (MeshDesc * len(descs))(*descs)
+        for d in arr:
+            d.stream = ctypes.c_void_p(st.cuda_stream)
+        self._descs = arr
+        h = ctypes.c_void_p()
+        _check(lib.dg_batch_create(arr, len(descs), ctypes.byref(h)))
+        self.h = h
+        self.count = len(descs)
+        offs = np.zeros(self.count + 1, dtype=np.int64)
+        tot = ctypes.c_int64()
+        _check(lib.dg_batch_layout(h, offs.ctypes.data_as(ctypes.c_void_p), ctypes.byref(tot)))
+        self.offsets = offs
+        self.total = tot.value
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.nloc = [(d.p + 1) ** d.dim for d in descs]
+
+    @classmethod
+    def from_workloads(cls, ws, stream=None) -> "Batch":
+        return cls([desc_from_fields(w.fields()) for w in ws], stream)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dg_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def empty(self) -> torch.Tensor:
+        return torch.empty(self.total, dtype=torch.float64, device=self.device)
+
+    def views(self, arena: torch.Tensor):
+        return [arena[self.offsets[i]:self.offsets[i + 1]].view(-1, self.nloc[i]) for i in range(self.count)]
+
+    def _dts(self, dts) -> np.ndarray:
+        a = np.ascontiguousarray(np.asarray(dts, dtype=np.float64))
+        if a.shape != (self.count,):
+            raise ValueError(f"need {self.count} time steps")
+        return a
+
+    def run(self, arena: torch.Tensor, dts, nsteps: int) -> torch.Tensor:
+        a = self._dts(dts)
+        _check(self.lib.dg_batch_run(self.h, _ptr(arena, self.total, "arena"),
+                                     a.ctypes.data_as(ctypes.c_void_p), int(nsteps)))
+        return arena
+
+    def run_sequential(self, arena: torch.Tensor, dts, nsteps: int) -> torch.Tensor:
+        a = self._dts(dts)
+        _check(self.lib.dg_batch_run_sequential(self.h, _ptr(arena, self.total, "arena"),
+                                                a.ctypes.data_as(ctypes.c_void_p), int(nsteps)))
+        return arena
+
+    def tune(self, arena: torch.Tensor, dts, reps: int = 5) -> str:
+        a = self._dts(dts)
+        buf = ctypes.create_string_buffer(16384)
+        _check(self.lib.dg_batch_tune(self.h, _ptr(arena, self.total, "arena"),
+                                      a.ctypes.data_as(ctypes.c_void_p), int(reps), buf, len(buf)))
+        return buf.value.decode()
+
+    def num_classes(self) -> int:
+        n = ctypes.c_int32()
+        _check(self.lib.dg_batch_num_classes(self.h, ctypes.byref(n)))
+        return n.value
+
+    def schedule(self, cls: int):
+        info = np.zeros(10, dtype=np.int32)
+        _check(self.lib.dg_batch_get_schedule(self.h, int(cls), info.ctypes.data_as(ctypes.c_void_p)))
+        keys = ("dim", "p", "flux", "mode", "problems", "tx", "ty", "grid_per_cu", "order", "branch")
+        return dict(zip(keys, info.tolist()))
+
+    def set_schedule(self, cls: int, tx: int, ty: int, grid_per_cu: int, order: int) -> None:
+        _check(self.lib.dg_batch_set_schedule(self.h, int(cls), int(tx), int(ty), int(grid_per_cu), int(order)))
+
+    def set_branches(self, n: int) -> None:
+        _check(self.lib.dg_batch_set_branches(self.h, int(n)))

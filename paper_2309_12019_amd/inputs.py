@@ -93,31 +93,51 @@ class Workload:
         d.pop("ic")
         return d
 
-    def eval_ic(self, pts: np.ndarray) -> np.ndarray:
-        """Initial data at points pts [..., dim]."""
-        pts = np.asarray(pts, dtype=np.float64)
+    def eval_ic(self, pts):
+        """Initial data at points pts [..., dim] (numpy array or torch tensor)."""
+        if isinstance(pts, (list, tuple)) or (hasattr(pts, "dtype") and not hasattr(pts, "is_cuda")):
+            pts = np.asarray(pts, dtype=np.float64)
         if self.dim == 1:
             return self.ic(pts[..., 0])
         return self.ic(pts[..., 0], pts[..., 1])
 
 
 # ---------------------------------------------------------------------------
-# initial data
+# initial data (numpy arrays, or torch tensors for evaluation on the device)
 # ---------------------------------------------------------------------------
+class _Ops:
+    """The few array operations the initial data need, for numpy or torch."""
+
+    def __init__(self, x):
+        import sys
+        torch = sys.modules.get("torch")
+        self.t = torch is not None and isinstance(x, torch.Tensor)
+        self.m = torch if self.t else np
+
+    def where(self, c, a, b):
+        if self.t:
+            a = a if isinstance(a, self.m.Tensor) else self.m.full_like(c, a, dtype=self.m.float64)
+            b = b if isinstance(b, self.m.Tensor) else self.m.full_like(c, b, dtype=self.m.float64)
+        return self.m.where(c, a, b)
+
+    def fl(self, c):
+        return c.to(self.m.float64) if self.t else c.astype(np.float64)
+
+
 def sin_plus_pulse(x):
     """sin(2 pi x) plus a unit square pulse on [0.3, 0.5]."""
-    x = np.asarray(x)
-    return np.sin(2 * np.pi * x) + ((x >= 0.3) & (x <= 0.5)).astype(np.float64)
+    o = _Ops(x)
+    return o.m.sin(2 * np.pi * x) + o.fl((x >= 0.3) & (x <= 0.5))
 
 
 def cos_wave(x):
     """cos(2 pi (x - 0.5)), the smooth advection datum of Sec. 5.1."""
-    return np.cos(2 * np.pi * (np.asarray(x) - 0.5))
+    return _Ops(x).m.cos(2 * np.pi * (x - 0.5))
 
 
 def sin_wave(x):
     """sin(2 pi x), the Burgers datum of Sec. 5.2."""
-    return np.sin(2 * np.pi * np.asarray(x))
+    return _Ops(x).m.sin(2 * np.pi * x)
 
 
 def square_and_bump(x):
@@ -152,19 +172,20 @@ class HumpAndCylinder:
         self.hump, self.cyl = shapes
 
     def __call__(self, x, y):
-        x, y = np.asarray(x), np.asarray(y)
+        o = _Ops(x)
+        m = o.m
         hx, hy, hr = self.hump
-        rho = np.hypot(x - hx, y - hy)
-        u = np.where(rho <= hr, 0.25 * (1 + np.cos(np.pi * rho / hr)), 0.0)
+        rho = m.hypot(x - hx, y - hy)
+        u = o.where(rho <= hr, 0.25 * (1 + m.cos(np.pi * rho / hr)), 0.0)
         cx, cy, cr = self.cyl
         ox, oy = cx - 0.5, cy - 0.5
         on = math.hypot(ox, oy)
         ex, ey = ox / on, oy / on                 # outward radial unit vector
         s = (x - cx) * ex + (y - cy) * ey         # along the radial direction
         t = -(x - cx) * ey + (y - cy) * ex        # across it
-        inside = np.hypot(x - cx, y - cy) <= cr
-        slot = (np.abs(t) < cr / 6) & (s < 2 * cr / 3)
-        return u + np.where(inside & ~slot, 1.0, 0.0)
+        inside = m.hypot(x - cx, y - cy) <= cr
+        slot = (m.abs(t) < cr / 6) & (s < 2 * cr / 3)
+        return u + o.fl(inside & ~slot)
 
 
 class FourierModes:
@@ -186,10 +207,13 @@ class FourierModes:
         self.dim = dim
 
     def __call__(self, x, y=None):
-        x = np.asarray(x)
-        y = np.zeros_like(x) if y is None else np.asarray(y)
-        arg = 2 * np.pi * (x[..., None] * self.k[:, 0] + y[..., None] * self.k[:, 1]) + self.phi
-        return (self.a * np.cos(arg)).sum(-1)
+        o = _Ops(x)
+        m = o.m
+        y = m.zeros_like(x) if y is None else y
+        out = m.zeros_like(x)
+        for kx, ky, a, ph in zip(self.k[:, 0], self.k[:, 1], self.a, self.phi):
+            out = out + a * m.cos(2 * np.pi * (kx * x + ky * y) + ph)
+        return out
 
     def bound(self) -> float:
         return float(np.abs(self.a).sum())
