@@ -148,6 +148,42 @@ int dg_set_stream(dg_ctx* ctx, void* stream);
 /* Message of the last failure on the calling thread ("" if none). */
 const char* dg_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Discrete adjoint (reverse mode of the fully discrete scheme).
+ *
+ * The derivative is that of the computed map, including the HWENO weights,
+ * the sensor min(1, ratio)^q and its threshold, lambda_e and the LLF wave
+ * speed; where a max/min switches the derivative of the active branch is
+ * used (ties: split evenly).  The first adjoint call on a context allocates
+ * three state-sized buffers and one sensor-record buffer.
+ * ------------------------------------------------------------------------ */
+
+/* out = J(U)^T v: the transpose Jacobian of dU/dt = L(U) (dg_rhs) applied to
+ * v.  U, v, out: device [n_cells * n_loc]; out must not overlap U or v. */
+int dg_rhs_vjp(dg_ctx* ctx, const double* U, const double* v, double* out);
+
+/* lam_in = (d step(Un) / d Un)^T lam_out for one SSP-RK3 step of size dt
+ * (eq. ssp); the stage states are recomputed from Un.  lam_in may alias
+ * lam_out but not Un. */
+int dg_step_adjoint(dg_ctx* ctx, const double* Un, double dt, const double* lam_out, double* lam_in);
+
+/* Checkpointed gradient of a function of U^N with respect to U^0 over
+ * nsteps steps, with at most nsnaps stored states (binomial checkpointing:
+ * each reverse sub-range advances to a checkpoint chosen so the remainder
+ * can be reversed with one slot fewer within the same number of sweeps).
+ * ckpt: caller-owned device buffer of (nsnaps + 2) * n_cells * n_loc doubles
+ * (slot 0 holds U^0, the last slot is working space); it must not change
+ * between the two calls.
+ * dg_adjoint_forward: U^0 -> U^N (written to UT), storing checkpoints.
+ * dg_adjoint_backward: lam holds dJ/dU^N on entry and dJ/dU^0 on exit. */
+int dg_adjoint_forward(dg_ctx* ctx, const double* U0, double* UT, double dt, int32_t nsteps, int32_t nsnaps,
+                       double* ckpt);
+int dg_adjoint_backward(dg_ctx* ctx, double dt, int32_t nsteps, int32_t nsnaps, double* ckpt, double* lam);
+
+/* Host-only statistics of the checkpoint schedule: stats[6] = {forward-sweep
+ * steps, recomputed steps, stores, adjoint steps, highest slot, actions}. */
+int dg_revolve_stats(int32_t nsteps, int32_t nsnaps, int64_t* stats);
+
 /* Host-side validation of a descriptor (the checks dg_init_mesh performs
  * before any device call).  DG_OK or DG_EINVAL. */
 int dg_validate_desc(const dg_mesh_desc* desc);

@@ -64,6 +64,10 @@ struct dg_ctx {
   size_t red_len = 0;
   LaunchFn launch = nullptr;
   std::map<GraphKey, hipGraphExec_t> graphs;
+  // adjoint buffers, allocated on first use
+  double* A1 = nullptr;   // cotangent of U^(2)
+  double* A2 = nullptr;   // cotangent of U^(1)
+  double* Z = nullptr;    // sensor records
 };
 
 namespace {
@@ -181,6 +185,134 @@ int check_tile(const dg_ctx* c, int tx, int ty) {
   return DG_OK;
 }
 
+int zrec_size(int dim, int nl) { return nl + 2 * (2 * dim + 1) + 1; }
+
+int ensure_adjoint(dg_ctx* c) {
+  if (c->A1) return DG_OK;
+  const size_t n = (size_t)c->ncells * c->nl;
+  const size_t nz = (size_t)c->ncells * zrec_size(c->d.dim, c->nl);
+  hipError_t e;
+  if ((e = hipMalloc(&c->A1, n * sizeof(double))) != hipSuccess ||
+      (e = hipMalloc(&c->A2, n * sizeof(double))) != hipSuccess ||
+      (e = hipMalloc(&c->Z, nz * sizeof(double))) != hipSuccess) {
+    if (c->A1) (void)hipFree(c->A1);
+    if (c->A2) (void)hipFree(c->A2);
+    c->A1 = c->A2 = nullptr;
+    c->Z = nullptr;
+    return fail(DG_ENOMEM, "adjoint buffers: %s", hipGetErrorString(e));
+  }
+  return DG_OK;
+}
+
+// out = alpha v + beta J(U)^T v + g1 X + g2 Y
+int adjoint_stage(dg_ctx* c, hipStream_t st, const double* U, const double* v, double* out, double alpha,
+                  double beta, const double* X, double g1, const double* Y, double g2) {
+  LaunchReq r{};
+  r.flux = c->d.flux;
+  r.mode = c->d.mode;
+  r.stream = st;
+  r.adj.s = base_args(c);
+  r.adj.s.uin = U;
+  r.adj.v = v;
+  r.adj.z = c->Z;
+  r.adj.out = out;
+  r.adj.X = X;
+  r.adj.Y = Y;
+  r.adj.alpha = alpha;
+  r.adj.beta = beta;
+  r.adj.g1 = g1;
+  r.adj.g2 = g2;
+  hipError_t e;
+  if (c->d.mode == DG_MODE_WENO) {
+    r.kind = dgk::LAUNCH_ADJ_SENSOR;
+    if ((e = c->launch(&r)) != hipSuccess) return hip_fail(e, "adjoint sensor launch");
+  }
+  r.kind = dgk::LAUNCH_ADJ_GRAD;
+  if ((e = c->launch(&r)) != hipSuccess) return hip_fail(e, "adjoint launch");
+  return DG_OK;
+}
+
+// lam_in = (d step(Un) / d Un)^T lam_out for eq. (ssp); recomputes U^(1), U^(2)
+int rk3_adjoint(dg_ctx* c, hipStream_t st, const double* Un, double dt, const double* lam_out, double* lam_in) {
+  int rc;
+  if ((rc = stage(c, st, Un, Un, c->U1, nullptr, 0.0, 1.0, dt, 0))) return rc;
+  if ((rc = stage(c, st, c->U1, Un, c->U2, nullptr, 0.75, 0.25, dt, 0))) return rc;
+  const double a2 = 0.75, b2 = 0.25, a3 = 1.0 / 3.0, b3 = 2.0 / 3.0;
+  // stage 3: U = a3 Un + b3 (U2 + dt L(U2))  ->  lam_U2 = b3 mu + b3 dt J(U2)^T mu
+  if ((rc = adjoint_stage(c, st, c->U2, lam_out, c->A1, b3, b3 * dt, nullptr, 0, nullptr, 0))) return rc;
+  // stage 2: U2 = a2 Un + b2 (U1 + dt L(U1))
+  if ((rc = adjoint_stage(c, st, c->U1, c->A1, c->A2, b2, b2 * dt, nullptr, 0, nullptr, 0))) return rc;
+  // stage 1: U1 = Un + dt L(Un); lam_n = lam_U1 + dt J(Un)^T lam_U1 + a2 lam_U2 + a3 mu
+  return adjoint_stage(c, st, Un, c->A2, lam_in, 1.0, dt, c->A1, a2, lam_out, a3);
+}
+
+// ---- binomial checkpointing (revolve-style) --------------------------------
+enum { RV_RESTORE = 0, RV_ADVANCE = 1, RV_STORE = 2, RV_ADJOINT = 3 };
+struct RvAction {
+  int op, a;
+};
+
+long long binom_capped(int n, int k) {
+  if (k < 0 || k > n) return 0;
+  long long r = 1;
+  for (int i = 1; i <= k; ++i) {
+    r = r * (n - k + i) / i;
+    if (r > (1LL << 40)) return 1LL << 40;
+  }
+  return r;
+}
+
+// Reverse steps [lo, hi) given the state at lo in slot `slot_lo` and `s` free
+// slots: advance m steps and checkpoint, reverse the tail with s-1 slots, then
+// the head with s.  m = n - C(s-1+t, s-1) with t the smallest number of sweeps
+// such that C(s+t, s) >= n (the binomial bound of reversal with s snapshots).
+void rv_plan(int lo, int hi, int s, int slot_lo, std::vector<int>& freeslots, std::vector<RvAction>& out) {
+  const int n = hi - lo;
+  if (n == 1) {
+    out.push_back({RV_RESTORE, slot_lo});
+    out.push_back({RV_ADJOINT, lo});
+    return;
+  }
+  if (s == 0 || freeslots.empty()) {
+    for (int k = hi - 1; k >= lo; --k) {
+      out.push_back({RV_RESTORE, slot_lo});
+      if (k > lo) out.push_back({RV_ADVANCE, k - lo});
+      out.push_back({RV_ADJOINT, k});
+    }
+    return;
+  }
+  int t = 1;
+  while (binom_capped(s + t, s) < n) ++t;
+  long long m = n - binom_capped(s - 1 + t, s - 1);
+  if (m < 1) m = 1;
+  if (m > n - 1) m = n - 1;
+  const int slot = freeslots.back();
+  freeslots.pop_back();
+  out.push_back({RV_RESTORE, slot_lo});
+  out.push_back({RV_ADVANCE, (int)m});
+  out.push_back({RV_STORE, slot});
+  rv_plan(lo + (int)m, hi, s - 1, slot, freeslots, out);
+  freeslots.push_back(slot);
+  rv_plan(lo, lo + (int)m, s, slot_lo, freeslots, out);
+}
+
+std::vector<RvAction> rv_schedule(int nsteps, int nsnaps) {
+  std::vector<int> freeslots;
+  for (int k = nsnaps; k >= 1; --k) freeslots.push_back(k);
+  std::vector<RvAction> out;
+  rv_plan(0, nsteps, nsnaps, 0, freeslots, out);
+  return out;
+}
+
+// index of the first action of the reverse sweep: the restore that precedes
+// the first adjoint step
+size_t rv_split(const std::vector<RvAction>& a) {
+  size_t i = 0;
+  while (i < a.size() && a[i].op != RV_ADJOINT) ++i;
+  while (i > 0 && a[i].op != RV_RESTORE) --i;
+  return i;
+}
+
 void drop_graphs(dg_ctx* c) {
   for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
   c->graphs.clear();
@@ -282,6 +414,9 @@ void dg_destroy(dg_ctx* c) {
   if (c->U1) (void)hipFree(c->U1);
   if (c->U2) (void)hipFree(c->U2);
   if (c->red) (void)hipFree(c->red);
+  if (c->A1) (void)hipFree(c->A1);
+  if (c->A2) (void)hipFree(c->A2);
+  if (c->Z) (void)hipFree(c->Z);
   if (c->capture) (void)hipStreamDestroy(c->capture);
   delete c;
 }
@@ -445,6 +580,115 @@ int dg_get_tile(const dg_ctx* c, int32_t* tx, int32_t* ty) {
   if (tx) *tx = c->tx;
   if (ty) *ty = c->ty;
   return DG_OK;
+}
+
+int dg_rhs_vjp(dg_ctx* c, const double* U, const double* v, double* out) {
+  if (!c || !U || !v || !out) return fail(DG_EINVAL, "NULL argument");
+  if (out == U || out == v) return fail(DG_EINVAL, "out must not overlap U or v");
+  int rc = ensure_adjoint(c);
+  if (rc) return rc;
+  return adjoint_stage(c, c->stream, U, v, out, 0.0, 1.0, nullptr, 0, nullptr, 0);
+}
+
+int dg_step_adjoint(dg_ctx* c, const double* Un, double dt, const double* lam_out, double* lam_in) {
+  if (!c || !Un || !lam_out || !lam_in) return fail(DG_EINVAL, "NULL argument");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite and > 0");
+  if (lam_in == Un) return fail(DG_EINVAL, "lam_in must not overlap Un");
+  int rc = ensure_adjoint(c);
+  if (rc) return rc;
+  return rk3_adjoint(c, c->stream, Un, dt, lam_out, lam_in);
+}
+
+int dg_revolve_stats(int32_t nsteps, int32_t nsnaps, int64_t* stats) {
+  if (nsteps < 1 || nsnaps < 0 || !stats) return fail(DG_EINVAL, "need nsteps >= 1, nsnaps >= 0, stats");
+  auto a = rv_schedule(nsteps, nsnaps);
+  const size_t split = rv_split(a);
+  int64_t fwd_steps = 0, rec_steps = 0, stores = 0, adj = 0, maxslot = 0;
+  int64_t last_adj = nsteps;
+  for (size_t i = 0; i < a.size(); ++i) {
+    if (a[i].op == RV_ADVANCE) (i < split ? fwd_steps : rec_steps) += a[i].a;
+    if (a[i].op == RV_STORE) {
+      ++stores;
+      maxslot = a[i].a > maxslot ? a[i].a : maxslot;
+    }
+    if (a[i].op == RV_ADJOINT) {
+      if (a[i].a != last_adj - 1) return fail(DG_EINVAL, "internal: adjoint steps out of order");
+      last_adj = a[i].a;
+      ++adj;
+    }
+  }
+  stats[0] = fwd_steps;   // steps advanced by the forward sweep (before the final step)
+  stats[1] = rec_steps;   // steps recomputed during the reverse sweep
+  stats[2] = stores;      // checkpoint stores
+  stats[3] = adj;         // adjoint steps (== nsteps)
+  stats[4] = maxslot;     // highest checkpoint slot used (<= nsnaps)
+  stats[5] = (int64_t)a.size();
+  return DG_OK;
+}
+
+int dg_adjoint_forward(dg_ctx* c, const double* U0, double* UT, double dt, int32_t nsteps, int32_t nsnaps,
+                       double* ckpt) {
+  if (!c || !U0 || !UT || !ckpt) return fail(DG_EINVAL, "NULL argument");
+  if (nsteps < 1 || nsnaps < 0) return fail(DG_EINVAL, "need nsteps >= 1 and nsnaps >= 0");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite and > 0");
+  const size_t n = (size_t)c->ncells * c->nl;
+  double* work = ckpt + (size_t)(nsnaps + 1) * n;
+  hipError_t e = hipMemcpyAsync(ckpt, U0, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "checkpoint copy");
+  auto a = rv_schedule(nsteps, nsnaps);
+  const size_t split = rv_split(a);
+  int rc = DG_OK;
+  for (size_t i = 0; i < split && rc == DG_OK; ++i) {
+    if (a[i].op == RV_RESTORE)
+      e = hipMemcpyAsync(work, ckpt + (size_t)a[i].a * n, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+    else if (a[i].op == RV_STORE)
+      e = hipMemcpyAsync(ckpt + (size_t)a[i].a * n, work, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+    else if (a[i].op == RV_ADVANCE)
+      for (int k = 0; k < a[i].a && rc == DG_OK; ++k) rc = rk3_step(c, c->stream, work, dt);
+    if (e != hipSuccess) return hip_fail(e, "checkpoint copy");
+  }
+  if (rc) return rc;
+  // the state at nsteps-1 is restored by the first reverse action; reach U_T from it
+  const int slot = a[split].a;
+  int k0 = 0;
+  for (size_t i = split; i < a.size() && a[i].op != RV_ADJOINT; ++i)
+    if (a[i].op == RV_ADVANCE) k0 += a[i].a;
+  if ((e = hipMemcpyAsync(UT, ckpt + (size_t)slot * n, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream)) !=
+      hipSuccess)
+    return hip_fail(e, "checkpoint copy");
+  for (int k = 0; k < k0 + 1 && rc == DG_OK; ++k) rc = rk3_step(c, c->stream, UT, dt);
+  return rc;
+}
+
+int dg_adjoint_backward(dg_ctx* c, double dt, int32_t nsteps, int32_t nsnaps, double* ckpt, double* lam) {
+  if (!c || !ckpt || !lam) return fail(DG_EINVAL, "NULL argument");
+  if (nsteps < 1 || nsnaps < 0) return fail(DG_EINVAL, "need nsteps >= 1 and nsnaps >= 0");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite and > 0");
+  int rc = ensure_adjoint(c);
+  if (rc) return rc;
+  const size_t n = (size_t)c->ncells * c->nl;
+  double* work = ckpt + (size_t)(nsnaps + 1) * n;
+  auto a = rv_schedule(nsteps, nsnaps);
+  hipError_t e = hipSuccess;
+  for (size_t i = rv_split(a); i < a.size() && rc == DG_OK; ++i) {
+    switch (a[i].op) {
+      case RV_RESTORE:
+        e = hipMemcpyAsync(work, ckpt + (size_t)a[i].a * n, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+        break;
+      case RV_STORE:
+        e = hipMemcpyAsync(ckpt + (size_t)a[i].a * n, work, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+        break;
+      case RV_ADVANCE:
+        for (int k = 0; k < a[i].a && rc == DG_OK; ++k) rc = rk3_step(c, c->stream, work, dt);
+        break;
+      case RV_ADJOINT:
+        // lam <- (d step / d U^k)^T lam, with U^k in the work slot
+        rc = rk3_adjoint(c, c->stream, work, dt, lam, lam);
+        break;
+    }
+    if (e != hipSuccess) return hip_fail(e, "checkpoint copy");
+  }
+  return rc;
 }
 
 int dg_set_stream(dg_ctx* c, void* stream) {

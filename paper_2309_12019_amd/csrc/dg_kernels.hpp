@@ -68,7 +68,7 @@ __host__ __device__ inline int tile_lds_doubles(int dim, int nl, int tx, int ty)
 }
 
 // x mod n for x in [-1, n + tile]: cheap for the common single wrap
-__device__ inline int wrap_index(int x, int n) {
+__host__ __device__ inline int wrap_index(int x, int n) {
   if (x < 0) return x + n;
   while (x >= n) x -= n;
   return x;
@@ -465,9 +465,11 @@ struct Cell {
 
 // Global cell index of slot (gx, gy) relative to the mesh, with periodic wrap;
 // false if the slot lies outside a non-periodic boundary.
+// (In 1D the row index is ignored.)
 template <int DIM>
-__device__ inline bool slot_cell(const StageArgs& A, int gx, int gy, size_t& cell) {
+__host__ __device__ inline bool slot_cell(const StageArgs& A, int gx, int gy, size_t& cell) {
   const int nx = A.nx, ny = DIM == 2 ? A.ny : 1;
+  if (DIM == 1) gy = 0;
   if ((unsigned)gx >= (unsigned)nx) {
     if (!A.per_x) return false;
     gx = wrap_index(gx, nx);
@@ -478,6 +480,56 @@ __device__ inline bool slot_cell(const StageArgs& A, int gx, int gy, size_t& cel
   }
   cell = (size_t)gy * nx + gx;
   return true;
+}
+
+// The slots thread t of the tile at (ix0, iy0) loads: its own cell's slot
+// (always) and at most one slot of the halo ring (no corners: the stencil has
+// face neighbours only).  gx, gy are mesh coordinates before wrapping; in 1D
+// the row is 0.
+template <int DIM, int TX, int TY>
+__host__ __device__ inline bool tile_slots(int t, int ix0, int iy0, int& sc, int& gx, int& gy, int& hslot, int& hgx,
+                                           int& hgy) {
+  using G = TileGeom<DIM, TX, TY>;
+  const int lx = DIM == 2 ? t % TX : t, ly = DIM == 2 ? t / TX : 0;
+  sc = DIM == 2 ? (ly + 1) * G::W + lx + 1 : lx + 1;
+  gx = ix0 + lx;
+  gy = DIM == 2 ? iy0 + ly : 0;
+  int sx, sy;
+  if constexpr (DIM == 1) {
+    if (t >= 2) return false;
+    sx = t == 0 ? 0 : TX + 1;
+    sy = 0;
+  } else {
+    if (t >= 2 * TX + 2 * TY) return false;
+    if (t < TX) {
+      sx = t + 1;
+      sy = 0;
+    } else if (t < 2 * TX) {
+      sx = t - TX + 1;
+      sy = TY + 1;
+    } else if (t < 2 * TX + TY) {
+      sx = 0;
+      sy = t - 2 * TX + 1;
+    } else {
+      sx = TX + 1;
+      sy = t - 2 * TX - TY + 1;
+    }
+  }
+  hslot = sy * G::W + sx;
+  hgx = ix0 - 1 + sx;
+  hgy = DIM == 2 ? iy0 - 1 + sy : 0;
+  return true;
+}
+
+// Mesh index of the face neighbour f (0: -x, 1: +x, 2: -y, 3: +y) of cell
+// (ix, iy), wrapping periodically; callers use it only where the neighbour
+// exists (periodic axis or interior face).
+__host__ __device__ inline size_t neighbour_cell(int ix, int iy, int f, int nx, int ny) {
+  if (f == 0) ix = ix == 0 ? nx - 1 : ix - 1;
+  if (f == 1) ix = ix == nx - 1 ? 0 : ix + 1;
+  if (f == 2) iy = iy == 0 ? ny - 1 : iy - 1;
+  if (f == 3) iy = iy == ny - 1 ? 0 : iy + 1;
+  return (size_t)iy * nx + ix;
 }
 
 // Load one slot (a cell's NL coefficients, or the constant exterior state
@@ -530,29 +582,13 @@ __device__ inline void stage_tile(const StageArgs& A, double* lds, int ix0, int 
 #pragma unroll
     for (int j = 0; j < NL; ++j) lds_un[j * G::NT + t] = un[j];
   }
-  // interior slots (cells past a ragged edge hold the wrapped or exterior state)
-  load_slot<DIM, NL, S>(A, lds, sc, ix, iy);
-  // halo ring: no corners (the stencil has face neighbours only)
-  if constexpr (DIM == 1) {
-    if (t < 2) load_slot<DIM, NL, S>(A, lds, t == 0 ? 0 : TX + 1, t == 0 ? ix0 - 1 : ix0 + TX, 0);
-  } else {
-    if (t < 2 * TX + 2 * TY) {
-      int sx, sy;
-      if (t < TX) {
-        sx = t + 1;
-        sy = 0;
-      } else if (t < 2 * TX) {
-        sx = t - TX + 1;
-        sy = TY + 1;
-      } else if (t < 2 * TX + TY) {
-        sx = 0;
-        sy = t - 2 * TX + 1;
-      } else {
-        sx = TX + 1;
-        sy = t - 2 * TX - TY + 1;
-      }
-      load_slot<DIM, NL, S>(A, lds, sy * W + sx, ix0 - 1 + sx, iy0 - 1 + sy);
-    }
+  // own slot (cells past a ragged edge hold the wrapped or exterior state) and
+  // one slot of the halo ring
+  {
+    int osc, ogx, ogy, hs, hgx, hgy;
+    const bool halo = tile_slots<DIM, TX, TY>(t, ix0, iy0, osc, ogx, ogy, hs, hgx, hgy);
+    load_slot<DIM, NL, S>(A, lds, osc, ogx, ogy);
+    if (halo) load_slot<DIM, NL, S>(A, lds, hs, hgx, hgy);
   }
   __syncthreads();
   if (active) {

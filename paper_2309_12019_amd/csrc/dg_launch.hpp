@@ -1,11 +1,12 @@
 // Interface between the C-ABI layer and the per-(dim, p) kernel objects.
 #pragma once
 
-#include "dg_kernels.hpp"
+#include "dg_adjoint.hpp"
 
 namespace dgk {
 
-enum LaunchKind { LAUNCH_STAGE = 0, LAUNCH_PROJECT = 1, LAUNCH_LAMBDA = 2, LAUNCH_BATCH = 3 };
+enum LaunchKind { LAUNCH_STAGE = 0, LAUNCH_PROJECT = 1, LAUNCH_LAMBDA = 2, LAUNCH_BATCH = 3,
+                  LAUNCH_ADJ_SENSOR = 4, LAUNCH_ADJ_GRAD = 5 };
 
 struct LaunchReq {
   int kind;
@@ -16,6 +17,7 @@ struct LaunchReq {
   long long ncells;
   hipStream_t stream;
   BatchStageArgs batch;  // LAUNCH_BATCH (tile shape in args.tx/args.ty, grid in ncells)
+  AdjArgs adj;           // LAUNCH_ADJ_* (tile shape in adj.s.tx/adj.s.ty)
 };
 
 typedef hipError_t (*LaunchFn)(const LaunchReq*);

@@ -76,6 +76,48 @@ hipError_t launch_batch_f(const LaunchReq* r) {
   }
 }
 
+template <int FLUX, int MODE, int TX, int TY>
+hipError_t launch_adj_tile(const LaunchReq* r) {
+  constexpr int NL = DGK_DIM == 1 ? DGK_P + 1 : (DGK_P + 1) * (DGK_P + 1);
+  constexpr int S = TileGeom<DGK_DIM, TX, TY>::S;
+  const AdjArgs& Ad = r->adj;
+  dim3 grid((Ad.s.nx + TX - 1) / TX, DGK_DIM == 2 ? (Ad.s.ny + TY - 1) / TY : 1);
+  dim3 block(DGK_DIM == 2 ? TX * TY : TX);
+  const bool sens = r->kind == LAUNCH_ADJ_SENSOR;
+  const size_t lds = sizeof(double) * (size_t)NL * S * (sens ? 1 : 2);
+  const void* k = sens ? reinterpret_cast<const void*>(adj_sensor_kernel<DGK_DIM, DGK_P, FLUX, MODE, TX, TY>)
+                       : reinterpret_cast<const void*>(adj_grad_kernel<DGK_DIM, DGK_P, FLUX, MODE, TX, TY>);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  if (sens)
+    hipLaunchKernelGGL((adj_sensor_kernel<DGK_DIM, DGK_P, FLUX, MODE, TX, TY>), grid, block, lds, r->stream, Ad);
+  else
+    hipLaunchKernelGGL((adj_grad_kernel<DGK_DIM, DGK_P, FLUX, MODE, TX, TY>), grid, block, lds, r->stream, Ad);
+  return hipGetLastError();
+}
+
+template <int FLUX, int MODE>
+hipError_t launch_adj_fm(const LaunchReq* r) {
+  if constexpr (DGK_DIM == 1) {
+    if (r->adj.s.tx == 64) return launch_adj_tile<FLUX, MODE, 64, 1>(r);
+    return launch_adj_tile<FLUX, MODE, 256, 1>(r);
+  } else {
+    if (r->adj.s.tx == 8) return launch_adj_tile<FLUX, MODE, 8, 8>(r);
+    return launch_adj_tile<FLUX, MODE, 16, 16>(r);
+  }
+}
+
+template <int FLUX>
+hipError_t launch_adj_f(const LaunchReq* r) {
+  switch (r->mode) {
+    case MODE_DG: return launch_adj_fm<FLUX, MODE_DG>(r);
+    case MODE_LO: return launch_adj_fm<FLUX, MODE_LO>(r);
+    default: return launch_adj_fm<FLUX, MODE_WENO>(r);
+  }
+}
+
 template <int FLUX>
 hipError_t launch_stage_f(int mode, const StageArgs& A, hipStream_t s) {
   switch (mode) {
@@ -103,6 +145,11 @@ extern "C" hipError_t DGK_CAT(dgk_launch, DGK_DIM, DGK_P)(const LaunchReq* r) {
     case LAUNCH_BATCH: {
       if (r->flux == FLUX_LINADV) return launch_batch_f<FLUX_LINADV>(r);
       return launch_batch_f<FLUX_BURGERS>(r);
+    }
+    case LAUNCH_ADJ_SENSOR:
+    case LAUNCH_ADJ_GRAD: {
+      if (r->flux == FLUX_LINADV) return launch_adj_f<FLUX_LINADV>(r);
+      return launch_adj_f<FLUX_BURGERS>(r);
     }
     case LAUNCH_PROJECT: {
       const long long n = r->ncells;

@@ -67,6 +67,14 @@ EXPORTS = {
     "dg_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "dg_last_error": (ctypes.c_char_p, []),
     "dg_validate_desc": (ctypes.c_int, [ctypes.POINTER(MeshDesc)]),
+    "dg_rhs_vjp": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "dg_step_adjoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
+                                       ctypes.c_void_p]),
+    "dg_adjoint_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                          ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]),
+    "dg_adjoint_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.c_void_p, ctypes.c_void_p]),
+    "dg_revolve_stats": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]),
     "dg_batch_create": (ctypes.c_int, [ctypes.POINTER(MeshDesc), ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
     "dg_batch_destroy": (None, [ctypes.c_void_p]),
     "dg_batch_layout": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
@@ -212,6 +220,36 @@ class DG:
             _check(rc)
         return cnt.value
 
+    def rhs_vjp(self, U: torch.Tensor, v: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        out = self.empty() if out is None else out
+        n = self.ncells * self.nloc
+        _check(self.lib.dg_rhs_vjp(self.h, _ptr(U, n, "U"), _ptr(v, n, "v"), _ptr(out, n, "out")))
+        return out
+
+    def step_adjoint(self, Un: torch.Tensor, dt: float, lam_out: torch.Tensor,
+                     lam_in: Optional[torch.Tensor] = None) -> torch.Tensor:
+        lam_in = self.empty() if lam_in is None else lam_in
+        n = self.ncells * self.nloc
+        _check(self.lib.dg_step_adjoint(self.h, _ptr(Un, n, "Un"), float(dt), _ptr(lam_out, n, "lam_out"),
+                                        _ptr(lam_in, n, "lam_in")))
+        return lam_in
+
+    def checkpoints(self, nsnaps: int) -> torch.Tensor:
+        return torch.empty((nsnaps + 2) * self.ncells * self.nloc, dtype=torch.float64, device=self.device)
+
+    def adjoint_forward(self, U0, dt, nsteps, nsnaps, ckpt, UT=None) -> torch.Tensor:
+        UT = self.empty() if UT is None else UT
+        n = self.ncells * self.nloc
+        _check(self.lib.dg_adjoint_forward(self.h, _ptr(U0, n, "U0"), _ptr(UT, n, "UT"), float(dt), int(nsteps),
+                                           int(nsnaps), _ptr(ckpt, (nsnaps + 2) * n, "ckpt")))
+        return UT
+
+    def adjoint_backward(self, dt, nsteps, nsnaps, ckpt, lam) -> torch.Tensor:
+        n = self.ncells * self.nloc
+        _check(self.lib.dg_adjoint_backward(self.h, float(dt), int(nsteps), int(nsnaps),
+                                            _ptr(ckpt, (nsnaps + 2) * n, "ckpt"), _ptr(lam, n, "lam")))
+        return lam
+
     def set_tile(self, tx: int, ty: int = 1) -> None:
         _check(self.lib.dg_set_tile(self.h, int(tx), int(ty)))
 
@@ -315,3 +353,36 @@ class Batch:
 
     def set_branches(self, n: int) -> None:
         _check(self.lib.dg_batch_set_branches(self.h, int(n)))
+
+
+def revolve_stats(nsteps: int, nsnaps: int) -> dict:
+    """Host-only statistics of the checkpoint schedule (no GPU needed)."""
+    lib = load()
+    st = np.zeros(6, dtype=np.int64)
+    _check(lib.dg_revolve_stats(int(nsteps), int(nsnaps), st.ctypes.data_as(ctypes.c_void_p)))
+    keys = ("forward_steps", "recomputed_steps", "stores", "adjoint_steps", "max_slot", "actions")
+    return dict(zip(keys, st.tolist()))
+
+
+class DGRunFunction(torch.autograd.Function):
+    """U^N = run(U^0) as a differentiable op: the forward stores checkpoints,
+    the backward runs the hand-written discrete adjoint over them."""
+
+    @staticmethod
+    def forward(ctx, U0, dg: "DG", dt: float, nsteps: int, nsnaps: int):
+        ckpt = dg.checkpoints(nsnaps)
+        UT = dg.adjoint_forward(U0.detach().contiguous(), dt, nsteps, nsnaps, ckpt)
+        ctx.dg, ctx.dt, ctx.nsteps, ctx.nsnaps, ctx.ckpt = dg, dt, nsteps, nsnaps, ckpt
+        return UT
+
+    @staticmethod
+    def backward(ctx, gUT):
+        lam = gUT.detach().clone().contiguous()
+        ctx.dg.adjoint_backward(ctx.dt, ctx.nsteps, ctx.nsnaps, ctx.ckpt, lam)
+        ctx.ckpt = None
+        return lam, None, None, None, None
+
+
+def run_differentiable(dg: "DG", U0: torch.Tensor, dt: float, nsteps: int, nsnaps: Optional[int] = None):
+    """nsteps SSP-RK3 steps of U0 with gradients through torch.autograd."""
+    return DGRunFunction.apply(U0, dg, dt, nsteps, nsteps if nsnaps is None else nsnaps)

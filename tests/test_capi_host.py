@@ -78,3 +78,28 @@ def test_null_arguments_rejected(lib):
     assert lib.dg_project_ic(None, None, None) == -1
     assert lib.dg_sizes(None, None, None, None) == -1
     lib.dg_destroy(None)
+
+
+@pytest.mark.parametrize("n,s", [(1, 0), (10, 0), (10, 2), (10, 9), (37, 3), (400, 20), (400, 400), (64, 6)])
+def test_checkpoint_schedule_properties(lib, n, s):
+    """Binomial checkpointing plan (host only): every step is reversed once, in
+    order (checked inside the planner), no more than s slots are used, and
+    enough slots remove all recomputation."""
+    from paper_2309_12019_amd import dgweno
+    st = dgweno.revolve_stats(n, s)
+    assert st["adjoint_steps"] == n
+    assert st["max_slot"] <= s
+    assert st["forward_steps"] == (n - 1 if s > 0 else 0)
+    if s >= n - 1:
+        assert st["recomputed_steps"] == 0
+    if s == 0:
+        assert st["recomputed_steps"] == n * (n - 1) // 2
+
+
+def test_checkpoint_recomputation_decreases_with_slots(lib):
+    from paper_2309_12019_amd import dgweno
+    rec = [dgweno.revolve_stats(200, s)["recomputed_steps"] for s in (1, 2, 4, 8, 16, 199)]
+    assert all(a >= b for a, b in zip(rec, rec[1:])) and rec[-1] == 0
+    # binomial bound: with s slots and t sweeps, C(s+t, s) steps are reversible
+    # with at most t recomputations of each step
+    assert dgweno.revolve_stats(200, 8)["recomputed_steps"] <= 3 * 200

@@ -1,0 +1,188 @@
+"""Discrete adjoint on the GPU: J^T v of the operator, the adjoint of one
+SSP-RK3 step and the checkpointed run adjoint, against the oracle's reverse
+mode and against finite differences of the GPU forward map."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from helpers import oracle_for, oracle_initial
+from paper_2309_12019_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _dg():
+    from paper_2309_12019_amd import dgweno
+    return dgweno
+
+
+def relinf(a, b):
+    return float((a - b).abs().max() / b.abs().max().clamp_min(1e-300))
+
+
+def _mesh(kind, p, mode):
+    if kind == "adv1d":
+        w = inputs.adv1d(300, p, mode=mode)
+    elif kind == "burgers1d":
+        w = inputs.burgers1d(300, p, mode=mode)
+    elif kind == "rot2d":
+        w = inputs.rot2d(40, p, mode=mode, ny=36)
+        w.cy = 0.45
+    else:
+        w = inputs.burgers2d(40, p, mode=mode, ny=36, steps=1)
+    return w
+
+
+def _state(w, O, seed):
+    U = oracle_initial(w, O)
+    rng = np.random.default_rng(seed)
+    return U + 0.01 * torch.from_numpy(rng.standard_normal(U.shape)) * U.abs().max()
+
+
+@pytest.mark.parametrize("kind", ["adv1d", "burgers1d", "rot2d", "burgers2d"])
+@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_rhs_vjp_matches_oracle_reverse_mode(kind, p, mode):
+    _note(f"[vjp] {kind} p={p} mode={mode}")
+    w = _mesh(kind, p, mode)
+    O = oracle_for(w)
+    U = _state(w, O, 5)
+    v = torch.from_numpy(np.random.default_rng(6).standard_normal(U.shape))
+    Ur = U.clone().requires_grad_(True)
+    (ref,) = torch.autograd.grad(O.rhs(Ur), Ur, v)
+    g = _dg().DG.from_workload(w)
+    got = g.rhs_vjp(U.cuda().contiguous(), v.cuda().contiguous())
+    torch.cuda.synchronize()
+    assert relinf(got.cpu(), ref) <= 1e-11
+
+
+@pytest.mark.parametrize("kind,p", [("burgers2d", 4), ("rot2d", 4), ("adv1d", 4)])
+def test_rhs_vjp_degree4(kind, p):
+    _note(f"[vjp] {kind} p={p}")
+    w = _mesh(kind, p, 2)
+    O = oracle_for(w)
+    U = _state(w, O, 8)
+    v = torch.from_numpy(np.random.default_rng(9).standard_normal(U.shape))
+    Ur = U.clone().requires_grad_(True)
+    (ref,) = torch.autograd.grad(O.rhs(Ur), Ur, v)
+    got = _dg().DG.from_workload(w).rhs_vjp(U.cuda().contiguous(), v.cuda().contiguous())
+    torch.cuda.synchronize()
+    assert relinf(got.cpu(), ref) <= 1e-10
+
+
+@pytest.mark.parametrize("kind", ["burgers2d", "rot2d", "burgers1d"])
+def test_vjp_against_finite_differences_of_the_gpu_operator(kind):
+    """<w, (L(U + d v) - L(U - d v)) / 2d> = <J^T w, v> (dot-product test with
+    the tangent from central differences of the GPU operator).  The step is
+    small (2e-7 along a unit direction) so that no max/min switch of the LLF
+    wave speed or of lambda_e falls between the two evaluations; the bar is
+    the 1e-6 relative agreement asked of the adjoint."""
+    _note(f"[vjp fd] {kind}")
+    w = _mesh(kind, 2, 2)
+    O = oracle_for(w)
+    g = _dg().DG.from_workload(w)
+    rng = np.random.default_rng(11)
+    U = _state(w, O, 12).cuda().contiguous()
+    ws = torch.from_numpy(rng.standard_normal(U.shape)).cuda()
+    JTw = g.rhs_vjp(U, ws.contiguous())
+    for _ in range(3):
+        v = torch.from_numpy(rng.standard_normal(U.shape)).cuda()
+        v /= v.norm()
+        fd = []
+        for d in (2e-7, 1e-7):
+            Lp = g.rhs((U + d * v).contiguous())
+            Lm = g.rhs((U - d * v).contiguous())
+            fd.append(float((ws * (Lp - Lm)).sum()) / (2 * d))
+        fdv = (4 * fd[1] - fd[0]) / 3
+        ad = float((JTw * v).sum())
+        assert abs(fdv - ad) <= 1e-6 * abs(ad)
+
+
+@pytest.mark.parametrize("kind,p,mode", [("burgers2d", 2, 2), ("rot2d", 3, 2), ("burgers1d", 3, 2),
+                                         ("adv1d", 2, 1), ("burgers2d", 1, 0)])
+def test_step_adjoint_matches_oracle(kind, p, mode):
+    _note(f"[step adjoint] {kind} p={p} mode={mode}")
+    w = _mesh(kind, p, mode)
+    O = oracle_for(w)
+    U = _state(w, O, 2)
+    lam = torch.from_numpy(np.random.default_rng(3).standard_normal(U.shape))
+    ref = O.step_vjp(U, w.dt(), lam)
+    g = _dg().DG.from_workload(w)
+    got = g.step_adjoint(U.cuda().contiguous(), w.dt(), lam.cuda().contiguous())
+    torch.cuda.synchronize()
+    assert relinf(got.cpu(), ref) <= 1e-11
+
+
+def test_checkpointed_adjoint_independent_of_snapshots_and_matches_oracle():
+    """2D Burgers, 24 x 24 P2, 20 steps: the gradient of J = int_W u^2 with
+    respect to U^0 is the same for every checkpoint budget (bitwise) and
+    matches the oracle's reverse mode."""
+    _note("[revolve] burgers2d 24x24 P2 20 steps")
+    w = inputs.burgers2d(24, 2, steps=20)
+    O = oracle_for(w)
+    U0 = oracle_initial(w, O)
+    dgweno = _dg()
+    g = dgweno.DG.from_workload(w)
+    inside = ((O.xc > 0.25) & (O.xc < 0.75) & (O.yc > 0.25) & (O.yc < 0.75)).to(torch.float64)
+    Jfun = lambda U: O.window_functional(U, (0.25, 0.75), (0.25, 0.75))
+    ref = O.run_grad(U0, w.dt(), 20, Jfun)
+    Md = torch.diag(O.M)
+    grads = []
+    for nsnaps in (20, 4, 1, 0):
+        ck = g.checkpoints(nsnaps)
+        UT = g.adjoint_forward(U0.cuda().contiguous(), w.dt(), 20, nsnaps, ck)
+        lam = (2 * UT * Md.cuda()[None, :] * inside.cuda()[:, None]).contiguous()
+        g.adjoint_backward(w.dt(), 20, nsnaps, ck, lam)
+        torch.cuda.synchronize()
+        grads.append(lam.cpu())
+        assert relinf(UT.cpu(), O.run(U0, w.dt(), 20)) <= 1e-11
+    for gr in grads[1:]:
+        assert torch.equal(gr, grads[0])
+    assert relinf(grads[0], ref) <= 1e-10
+
+
+def test_autograd_function_and_finite_differences():
+    """The torch.autograd wrapper gives the checkpointed adjoint's gradient;
+    directional derivatives agree with central differences of the GPU run."""
+    _note("[autograd] burgers2d 32x32 P2 30 steps")
+    w = inputs.burgers2d(32, 2, steps=30)
+    dgweno = _dg()
+    g = dgweno.DG.from_workload(w)
+    U0 = g.initial_state(w)
+    dev = U0.device
+    xc = (torch.arange(32, device=dev, dtype=torch.float64) + 0.5) / 32
+    inside = (((xc > 0.25) & (xc < 0.75))[None, :] & ((xc > 0.25) & (xc < 0.75))[:, None]).reshape(-1)
+    mh = torch.tensor([4 / ((2 * a + 1) * (2 * b + 1)) for b in range(3) for a in range(3)],
+                      dtype=torch.float64, device=dev) * (0.5 / 32) ** 2
+
+    def J(U):
+        return ((U * U * mh[None, :]).sum(1) * inside).sum()
+
+    x = U0.clone().requires_grad_(True)
+    UT = dgweno.run_differentiable(g, x, w.dt(), 30, nsnaps=6)
+    Jv = J(UT)
+    Jv.backward()
+    grad = x.grad.clone()
+    rng = np.random.default_rng(1)
+    for _ in range(4):
+        d = torch.from_numpy(rng.standard_normal(U0.shape)).to(dev)
+        d /= d.norm()
+        h = 1e-4 * float(U0.abs().max())
+
+        def Jat(s):
+            U = (U0 + s * d).contiguous()
+            g.run(U, w.dt(), 30)
+            return float(J(U))
+
+        fd1 = (Jat(h) - Jat(-h)) / (2 * h)
+        fd2 = (Jat(h / 2) - Jat(-h / 2)) / h
+        fd = (4 * fd2 - fd1) / 3
+        ad = float((grad * d).sum())
+        assert abs(fd - ad) <= 1e-6 * abs(ad)
