@@ -147,6 +147,102 @@ def bench_batch(steps=100, seed=0, count=512):
             "tuned_schedule": [B.schedule(c) for c in range(B.num_classes())]}
 
 
+def bench_adjoint(n=512, steps=400, ndir=32, nsnaps=None, seed=0):
+    """Gradient of J = int_W u(T)^2 dx, W = [0.25, 0.75]^2, with respect to all
+    initial DOFs of 2D Burgers (n x n, P2, seeded Fourier data, `steps` steps)
+    by the checkpointed discrete adjoint; cost relative to the plain forward
+    run; central differences (Richardson over delta, delta/2) of the GPU
+    forward run along `ndir` random unit directions at two step sizes."""
+    import numpy as np
+    import torch
+    from paper_2309_12019_amd import dgweno, inputs
+    w = inputs.burgers2d(n, 2, seed=seed, steps=steps)
+    g = dgweno.DG.from_workload(w)
+    U0 = g.initial_state(w)
+    dt = w.dt()
+    dev = U0.device
+    xc = (torch.arange(n, device=dev, dtype=torch.float64) + 0.5) / n
+    win = (xc > 0.25) & (xc < 0.75)
+    inside = (win[None, :] & win[:, None]).reshape(-1).to(torch.float64)
+    mh = torch.tensor([4.0 / ((2 * a + 1) * (2 * b + 1)) for b in range(3) for a in range(3)],
+                      dtype=torch.float64, device=dev) * (0.5 / n) ** 2
+
+    def J(U):
+        return ((U * U * mh[None, :]).sum(1) * inside).sum()
+
+    st = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        out = fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        return out, e0.elapsed_time(e1) / 1e3
+
+    # plain forward (graph-captured run), warmed
+    U = U0.clone()
+    g.run(U, dt, steps)
+    U = U0.clone()
+    _, t_fwd = timed(lambda: g.run(U, dt, steps))
+    res = {"workload": f"2D Burgers {n}x{n} P2 WENO, seeded Fourier data, {steps} SSP-RK3 steps, "
+                       f"J = int over [0.25,0.75]^2 of u(T)^2", "dofs": w.ndof, "forward_s": t_fwd}
+    main = steps if nsnaps is None else nsnaps
+    for ns, keep in ((main, True), (main, False), (20, False)):
+        ck = g.checkpoints(ns)
+        stg = g.stage_checkpoints(steps) if keep else None
+        UT, t_f = timed(lambda: g.adjoint_forward(U0, dt, steps, ns, ck, stages=stg))
+        lam = (2 * UT * mh[None, :] * inside[:, None]).contiguous()
+        _, t_b = timed(lambda: g.adjoint_backward(dt, steps, ns, ck, lam, stages=stg))
+        del ck, stg
+        torch.cuda.empty_cache()
+        st_ = dgweno.revolve_stats(steps, ns)
+        key = f"snapshots_{ns}" + ("_with_stage_states" if keep else "")
+        res[key] = {"forward_with_checkpoints_s": t_f, "backward_s": t_b,
+                    "cost_vs_forward": (t_f + t_b) / t_fwd,
+                    "recomputed_steps": st_["recomputed_steps"],
+                    "checkpoint_bytes": (ns + 2 + (2 * steps if keep else 0)) * w.ndof * 8}
+        if keep:
+            grad = lam.clone()
+            JT = float(J(UT))
+            res["cost_vs_forward"] = (t_f + t_b) / t_fwd
+            res["schedule"] = key
+    # finite differences of the forward map
+    rng = np.random.default_rng(1)
+    umax = float(U0.abs().max())
+
+    def dJ(d, s):
+        """J(U(s)) - J(U(-s)) summed as (U+ - U-)(U+ + U-): the two values of
+        J agree to ~1e-9 of J, below the rounding of each sum on its own."""
+        Up = (U0 + s * d).contiguous()
+        Um = (U0 - s * d).contiguous()
+        g.run(Up, dt, steps)
+        g.run(Um, dt, steps)
+        return float((((Up - Um) * (Up + Um) * mh[None, :]).sum(1) * inside).sum())
+
+    rows = []
+    for k in range(ndir):
+        d = torch.from_numpy(rng.standard_normal(U0.shape)).to(dev)
+        d /= d.norm()
+        ad = float((grad * d).sum())
+        row = {"ad": ad}
+        for tag, delta in (("1e-4", 1e-4 * umax), ("1e-6", 1e-6 * umax), ("1e-8", 1e-8 * umax)):
+            fd1 = dJ(d, delta) / (2 * delta)
+            fd2 = dJ(d, delta / 2) / delta
+            fd = (4 * fd2 - fd1) / 3
+            row[tag] = abs(fd - ad) / abs(ad)
+        rows.append(row)
+    for tag in ("1e-4", "1e-6", "1e-8"):
+        errs = [r[tag] for r in rows]
+        res[f"fd_delta_{tag}_umax"] = {"directions": ndir, "max_rel_err": max(errs),
+                                       "median_rel_err": float(np.median(errs)),
+                                       "within_1e-6": int(sum(e <= 1e-6 for e in errs))}
+    res["J"] = JT
+    return res
+
+
 def traffic_for(wname):
     """HBM bytes per stage launch from the committed rocprofv3 counter summary,
     if one exists for this workload (else None)."""
@@ -171,6 +267,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=100)
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-n", type=int, default=512)
+    ap.add_argument("--adjoint-steps", type=int, default=400)
+    ap.add_argument("--adjoint-dirs", type=int, default=32)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -228,6 +328,8 @@ def main():
         line["extra"] = extra
     if not args.no_batch:
         line["batched"] = bench_batch(args.batch_steps)
+    if not args.no_adjoint:
+        line["adjoint"] = bench_adjoint(args.adjoint_n, args.adjoint_steps, args.adjoint_dirs)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(line), flush=True)

@@ -172,13 +172,18 @@ int dg_step_adjoint(dg_ctx* ctx, const double* Un, double dt, const double* lam_
  * each reverse sub-range advances to a checkpoint chosen so the remainder
  * can be reversed with one slot fewer within the same number of sweeps).
  * ckpt: caller-owned device buffer of (nsnaps + 2) * n_cells * n_loc doubles
- * (slot 0 holds U^0, the last slot is working space); it must not change
- * between the two calls.
+ * (slot 0 holds U^0, the last slot is working space).  stages: NULL, or a
+ * device buffer of 2 * nsteps * n_cells * n_loc doubles that receives the RK
+ * stage states U^(1), U^(2) of every step the forward sweep advances (with
+ * nsnaps >= nsteps - 1 that is every step); the backward then skips their
+ * recomputation.  ckpt and stages must not change between the two calls, and
+ * both calls take the same stages argument.
  * dg_adjoint_forward: U^0 -> U^N (written to UT), storing checkpoints.
  * dg_adjoint_backward: lam holds dJ/dU^N on entry and dJ/dU^0 on exit. */
 int dg_adjoint_forward(dg_ctx* ctx, const double* U0, double* UT, double dt, int32_t nsteps, int32_t nsnaps,
-                       double* ckpt);
-int dg_adjoint_backward(dg_ctx* ctx, double dt, int32_t nsteps, int32_t nsnaps, double* ckpt, double* lam);
+                       double* ckpt, double* stages);
+int dg_adjoint_backward(dg_ctx* ctx, double dt, int32_t nsteps, int32_t nsnaps, double* ckpt,
+                        const double* stages, double* lam);
 
 /* Host-only statistics of the checkpoint schedule: stats[6] = {forward-sweep
  * steps, recomputed steps, stores, adjoint steps, highest slot, actions}. */

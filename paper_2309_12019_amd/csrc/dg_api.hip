@@ -126,12 +126,15 @@ int stage(dg_ctx* c, hipStream_t st, const double* uin, const double* un, double
   return DG_OK;
 }
 
-// eq. (ssp): U1 = U + dt L(U); U2 = 3/4 U + 1/4 (U1 + dt L(U1)); U = 1/3 U + 2/3 (U2 + dt L(U2))
-int rk3_step(dg_ctx* c, hipStream_t st, double* U, double dt) {
+// eq. (ssp): U1 = U + dt L(U); U2 = 3/4 U + 1/4 (U1 + dt L(U1)); U = 1/3 U + 2/3 (U2 + dt L(U2)).
+// The stage states go to U1, U2 (default: the context's buffers).
+int rk3_step(dg_ctx* c, hipStream_t st, double* U, double dt, double* U1 = nullptr, double* U2 = nullptr) {
   int rc;
-  if ((rc = stage(c, st, U, U, c->U1, nullptr, 0.0, 1.0, dt, 0))) return rc;
-  if ((rc = stage(c, st, c->U1, U, c->U2, nullptr, 0.75, 0.25, dt, 0))) return rc;
-  return stage(c, st, c->U2, U, U, nullptr, 1.0 / 3.0, 2.0 / 3.0, dt, 0);
+  U1 = U1 ? U1 : c->U1;
+  U2 = U2 ? U2 : c->U2;
+  if ((rc = stage(c, st, U, U, U1, nullptr, 0.0, 1.0, dt, 0))) return rc;
+  if ((rc = stage(c, st, U1, U, U2, nullptr, 0.75, 0.25, dt, 0))) return rc;
+  return stage(c, st, U2, U, U, nullptr, 1.0 / 3.0, 2.0 / 3.0, dt, 0);
 }
 
 int validate(const dg_mesh_desc* d) {
@@ -232,16 +235,22 @@ int adjoint_stage(dg_ctx* c, hipStream_t st, const double* U, const double* v, d
   return DG_OK;
 }
 
-// lam_in = (d step(Un) / d Un)^T lam_out for eq. (ssp); recomputes U^(1), U^(2)
-int rk3_adjoint(dg_ctx* c, hipStream_t st, const double* Un, double dt, const double* lam_out, double* lam_in) {
+// lam_in = (d step(Un) / d Un)^T lam_out for eq. (ssp).  The stage states
+// U^(1), U^(2) are recomputed from Un unless given (S1, S2).
+int rk3_adjoint(dg_ctx* c, hipStream_t st, const double* Un, double dt, const double* lam_out, double* lam_in,
+                const double* S1 = nullptr, const double* S2 = nullptr) {
   int rc;
-  if ((rc = stage(c, st, Un, Un, c->U1, nullptr, 0.0, 1.0, dt, 0))) return rc;
-  if ((rc = stage(c, st, c->U1, Un, c->U2, nullptr, 0.75, 0.25, dt, 0))) return rc;
+  if (!S1 || !S2) {
+    if ((rc = stage(c, st, Un, Un, c->U1, nullptr, 0.0, 1.0, dt, 0))) return rc;
+    if ((rc = stage(c, st, c->U1, Un, c->U2, nullptr, 0.75, 0.25, dt, 0))) return rc;
+    S1 = c->U1;
+    S2 = c->U2;
+  }
   const double a2 = 0.75, b2 = 0.25, a3 = 1.0 / 3.0, b3 = 2.0 / 3.0;
   // stage 3: U = a3 Un + b3 (U2 + dt L(U2))  ->  lam_U2 = b3 mu + b3 dt J(U2)^T mu
-  if ((rc = adjoint_stage(c, st, c->U2, lam_out, c->A1, b3, b3 * dt, nullptr, 0, nullptr, 0))) return rc;
+  if ((rc = adjoint_stage(c, st, S2, lam_out, c->A1, b3, b3 * dt, nullptr, 0, nullptr, 0))) return rc;
   // stage 2: U2 = a2 Un + b2 (U1 + dt L(U1))
-  if ((rc = adjoint_stage(c, st, c->U1, c->A1, c->A2, b2, b2 * dt, nullptr, 0, nullptr, 0))) return rc;
+  if ((rc = adjoint_stage(c, st, S1, c->A1, c->A2, b2, b2 * dt, nullptr, 0, nullptr, 0))) return rc;
   // stage 1: U1 = Un + dt L(Un); lam_n = lam_U1 + dt J(Un)^T lam_U1 + a2 lam_U2 + a3 mu
   return adjoint_stage(c, st, Un, c->A2, lam_in, 1.0, dt, c->A1, a2, lam_out, a3);
 }
@@ -626,8 +635,26 @@ int dg_revolve_stats(int32_t nsteps, int32_t nsnaps, int64_t* stats) {
   return DG_OK;
 }
 
+// Steps whose stage states the forward sweep records: every step advanced
+// before the first reverse action (the step index of each slot is tracked
+// through the stores and restores), and the final step to U^N.
+std::vector<char> rv_stage_steps(const std::vector<RvAction>& a, int nsteps, int nsnaps) {
+  std::vector<char> have(nsteps, 0);
+  std::vector<int> slot_step(nsnaps + 1, 0);
+  const size_t split = rv_split(a);
+  int cur = 0;
+  for (size_t i = 0; i < split; ++i) {
+    if (a[i].op == RV_RESTORE) cur = slot_step[a[i].a];
+    if (a[i].op == RV_STORE) slot_step[a[i].a] = cur;
+    if (a[i].op == RV_ADVANCE)
+      for (int k = 0; k < a[i].a; ++k) have[cur++] = 1;
+  }
+  have[nsteps - 1] = 1;
+  return have;
+}
+
 int dg_adjoint_forward(dg_ctx* c, const double* U0, double* UT, double dt, int32_t nsteps, int32_t nsnaps,
-                       double* ckpt) {
+                       double* ckpt, double* stages) {
   if (!c || !U0 || !UT || !ckpt) return fail(DG_EINVAL, "NULL argument");
   if (nsteps < 1 || nsnaps < 0) return fail(DG_EINVAL, "need nsteps >= 1 and nsnaps >= 0");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite and > 0");
@@ -637,14 +664,21 @@ int dg_adjoint_forward(dg_ctx* c, const double* U0, double* UT, double dt, int32
   if (e != hipSuccess) return hip_fail(e, "checkpoint copy");
   auto a = rv_schedule(nsteps, nsnaps);
   const size_t split = rv_split(a);
+  auto S1 = [&](int k) { return stages ? stages + (size_t)(2 * k) * n : nullptr; };
+  auto S2 = [&](int k) { return stages ? stages + (size_t)(2 * k + 1) * n : nullptr; };
   int rc = DG_OK;
+  int cur = 0;  // step index of the working state
+  std::vector<int> slot_step(nsnaps + 1, 0);
   for (size_t i = 0; i < split && rc == DG_OK; ++i) {
-    if (a[i].op == RV_RESTORE)
+    if (a[i].op == RV_RESTORE) {
       e = hipMemcpyAsync(work, ckpt + (size_t)a[i].a * n, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
-    else if (a[i].op == RV_STORE)
+      cur = slot_step[a[i].a];
+    } else if (a[i].op == RV_STORE) {
       e = hipMemcpyAsync(ckpt + (size_t)a[i].a * n, work, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
-    else if (a[i].op == RV_ADVANCE)
-      for (int k = 0; k < a[i].a && rc == DG_OK; ++k) rc = rk3_step(c, c->stream, work, dt);
+      slot_step[a[i].a] = cur;
+    } else if (a[i].op == RV_ADVANCE) {
+      for (int k = 0; k < a[i].a && rc == DG_OK; ++k, ++cur) rc = rk3_step(c, c->stream, work, dt, S1(cur), S2(cur));
+    }
     if (e != hipSuccess) return hip_fail(e, "checkpoint copy");
   }
   if (rc) return rc;
@@ -656,11 +690,15 @@ int dg_adjoint_forward(dg_ctx* c, const double* U0, double* UT, double dt, int32
   if ((e = hipMemcpyAsync(UT, ckpt + (size_t)slot * n, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream)) !=
       hipSuccess)
     return hip_fail(e, "checkpoint copy");
-  for (int k = 0; k < k0 + 1 && rc == DG_OK; ++k) rc = rk3_step(c, c->stream, UT, dt);
+  for (int k = 0; k < k0 + 1 && rc == DG_OK; ++k) {
+    const int step = nsteps - 1 - k0 + k;
+    rc = rk3_step(c, c->stream, UT, dt, k == k0 ? S1(step) : nullptr, k == k0 ? S2(step) : nullptr);
+  }
   return rc;
 }
 
-int dg_adjoint_backward(dg_ctx* c, double dt, int32_t nsteps, int32_t nsnaps, double* ckpt, double* lam) {
+int dg_adjoint_backward(dg_ctx* c, double dt, int32_t nsteps, int32_t nsnaps, double* ckpt, const double* stages,
+                        double* lam) {
   if (!c || !ckpt || !lam) return fail(DG_EINVAL, "NULL argument");
   if (nsteps < 1 || nsnaps < 0) return fail(DG_EINVAL, "need nsteps >= 1 and nsnaps >= 0");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite and > 0");
@@ -669,6 +707,7 @@ int dg_adjoint_backward(dg_ctx* c, double dt, int32_t nsteps, int32_t nsnaps, do
   const size_t n = (size_t)c->ncells * c->nl;
   double* work = ckpt + (size_t)(nsnaps + 1) * n;
   auto a = rv_schedule(nsteps, nsnaps);
+  std::vector<char> have = stages ? rv_stage_steps(a, nsteps, nsnaps) : std::vector<char>(nsteps, 0);
   hipError_t e = hipSuccess;
   for (size_t i = rv_split(a); i < a.size() && rc == DG_OK; ++i) {
     switch (a[i].op) {
@@ -681,10 +720,16 @@ int dg_adjoint_backward(dg_ctx* c, double dt, int32_t nsteps, int32_t nsnaps, do
       case RV_ADVANCE:
         for (int k = 0; k < a[i].a && rc == DG_OK; ++k) rc = rk3_step(c, c->stream, work, dt);
         break;
-      case RV_ADJOINT:
+      case RV_ADJOINT: {
         // lam <- (d step / d U^k)^T lam, with U^k in the work slot
-        rc = rk3_adjoint(c, c->stream, work, dt, lam, lam);
+        const int k = a[i].a;
+        if (have[k])
+          rc = rk3_adjoint(c, c->stream, work, dt, lam, lam, stages + (size_t)(2 * k) * n,
+                           stages + (size_t)(2 * k + 1) * n);
+        else
+          rc = rk3_adjoint(c, c->stream, work, dt, lam, lam);
         break;
+      }
     }
     if (e != hipSuccess) return hip_fail(e, "checkpoint copy");
   }

@@ -71,9 +71,9 @@ EXPORTS = {
     "dg_step_adjoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
                                        ctypes.c_void_p]),
     "dg_adjoint_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
-                                          ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]),
+                                          ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "dg_adjoint_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
-                                           ctypes.c_void_p, ctypes.c_void_p]),
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "dg_revolve_stats": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]),
     "dg_batch_create": (ctypes.c_int, [ctypes.POINTER(MeshDesc), ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
     "dg_batch_destroy": (None, [ctypes.c_void_p]),
@@ -237,17 +237,22 @@ class DG:
     def checkpoints(self, nsnaps: int) -> torch.Tensor:
         return torch.empty((nsnaps + 2) * self.ncells * self.nloc, dtype=torch.float64, device=self.device)
 
-    def adjoint_forward(self, U0, dt, nsteps, nsnaps, ckpt, UT=None) -> torch.Tensor:
+    def stage_checkpoints(self, nsteps: int) -> torch.Tensor:
+        return torch.empty(2 * nsteps * self.ncells * self.nloc, dtype=torch.float64, device=self.device)
+
+    def adjoint_forward(self, U0, dt, nsteps, nsnaps, ckpt, UT=None, stages=None) -> torch.Tensor:
         UT = self.empty() if UT is None else UT
         n = self.ncells * self.nloc
         _check(self.lib.dg_adjoint_forward(self.h, _ptr(U0, n, "U0"), _ptr(UT, n, "UT"), float(dt), int(nsteps),
-                                           int(nsnaps), _ptr(ckpt, (nsnaps + 2) * n, "ckpt")))
+                                           int(nsnaps), _ptr(ckpt, (nsnaps + 2) * n, "ckpt"),
+                                           _ptr(stages, 2 * nsteps * n, "stages")))
         return UT
 
-    def adjoint_backward(self, dt, nsteps, nsnaps, ckpt, lam) -> torch.Tensor:
+    def adjoint_backward(self, dt, nsteps, nsnaps, ckpt, lam, stages=None) -> torch.Tensor:
         n = self.ncells * self.nloc
         _check(self.lib.dg_adjoint_backward(self.h, float(dt), int(nsteps), int(nsnaps),
-                                            _ptr(ckpt, (nsnaps + 2) * n, "ckpt"), _ptr(lam, n, "lam")))
+                                            _ptr(ckpt, (nsnaps + 2) * n, "ckpt"),
+                                            _ptr(stages, 2 * nsteps * n, "stages"), _ptr(lam, n, "lam")))
         return lam
 
     def set_tile(self, tx: int, ty: int = 1) -> None:
@@ -369,20 +374,24 @@ class DGRunFunction(torch.autograd.Function):
     the backward runs the hand-written discrete adjoint over them."""
 
     @staticmethod
-    def forward(ctx, U0, dg: "DG", dt: float, nsteps: int, nsnaps: int):
+    def forward(ctx, U0, dg: "DG", dt: float, nsteps: int, nsnaps: int, keep_stages: bool):
         ckpt = dg.checkpoints(nsnaps)
-        UT = dg.adjoint_forward(U0.detach().contiguous(), dt, nsteps, nsnaps, ckpt)
-        ctx.dg, ctx.dt, ctx.nsteps, ctx.nsnaps, ctx.ckpt = dg, dt, nsteps, nsnaps, ckpt
+        stages = dg.stage_checkpoints(nsteps) if keep_stages else None
+        UT = dg.adjoint_forward(U0.detach().contiguous(), dt, nsteps, nsnaps, ckpt, stages=stages)
+        ctx.dg, ctx.dt, ctx.nsteps, ctx.nsnaps, ctx.ckpt, ctx.stages = dg, dt, nsteps, nsnaps, ckpt, stages
         return UT
 
     @staticmethod
     def backward(ctx, gUT):
         lam = gUT.detach().clone().contiguous()
-        ctx.dg.adjoint_backward(ctx.dt, ctx.nsteps, ctx.nsnaps, ctx.ckpt, lam)
-        ctx.ckpt = None
-        return lam, None, None, None, None
+        ctx.dg.adjoint_backward(ctx.dt, ctx.nsteps, ctx.nsnaps, ctx.ckpt, lam, stages=ctx.stages)
+        ctx.ckpt = ctx.stages = None
+        return lam, None, None, None, None, None
 
 
-def run_differentiable(dg: "DG", U0: torch.Tensor, dt: float, nsteps: int, nsnaps: Optional[int] = None):
-    """nsteps SSP-RK3 steps of U0 with gradients through torch.autograd."""
-    return DGRunFunction.apply(U0, dg, dt, nsteps, nsteps if nsnaps is None else nsnaps)
+def run_differentiable(dg: "DG", U0: torch.Tensor, dt: float, nsteps: int, nsnaps: Optional[int] = None,
+                       keep_stages: bool = False):
+    """nsteps SSP-RK3 steps of U0 with gradients through torch.autograd
+    (binomial checkpointing with nsnaps stored states; keep_stages also stores
+    the RK stage states of every step the forward sweep advances)."""
+    return DGRunFunction.apply(U0, dg, dt, nsteps, nsteps if nsnaps is None else nsnaps, keep_stages)
