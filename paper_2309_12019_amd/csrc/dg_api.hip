@@ -494,43 +494,56 @@ int dg_step(dg_ctx* c, double* U, double dt) {
   return rk3_step(c, c->stream, U, dt);
 }
 
+// The executable graph of `len` SSP-RK3 steps on U with step dt: from the
+// cache, else captured on the private capture stream and instantiated.
+static int run_graph(dg_ctx* c, double* U, double dt, int len, hipGraphExec_t* out) {
+  GraphKey key{U, dt, len};
+  auto it = c->graphs.find(key);
+  if (it != c->graphs.end()) {
+    *out = it->second;
+    return DG_OK;
+  }
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+  int rc = DG_OK;
+  for (int s = 0; s < len && rc == DG_OK; ++s) rc = rk3_step(c, c->capture, U, dt);
+  e = hipStreamEndCapture(c->capture, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+  c->graphs[key] = exec;
+  *out = exec;
+  return DG_OK;
+}
+
 int dg_run(dg_ctx* c, double* U, double dt, int32_t nsteps) {
   if (!c || !U) return fail(DG_EINVAL, "NULL argument");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite and > 0");
   if (nsteps < 0) return fail(DG_EINVAL, "nsteps must be >= 0");
   if (nsteps == 0) return DG_OK;
+  // whole chunks of up to 64 steps replay one captured graph; a remainder
+  // replays a second graph of its own length (both cached per (U, dt, length))
   const int chunk = nsteps < 64 ? nsteps : 64;
-  GraphKey key{U, dt, chunk};
-  auto it = c->graphs.find(key);
-  hipGraphExec_t exec = nullptr;
-  if (it != c->graphs.end()) {
-    exec = it->second;
-  } else {
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-    int rc = DG_OK;
-    for (int s = 0; s < chunk && rc == DG_OK; ++s) rc = rk3_step(c, c->capture, U, dt);
-    e = hipStreamEndCapture(c->capture, &g);
-    if (rc) {
-      if (g) (void)hipGraphDestroy(g);
-      return rc;
-    }
-    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-    e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
-    if (c->graphs.size() >= 16) drop_graphs(c);
-    c->graphs[key] = exec;
-  }
   const int reps = nsteps / chunk, rest = nsteps % chunk;
+  hipGraphExec_t exec = nullptr, tail = nullptr;
+  if (c->graphs.size() >= 15) drop_graphs(c);  // bounded cache; room for two entries
+  int rc = run_graph(c, U, dt, chunk, &exec);
+  if (rc == DG_OK && rest) rc = run_graph(c, U, dt, rest, &tail);
+  if (rc) return rc;
   for (int i = 0; i < reps; ++i) {
     hipError_t e = hipGraphLaunch(exec, c->stream);
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
   }
-  for (int s = 0; s < rest; ++s) {
-    int rc = rk3_step(c, c->stream, U, dt);
-    if (rc) return rc;
+  if (rest) {
+    hipError_t e = hipGraphLaunch(tail, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
   }
   return DG_OK;
 }

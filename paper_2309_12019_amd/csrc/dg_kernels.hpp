@@ -63,8 +63,7 @@ constexpr int kTiles2D[2][2] = {{16, 16}, {8, 8}};
 
 __host__ __device__ inline int tile_lds_doubles(int dim, int nl, int tx, int ty) {
   const int ns = dim == 1 ? tx + 2 : (tx + 2) * (ty + 2);
-  const int nt = dim == 1 ? tx : tx * ty;
-  return nl * (ns | 1) + nl * nt;   // halo tile + U^n of the tile's cells
+  return nl * (ns | 1);   // the tile with its face halo
 }
 
 // x mod n for x in [-1, n + tile]: cheap for the common single wrap
@@ -239,12 +238,10 @@ struct Cell {
     }
   }
 
-  // dU/dt of one cell and gamma_e
-  __device__ static inline void rhs(const StageArgs& A, const double* b, int ix, int iy, double (&L)[NL],
-                                    double& gam_out) {
-    double c[NL];
-#pragma unroll
-    for (int j = 0; j < NL; ++j) c[j] = b[j * S];
+  // dU/dt of one cell and gamma_e; c holds the cell's own coefficients (the
+  // same values as its LDS slot b), the neighbours are read from LDS
+  __device__ static inline void rhs(const StageArgs& A, const double* b, const double (&c)[NL], int ix, int iy,
+                                    double (&L)[NL], double& gam_out) {
     bool has[NF];
     has[0] = A.per_x || ix > 0;
     has[1] = A.per_x || ix < A.nx - 1;
@@ -532,12 +529,11 @@ __host__ __device__ inline size_t neighbour_cell(int ix, int iy, int f, int nx, 
   return (size_t)iy * nx + ix;
 }
 
-// Load one slot (a cell's NL coefficients, or the constant exterior state
-// outside a non-periodic boundary) into the coefficient-major LDS tile.
-template <int DIM, int NL, int S>
-__device__ inline void load_slot(const StageArgs& A, double* lds, int slot, int gx, int gy) {
+// The NL coefficients of the cell at mesh coordinates (gx, gy) before
+// wrapping, or the constant exterior state outside a non-periodic boundary.
+template <int DIM, int NL>
+__device__ inline void load_cell(const StageArgs& A, int gx, int gy, double (&v)[NL]) {
   size_t cell;
-  double v[NL];
   if (slot_cell<DIM>(A, gx, gy, cell)) {
     const double* src = A.uin + cell * NL;
 #pragma unroll
@@ -546,64 +542,63 @@ __device__ inline void load_slot(const StageArgs& A, double* lds, int slot, int 
 #pragma unroll
     for (int j = 0; j < NL; ++j) v[j] = j == 0 ? A.bc : 0.0;
   }
+}
+
+// Load one slot into the coefficient-major LDS tile.
+template <int DIM, int NL, int S>
+__device__ inline void load_slot(const StageArgs& A, double* lds, int slot, int gx, int gy) {
+  double v[NL];
+  load_cell<DIM, NL>(A, gx, gy, v);
 #pragma unroll
   for (int j = 0; j < NL; ++j) lds[j * S + slot] = v[j];
 }
 
-// One tile of the fused stage: TX*TY threads, one per cell.  LDS: NL * S
-// doubles (the tile with its face halo, coefficient-major) + NL * TX*TY
-// doubles (U^n of the tile's cells).  Each thread loads its own cell's
-// coefficients (one base address, compile-time offsets; a wave covers a
-// contiguous span), the first threads also load the halo ring, and each
-// thread writes its own results; one barrier separates loads from arithmetic.
+// One tile of the fused stage: TX*TY threads, one per cell.  Each thread
+// loads its own cell's coefficients into registers (a wave covers a
+// contiguous span of the cell-major state) and publishes them in the
+// coefficient-major LDS tile (NL * S doubles) for its neighbours; the first
+// threads also load the halo ring.  After one barrier each thread evaluates
+// its cell from registers (own) and LDS (face neighbours), reads U^n of its
+// cell and writes the RK combination straight to HBM.
 template <int DIM, int P, int FLUX, int MODE, int TX, int TY>
 __device__ inline void stage_tile(const StageArgs& A, double* lds, int ix0, int iy0) {
   using G = TileGeom<DIM, TX, TY>;
   using C = Cell<DIM, P, FLUX, MODE, G::S, G::W>;
   constexpr int NL = C::NL;
-  constexpr int S = G::S, W = G::W;
+  constexpr int S = G::S;
   const int nx = A.nx, ny = DIM == 2 ? A.ny : 1;
   const bool comb = !A.rhs_only && A.a != 0.0;
 
   const int t = threadIdx.x;
-  const int lx = DIM == 2 ? t % TX : t, ly = DIM == 2 ? t / TX : 0;
-  const int ix = ix0 + lx, iy = iy0 + ly;
-  const bool active = ix < nx && iy < ny;
-  const int sc = DIM == 2 ? (ly + 1) * W + lx + 1 : lx + 1;
-  const size_t cell = (size_t)iy * nx + ix;
-
-  // U^n of this cell (RK combination), issued together with the tile loads and
-  // parked in LDS so it holds no registers during the cell arithmetic
-  double* lds_un = lds + NL * S;
-  if (comb && active) {
-    double un[NL];
+  int sc, gx, gy, hs, hgx, hgy;
+  const bool halo = tile_slots<DIM, TX, TY>(t, ix0, iy0, sc, gx, gy, hs, hgx, hgy);
+  const bool active = gx < nx && gy < ny;
+  const size_t cell = (size_t)gy * nx + gx;
+  // own slot (cells past a ragged edge hold the wrapped or exterior state)
+  double c[NL];
+  load_cell<DIM, NL>(A, gx, gy, c);
+  if (halo) load_slot<DIM, NL, S>(A, lds, hs, hgx, hgy);
 #pragma unroll
-    for (int j = 0; j < NL; ++j) un[j] = A.un[cell * NL + j];
-#pragma unroll
-    for (int j = 0; j < NL; ++j) lds_un[j * G::NT + t] = un[j];
-  }
-  // own slot (cells past a ragged edge hold the wrapped or exterior state) and
-  // one slot of the halo ring
-  {
-    int osc, ogx, ogy, hs, hgx, hgy;
-    const bool halo = tile_slots<DIM, TX, TY>(t, ix0, iy0, osc, ogx, ogy, hs, hgx, hgy);
-    load_slot<DIM, NL, S>(A, lds, osc, ogx, ogy);
-    if (halo) load_slot<DIM, NL, S>(A, lds, hs, hgx, hgy);
-  }
+  for (int j = 0; j < NL; ++j) lds[j * S + sc] = c[j];
   __syncthreads();
   if (active) {
     double L[NL], gam;
-    C::rhs(A, lds + sc, ix, iy, L, gam);
+    C::rhs(A, lds + sc, c, gx, gy, L, gam);
     if (A.gamma) A.gamma[cell] = gam;
     double* dst = A.out + cell * NL;
     if (A.rhs_only) {
 #pragma unroll
       for (int j = 0; j < NL; ++j) dst[j] = L[j];
     } else {
+      double un[NL];
+      if (comb) {
+#pragma unroll
+        for (int j = 0; j < NL; ++j) un[j] = A.un[cell * NL + j];
+      }
 #pragma unroll
       for (int j = 0; j < NL; ++j) {
-        double v = A.b * fma(A.dt, L[j], lds[j * S + sc]);
-        if (comb) v = fma(A.a, lds_un[j * G::NT + t], v);
+        double v = A.b * fma(A.dt, L[j], c[j]);
+        if (comb) v = fma(A.a, un[j], v);
         dst[j] = v;
       }
     }
