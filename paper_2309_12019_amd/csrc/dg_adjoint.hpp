@@ -32,6 +32,9 @@ struct AdjArgs {
   double alpha, beta, g1, g2;
 };
 
+// Doubles per cell in the sensor record (the layout is ZRec's).
+__host__ __device__ constexpr int zrec_doubles(int dim, int nl) { return nl + 2 * (2 * dim + 1) + 1; }
+
 template <int DIM, int P>
 struct ZRec {
   static constexpr int NL = DIM == 1 ? P + 1 : (P + 1) * (P + 1);
@@ -39,6 +42,7 @@ struct ZRec {
   // dbar[NL], omega[NF+1], beta_bar[NF+1], gamma
   static constexpr int OM = NL, BB = NL + NF + 1, GA = NL + 2 * (NF + 1);
   static constexpr int SIZE = GA + 1;
+  static_assert(SIZE == zrec_doubles(DIM, NL), "record layout");
 };
 
 template <int DIM, int P, int FLUX, int MODE, int S, int W>
@@ -275,11 +279,8 @@ struct AdjCell {
 
   // Pass A: the sensor of one cell, forward and reverse, seeded with
   // gamma_bar = -(lambda / p) g . Khat c.  Writes the cell's record.
-  __device__ static inline void sensor_adjoint(const StageArgs& A, const double* b, int ix, int iy,
-                                               const double (&v)[NL], double* zrec) {
-    double c[NL];
-#pragma unroll
-    for (int j = 0; j < NL; ++j) c[j] = b[j * S];
+  __device__ static inline void sensor_adjoint(const StageArgs& A, const double* b, const double (&c)[NL], int ix,
+                                               int iy, const double (&v)[NL], double* zrec) {
     bool has[NF];
     has[0] = A.per_x || ix > 0;
     has[1] = A.per_x || ix < A.nx - 1;
@@ -298,6 +299,7 @@ struct AdjCell {
       beta[f + 1] = C::qform(cd);
       al[f + 1] = has[f] ? A.wnb * C::weight(A, beta[f + 1]) : 0.0;
       m += has[f];
+      __builtin_amdgcn_sched_barrier(0);
     }
     al[0] = (1.0 - m * A.wnb) * C::weight(A, beta[0]);
     double ssum = 0.0;
@@ -307,17 +309,20 @@ struct AdjCell {
     double om[NF + 1];
 #pragma unroll
     for (int l = 0; l <= NF; ++l) om[l] = al[l] * inv;
+    // d = c - c* (non-constant coefficients; the quadratic form ignores d_0)
     double d[NL];
+    d[0] = 0.0;
 #pragma unroll
-    for (int j = 0; j < NL; ++j) d[j] = om[0] * c[j];
+    for (int j = 1; j < NL; ++j) d[j] = om[0] * c[j];
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       C::template cand_any<0>(f, b, cd);
 #pragma unroll
       for (int j = 1; j < NL; ++j) d[j] = fma(om[f + 1], cd[j], d[j]);
+      __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
-    for (int j = 0; j < NL; ++j) d[j] = c[j] - d[j];
+    for (int j = 1; j < NL; ++j) d[j] = c[j] - d[j];
     const double num2 = C::qform(d);
     const double den2 = beta[0];
     double ratio;
@@ -371,6 +376,7 @@ struct AdjCell {
 #pragma unroll
       for (int j = 1; j < NL; ++j) t = fma(db[j], cd[j], t);
       omb[f + 1] = -t;
+      __builtin_amdgcn_sched_barrier(0);
     }
     double dot = 0.0;
 #pragma unroll
@@ -410,15 +416,10 @@ struct AdjCell {
   }
 
   // Pass B: J^T v of one cell (gather form), combined into the output
-  __device__ static inline void grad(const AdjArgs& Ad, const double* b, const double* bv, int ix, int iy,
-                                     size_t cell, double (&G)[NL]) {
+  __device__ static inline void grad(const AdjArgs& Ad, const double* b, const double* bv, const double (&c)[NL],
+                                     const double (&v)[NL], int ix, int iy, size_t cell, double (&G)[NL]) {
     const StageArgs& A = Ad.s;
-    double c[NL], v[NL], g[NL];
-#pragma unroll
-    for (int j = 0; j < NL; ++j) {
-      c[j] = b[j * S];
-      v[j] = bv[j * S];
-    }
+    double g[NL];
     scale_g(A, v, g);
 #pragma unroll
     for (int j = 0; j < NL; ++j) G[j] = 0.0;
@@ -506,6 +507,7 @@ struct AdjCell {
         for (int bb = 0; bb < N; ++bb)
 #pragma unroll
           for (int a = 0; a < N; ++a) G[a + N * bb] = fma(wq * TB::nd.L[a][qx], acc[bb], G[a + N * bb]);
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
 
@@ -590,6 +592,8 @@ struct AdjCell {
             const double so = plus ? 1.0 : TB::dg.sgn[i];
             G[j] = fma(-so, acc[k], G[j]);
           }
+        // one face live at a time (keeps the register count down)
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
 
@@ -650,94 +654,98 @@ struct AdjCell {
             if (fo == 2) cand_T<2>(cb, G);
             if (fo == 3) cand_T<3>(cb, G);
           }
+          __builtin_amdgcn_sched_barrier(0);
         }
       }
     }
   }
 };
 
-template <int DIM, int NL, int S>
-__device__ inline void load_slot_v(const AdjArgs& Ad, double* lds, int slot, int gx, int gy) {
+// The cotangent of the cell at (gx, gy) before wrapping; zero outside a
+// non-periodic boundary (no equation there).
+template <int DIM, int NL>
+__device__ inline void load_cell_v(const AdjArgs& Ad, int gx, int gy, double (&v)[NL]) {
   size_t cell;
-  double v[NL];
   if (slot_cell<DIM>(Ad.s, gx, gy, cell)) {
     const double* src = Ad.v + cell * NL;
 #pragma unroll
     for (int j = 0; j < NL; ++j) v[j] = src[j];
   } else {
 #pragma unroll
-    for (int j = 0; j < NL; ++j) v[j] = 0.0;  // no equation outside the domain
+    for (int j = 0; j < NL; ++j) v[j] = 0.0;
   }
-#pragma unroll
-  for (int j = 0; j < NL; ++j) lds[j * S + slot] = v[j];
 }
 
 // Pass A kernel: sensor records.  LDS: NL * S doubles (state tile + halo).
+// Each thread keeps its own cell's coefficients and cotangent in registers
+// and publishes the coefficients for its neighbours.
 template <int DIM, int P, int FLUX, int MODE, int TX, int TY>
 __global__ void __launch_bounds__(DIM == 2 ? TX * TY : TX) adj_sensor_kernel(const AdjArgs Ad) {
   using G = TileGeom<DIM, TX, TY>;
   using AC = AdjCell<DIM, P, FLUX, MODE, G::S, G::W>;
-  constexpr int NL = AC::NL, S = G::S, W = G::W;
+  constexpr int NL = AC::NL, S = G::S;
   extern __shared__ double lds[];
   const StageArgs& A = Ad.s;
   const int ix0 = blockIdx.x * TX, iy0 = DIM == 2 ? blockIdx.y * TY : 0;
   const int t = threadIdx.x;
-  const int lx = DIM == 2 ? t % TX : t, ly = DIM == 2 ? t / TX : 0;
-  const int ix = ix0 + lx, iy = iy0 + ly;
-  const bool active = ix < A.nx && iy < (DIM == 2 ? A.ny : 1);
-  const int sc = DIM == 2 ? (ly + 1) * W + lx + 1 : lx + 1;
-  const size_t cell = (size_t)iy * A.nx + ix;
-  {
-    int osc, ogx, ogy, hs, hgx, hgy;
-    const bool halo = tile_slots<DIM, TX, TY>(t, ix0, iy0, osc, ogx, ogy, hs, hgx, hgy);
-    load_slot<DIM, NL, S>(A, lds, osc, ogx, ogy);
-    if (halo) load_slot<DIM, NL, S>(A, lds, hs, hgx, hgy);
-  }
-  double v[NL];
+  int sc, gx, gy, hs, hgx, hgy;
+  const bool halo = tile_slots<DIM, TX, TY>(t, ix0, iy0, sc, gx, gy, hs, hgx, hgy);
+  const bool active = gx < A.nx && gy < (DIM == 2 ? A.ny : 1);
+  const size_t cell = (size_t)gy * A.nx + gx;
+  double c[NL], v[NL];
+  load_cell<DIM, NL>(A, gx, gy, c);
+  if (halo) load_slot<DIM, NL, S>(A, lds, hs, hgx, hgy);
   if (active) {
 #pragma unroll
     for (int j = 0; j < NL; ++j) v[j] = Ad.v[cell * NL + j];
   }
+#pragma unroll
+  for (int j = 0; j < NL; ++j) lds[j * S + sc] = c[j];
   __syncthreads();
   if (!active) return;
-  AC::sensor_adjoint(A, lds + sc, ix, iy, v, Ad.z + cell * (size_t)AC::Z::SIZE);
+  AC::sensor_adjoint(A, lds + sc, c, gx, gy, v, Ad.z + cell * (size_t)AC::Z::SIZE);
 }
 
-// Pass B kernel: J^T v and the combination.  LDS: 2 * NL * S doubles.
+// Pass B kernel: J^T v and the combination.  LDS: 2 * NL * S doubles (state
+// and cotangent tiles); own values stay in registers.
 template <int DIM, int P, int FLUX, int MODE, int TX, int TY>
 __global__ void __launch_bounds__(DIM == 2 ? TX * TY : TX) adj_grad_kernel(const AdjArgs Ad) {
   using G = TileGeom<DIM, TX, TY>;
   using AC = AdjCell<DIM, P, FLUX, MODE, G::S, G::W>;
-  constexpr int NL = AC::NL, S = G::S, W = G::W;
+  constexpr int NL = AC::NL, S = G::S;
   extern __shared__ double lds[];
   double* ldsv = lds + NL * S;
   const StageArgs& A = Ad.s;
   const int ix0 = blockIdx.x * TX, iy0 = DIM == 2 ? blockIdx.y * TY : 0;
   const int t = threadIdx.x;
-  const int lx = DIM == 2 ? t % TX : t, ly = DIM == 2 ? t / TX : 0;
-  const int ix = ix0 + lx, iy = iy0 + ly;
-  const bool active = ix < A.nx && iy < (DIM == 2 ? A.ny : 1);
-  const int sc = DIM == 2 ? (ly + 1) * W + lx + 1 : lx + 1;
-  const size_t cell = (size_t)iy * A.nx + ix;
-  {
-    int osc, ogx, ogy, hs, hgx, hgy;
-    const bool halo = tile_slots<DIM, TX, TY>(t, ix0, iy0, osc, ogx, ogy, hs, hgx, hgy);
-    load_slot<DIM, NL, S>(A, lds, osc, ogx, ogy);
-    load_slot_v<DIM, NL, S>(Ad, ldsv, osc, ogx, ogy);
-    if (halo) {
-      load_slot<DIM, NL, S>(A, lds, hs, hgx, hgy);
-      load_slot_v<DIM, NL, S>(Ad, ldsv, hs, hgx, hgy);
-    }
+  int sc, gx, gy, hs, hgx, hgy;
+  const bool halo = tile_slots<DIM, TX, TY>(t, ix0, iy0, sc, gx, gy, hs, hgx, hgy);
+  const bool active = gx < A.nx && gy < (DIM == 2 ? A.ny : 1);
+  const size_t cell = (size_t)gy * A.nx + gx;
+  double c[NL], v[NL];
+  load_cell<DIM, NL>(A, gx, gy, c);
+  load_cell_v<DIM, NL>(Ad, gx, gy, v);
+  if (halo) {
+    double hv[NL];
+    load_slot<DIM, NL, S>(A, lds, hs, hgx, hgy);
+    load_cell_v<DIM, NL>(Ad, hgx, hgy, hv);
+#pragma unroll
+    for (int j = 0; j < NL; ++j) ldsv[j * S + hs] = hv[j];
+  }
+#pragma unroll
+  for (int j = 0; j < NL; ++j) {
+    lds[j * S + sc] = c[j];
+    ldsv[j * S + sc] = v[j];
   }
   __syncthreads();
   if (!active) return;
   double Gr[NL];
-  AC::grad(Ad, lds + sc, ldsv + sc, ix, iy, cell, Gr);
+  AC::grad(Ad, lds + sc, ldsv + sc, c, v, gx, gy, cell, Gr);
   double* dst = Ad.out + cell * NL;
 #pragma unroll
   for (int j = 0; j < NL; ++j) {
     double o = Ad.beta * Gr[j];
-    if (Ad.alpha != 0.0) o = fma(Ad.alpha, ldsv[j * S + sc], o);
+    if (Ad.alpha != 0.0) o = fma(Ad.alpha, ldsv[j * S + sc], o);  // LDS: v is dead in registers by now
     if (Ad.X) o = fma(Ad.g1, Ad.X[cell * NL + j], o);
     if (Ad.Y) o = fma(Ad.g2, Ad.Y[cell * NL + j], o);
     dst[j] = o;

@@ -128,13 +128,21 @@ int stage(dg_ctx* c, hipStream_t st, const double* uin, const double* un, double
 
 // eq. (ssp): U1 = U + dt L(U); U2 = 3/4 U + 1/4 (U1 + dt L(U1)); U = 1/3 U + 2/3 (U2 + dt L(U2)).
 // The stage states go to U1, U2 (default: the context's buffers).
-int rk3_step(dg_ctx* c, hipStream_t st, double* U, double dt, double* U1 = nullptr, double* U2 = nullptr) {
+// One SSP-RK3 step from Un into Uout (Uout may be Un: the last stage reads
+// U^n and writes the same element from one thread); the stage states go to
+// U1, U2 (the handle's scratch unless given).
+int rk3_step_to(dg_ctx* c, hipStream_t st, const double* Un, double* Uout, double dt, double* U1 = nullptr,
+                double* U2 = nullptr) {
   int rc;
   U1 = U1 ? U1 : c->U1;
   U2 = U2 ? U2 : c->U2;
-  if ((rc = stage(c, st, U, U, U1, nullptr, 0.0, 1.0, dt, 0))) return rc;
-  if ((rc = stage(c, st, U1, U, U2, nullptr, 0.75, 0.25, dt, 0))) return rc;
-  return stage(c, st, U2, U, U, nullptr, 1.0 / 3.0, 2.0 / 3.0, dt, 0);
+  if ((rc = stage(c, st, Un, Un, U1, nullptr, 0.0, 1.0, dt, 0))) return rc;
+  if ((rc = stage(c, st, U1, Un, U2, nullptr, 0.75, 0.25, dt, 0))) return rc;
+  return stage(c, st, U2, Un, Uout, nullptr, 1.0 / 3.0, 2.0 / 3.0, dt, 0);
+}
+
+int rk3_step(dg_ctx* c, hipStream_t st, double* U, double dt, double* U1 = nullptr, double* U2 = nullptr) {
+  return rk3_step_to(c, st, U, U, dt, U1, U2);
 }
 
 int validate(const dg_mesh_desc* d) {
@@ -188,7 +196,7 @@ int check_tile(const dg_ctx* c, int tx, int ty) {
   return DG_OK;
 }
 
-int zrec_size(int dim, int nl) { return nl + 2 * (2 * dim + 1) + 1; }
+int zrec_size(int dim, int nl) { return dgk::zrec_doubles(dim, nl); }
 
 int ensure_adjoint(dg_ctx* c) {
   if (c->A1) return DG_OK;
@@ -680,19 +688,30 @@ int dg_adjoint_forward(dg_ctx* c, const double* U0, double* UT, double dt, int32
   auto S1 = [&](int k) { return stages ? stages + (size_t)(2 * k) * n : nullptr; };
   auto S2 = [&](int k) { return stages ? stages + (size_t)(2 * k + 1) * n : nullptr; };
   int rc = DG_OK;
-  int cur = 0;  // step index of the working state
+  int cur = 0;                 // step index of the current state
+  const double* state = ckpt;  // where the current state lives (a slot or the work buffer)
   std::vector<int> slot_step(nsnaps + 1, 0);
   for (size_t i = 0; i < split && rc == DG_OK; ++i) {
     if (a[i].op == RV_RESTORE) {
-      e = hipMemcpyAsync(work, ckpt + (size_t)a[i].a * n, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+      state = ckpt + (size_t)a[i].a * n;  // read in place; nothing is copied
       cur = slot_step[a[i].a];
     } else if (a[i].op == RV_STORE) {
-      e = hipMemcpyAsync(ckpt + (size_t)a[i].a * n, work, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+      double* dst = ckpt + (size_t)a[i].a * n;
+      if (state != dst) {
+        e = hipMemcpyAsync(dst, state, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "checkpoint copy");
+        state = dst;
+      }
       slot_step[a[i].a] = cur;
     } else if (a[i].op == RV_ADVANCE) {
-      for (int k = 0; k < a[i].a && rc == DG_OK; ++k, ++cur) rc = rk3_step(c, c->stream, work, dt, S1(cur), S2(cur));
+      // the last step of an advance that is stored writes straight into its slot
+      const bool stored = i + 1 < split && a[i + 1].op == RV_STORE;
+      for (int k = 0; k < a[i].a && rc == DG_OK; ++k, ++cur) {
+        double* dst = (stored && k == a[i].a - 1) ? ckpt + (size_t)a[i + 1].a * n : work;
+        rc = rk3_step_to(c, c->stream, state, dst, dt, S1(cur), S2(cur));
+        state = dst;
+      }
     }
-    if (e != hipSuccess) return hip_fail(e, "checkpoint copy");
   }
   if (rc) return rc;
   // the state at nsteps-1 is restored by the first reverse action; reach U_T from it
@@ -700,12 +719,11 @@ int dg_adjoint_forward(dg_ctx* c, const double* U0, double* UT, double dt, int32
   int k0 = 0;
   for (size_t i = split; i < a.size() && a[i].op != RV_ADJOINT; ++i)
     if (a[i].op == RV_ADVANCE) k0 += a[i].a;
-  if ((e = hipMemcpyAsync(UT, ckpt + (size_t)slot * n, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream)) !=
-      hipSuccess)
-    return hip_fail(e, "checkpoint copy");
+  state = ckpt + (size_t)slot * n;
   for (int k = 0; k < k0 + 1 && rc == DG_OK; ++k) {
     const int step = nsteps - 1 - k0 + k;
-    rc = rk3_step(c, c->stream, UT, dt, k == k0 ? S1(step) : nullptr, k == k0 ? S2(step) : nullptr);
+    rc = rk3_step_to(c, c->stream, state, UT, dt, k == k0 ? S1(step) : nullptr, k == k0 ? S2(step) : nullptr);
+    state = UT;
   }
   return rc;
 }
@@ -722,6 +740,8 @@ int dg_adjoint_backward(dg_ctx* c, double dt, int32_t nsteps, int32_t nsnaps, do
   auto a = rv_schedule(nsteps, nsnaps);
   std::vector<char> have = stages ? rv_stage_steps(a, nsteps, nsnaps) : std::vector<char>(nsteps, 0);
   hipError_t e = hipSuccess;
+  // A restored checkpoint is copied into the work buffer, where the adjoint
+  // step reads it (the copy also leaves it in the last-level cache).
   for (size_t i = rv_split(a); i < a.size() && rc == DG_OK; ++i) {
     switch (a[i].op) {
       case RV_RESTORE:
@@ -734,7 +754,7 @@ int dg_adjoint_backward(dg_ctx* c, double dt, int32_t nsteps, int32_t nsnaps, do
         for (int k = 0; k < a[i].a && rc == DG_OK; ++k) rc = rk3_step(c, c->stream, work, dt);
         break;
       case RV_ADJOINT: {
-        // lam <- (d step / d U^k)^T lam, with U^k in the work slot
+        // lam <- (d step / d U^k)^T lam, with U^k in the work buffer
         const int k = a[i].a;
         if (have[k])
           rc = rk3_adjoint(c, c->stream, work, dt, lam, lam, stages + (size_t)(2 * k) * n,

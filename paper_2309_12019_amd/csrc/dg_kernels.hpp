@@ -180,39 +180,40 @@ struct Cell {
     return pow_cold(t, -A.wpow);
   }
 
-  // gamma_e of eqs. (sensor)/(gensensor) with the HWENO reconstruction
+  // gamma_e of eqs. (sensor)/(gensensor) with the HWENO reconstruction.
+  // One pass over the candidates: each candidate's indicator gives its
+  // unnormalised weight alpha_l at once, so c* = sum_l alpha_l c^(l) / sum alpha
+  // accumulates while the candidate is in registers.
   __device__ static inline double sensor(const StageArgs& A, const double* b, const bool (&has)[NF],
                                          const double (&c)[NL]) {
-    double beta0 = qform(c);
-    double al[NF];
-    double cd[NL];
+    const double beta0 = qform(c);
     int m = 0;
 #pragma unroll
-    for (int f = 0; f < NF; ++f) {
-      cand_any<0>(f, b, cd);
-      const double bl = qform(cd);
-      al[f] = has[f] ? A.wnb * weight(A, bl) : 0.0;
-      m += has[f];
-    }
+    for (int f = 0; f < NF; ++f) m += has[f];
     const double a0 = (1.0 - m * A.wnb) * weight(A, beta0);
     double asum = a0;
+    double acc[NL];  // sum_l alpha_l c^(l), non-constant coefficients
 #pragma unroll
-    for (int f = 0; f < NF; ++f) asum += al[f];
-    const double inv = rcp(asum);
-    // c - c* = c - sum_l omega_l c^(l), non-constant coefficients
-    double cs[NL];
-    const double w0 = a0 * inv;
-#pragma unroll
-    for (int j = 0; j < NL; ++j) cs[j] = w0 * c[j];
+    for (int j = 1; j < NL; ++j) acc[j] = a0 * c[j];
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
+      double cd[NL];
       cand_any<0>(f, b, cd);
-      const double wl = al[f] * inv;
+      const double al = has[f] ? A.wnb * weight(A, qform(cd)) : 0.0;
+      asum += al;
 #pragma unroll
-      for (int j = 1; j < NL; ++j) cs[j] = fma(wl, cd[j], cs[j]);
+      for (int j = 1; j < NL; ++j) acc[j] = fma(al, cd[j], acc[j]);
+      // keep one candidate live at a time (the scheduler would otherwise
+      // hoist every candidate's LDS reads and double the register count)
+      __builtin_amdgcn_sched_barrier(0);
     }
+    const double inv = rcp(asum);
+    // c - c*: the constant coefficient of every candidate is c_0, and the
+    // quadratic form ignores it
+    double cs[NL];
+    cs[0] = 0.0;
 #pragma unroll
-    for (int j = 0; j < NL; ++j) cs[j] = c[j] - cs[j];
+    for (int j = 1; j < NL; ++j) cs[j] = fma(-inv, acc[j], c[j]);
     const double num2 = qform(cs);
     double ratio;
     if (num2 == 0.0)
