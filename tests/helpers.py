@@ -22,3 +22,46 @@ def oracle_initial(w, O=None):
     pts = O.proj_nodes().numpy()
     vals = torch.from_numpy(np.ascontiguousarray(w.eval_ic(pts)))
     return O.project(vals)
+
+
+def oracle_window(w: inputs.Workload, ix: int, iy: int, radius: int):
+    """An oracle on the window of cells within `radius` (max-norm) of cell
+    (ix, iy): same flux, sensor and geometry (window origin at the window's
+    first cell), never periodic; windows are clipped at non-periodic mesh
+    boundaries, where the window's own boundary is then the mesh boundary.
+    The operator at the window's centre depends only on the centre and its
+    face neighbours, one SSP-RK3 step on cells within three face steps, so
+    with radius 1 (operator) or 3 (step) the centre's value is the full
+    mesh's.  Returns the oracle, the global cell index of every window cell
+    (window order, x fastest) and the window index of the centre."""
+    p = oracle_problem(w)
+    h = p.h
+    ny = w.ny if w.dim == 2 else 1
+
+    def axis(i, n, per):
+        if per:
+            return [(i + d) % n for d in range(-radius, radius + 1)], radius
+        lo, hi = max(0, i - radius), min(n - 1, i + radius)
+        return list(range(lo, hi + 1)), i - lo
+
+    xs, cx = axis(ix, w.nx, w.periodic_x)
+    if w.dim == 2:
+        ys, cy = axis(iy, ny, w.periodic_y)
+    else:
+        ys, cy = [0], 0
+    # window geometry: the first window cell sits where its mesh cell sits
+    # (periodic windows are unrolled from that cell on)
+    x0 = w.x0 + (ix - cx) * h
+    y0 = (w.y0 + (iy - cy) * h) if w.dim == 2 else p.y0
+    p.nx = len(xs)
+    p.x0, p.x1 = x0, x0 + len(xs) * h
+    if w.dim == 2:
+        p.ny = len(ys)
+        p.y0, p.y1 = y0, y0 + len(ys) * h
+    p.periodic_x = False
+    p.periodic_y = False
+    # a periodic axis keeps all face neighbours of the centre: the window
+    # boundary is at least `radius` cells away from it
+    cells = [yy * w.nx + xx for yy in ys for xx in xs]
+    centre = cy * len(xs) + cx
+    return oracle.Oracle(p), cells, centre
