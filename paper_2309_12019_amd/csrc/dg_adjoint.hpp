@@ -25,7 +25,7 @@ namespace dgk {
 struct AdjArgs {
   StageArgs s;        // geometry, flux, sensor parameters; s.uin = U (state)
   const double* v;    // cotangent of L(U), [cells][NL]
-  double* z;          // sensor records, [cells][ZN]
+  double* z;          // sensor records, field-major: field k of cell e at z[k * cells + e]
   double* out;        // pass B: out = alpha v + beta J^T v + g1 X + g2 Y
   const double* X;    // optional [cells][NL]
   const double* Y;    // optional [cells][NL]
@@ -39,7 +39,9 @@ template <int DIM, int P>
 struct ZRec {
   static constexpr int NL = DIM == 1 ? P + 1 : (P + 1) * (P + 1);
   static constexpr int NF = 2 * DIM;
-  // dbar[NL], omega[NF+1], beta_bar[NF+1], gamma
+  // fields dbar[NL], omega[NF+1], beta_bar[NF+1], gamma; stored field-major
+  // (one plane of cells per field) so that a wave's stores and its reads of a
+  // neighbour's field are contiguous
   static constexpr int OM = NL, BB = NL + NF + 1, GA = NL + 2 * (NF + 1);
   static constexpr int SIZE = GA + 1;
   static_assert(SIZE == zrec_doubles(DIM, NL), "record layout");
@@ -280,7 +282,7 @@ struct AdjCell {
   // Pass A: the sensor of one cell, forward and reverse, seeded with
   // gamma_bar = -(lambda / p) g . Khat c.  Writes the cell's record.
   __device__ static inline void sensor_adjoint(const StageArgs& A, const double* b, const double (&c)[NL], int ix,
-                                               int iy, const double (&v)[NL], double* zrec) {
+                                               int iy, const double (&v)[NL], double* zrec, size_t zs) {
     bool has[NF];
     has[0] = A.per_x || ix > 0;
     has[1] = A.per_x || ix < A.nx - 1;
@@ -390,13 +392,13 @@ struct AdjCell {
     }
     bb[0] += den2b;
 #pragma unroll
-    for (int j = 0; j < NL; ++j) zrec[j] = db[j];
+    for (int j = 0; j < NL; ++j) zrec[j * zs] = db[j];
 #pragma unroll
     for (int l = 0; l <= NF; ++l) {
-      zrec[Z::OM + l] = om[l];
-      zrec[Z::BB + l] = bb[l];
+      zrec[(Z::OM + l) * zs] = om[l];
+      zrec[(Z::BB + l) * zs] = bb[l];
     }
-    zrec[Z::GA] = gam;
+    zrec[Z::GA * zs] = gam;
   }
 
   // numerical flux derivative dH/du^-
@@ -415,10 +417,67 @@ struct AdjCell {
     }
   }
 
+  // Face F (2D) of pass B: - sum_r w_r (g^- - g_nb^+) dH/du^- phi(r) into G
+  template <int F>
+  __device__ static inline void face2d(const StageArgs& A, const double* b, const double* bv, const double (&c)[NL],
+                                       const double (&g)[NL], const double (&vxl)[Q], const double (&vyl)[Q],
+                                       double (&G)[NL]) {
+    const double g2h = 2.0 / A.h;
+    constexpr int axis = F >> 1;
+    constexpr bool plus = F & 1;
+    const double s = plus ? 1.0 : -1.0;
+    double tm[N], tp[N], sm[N], sp[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      double t = 0.0, tn = 0.0, gt = 0.0, gn = 0.0;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const int j = axis == 0 ? i + N * k : k + N * i;
+        const double so = plus ? 1.0 : TB::dg.sgn[i];
+        const double sn = plus ? TB::dg.sgn[i] : 1.0;
+        t = fma(so, c[j], t);
+        tn = fma(sn, b[j * S + C::off(F)], tn);
+        gt = fma(so, g[j], gt);
+        gn = fma(sn * g2h * TB::dg.minv[i] * TB::dg.minv[k], bv[j * S + C::off(F)], gn);
+      }
+      tm[k] = t;
+      tp[k] = tn;
+      sm[k] = gt;
+      sp[k] = gn;
+    }
+    double acc[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) acc[k] = 0.0;
+#pragma unroll
+    for (int r = 0; r < Q; ++r) {
+      double um = tm[0], up = tp[0], gm = sm[0], gp = sp[0];
+#pragma unroll
+      for (int k = 1; k < N; ++k) {
+        um = fma(tm[k], TB::nd.L[k][r], um);
+        up = fma(tp[k], TB::nd.L[k][r], up);
+        gm = fma(sm[k], TB::nd.L[k][r], gm);
+        gp = fma(sp[k], TB::nd.L[k][r], gp);
+      }
+      const double vax = axis == 0 ? vxl[r] : vyl[r];
+      const double dl = TB::nd.w[r] * (gm - gp) * dllf(s, vax, um, up);
+#pragma unroll
+      for (int k = 0; k < N; ++k) acc[k] = fma(TB::nd.L[k][r], dl, acc[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const int j = axis == 0 ? i + N * k : k + N * i;
+        const double so = plus ? 1.0 : TB::dg.sgn[i];
+        G[j] = fma(-so, acc[k], G[j]);
+      }
+  }
+
   // Pass B: J^T v of one cell (gather form), combined into the output
   __device__ static inline void grad(const AdjArgs& Ad, const double* b, const double* bv, const double (&c)[NL],
                                      const double (&v)[NL], int ix, int iy, size_t cell, double (&G)[NL]) {
     const StageArgs& A = Ad.s;
+    const size_t zs = (size_t)A.nx * (DIM == 2 ? A.ny : 1);  // record field stride
     double g[NL];
     scale_g(A, v, g);
 #pragma unroll
@@ -435,7 +494,11 @@ struct AdjCell {
     const double yc = DIM == 2 ? A.y0 + (iy + 0.5) * A.h : 0.0;
     const double g2h = 2.0 / A.h;
 
-    // ---- volume: sum_q w_q (grad g . F'(u_q)) phi(q)
+    // ---- volume: sum_q w_q (grad g . F'(u_q)) phi(q); for the Burgers flux
+    // the same node values give lambda_e and its node (the order and the
+    // arithmetic of lambda(), so the result is the same)
+    double vmax = 0.0, vmax_u = 0.0;
+    int vmax_q = -1;
     if constexpr (DIM == 1) {
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
@@ -444,6 +507,11 @@ struct AdjCell {
         for (int a = 1; a < N; ++a) {
           u = fma(c[a], TB::nd.L[a][q], u);
           gd = fma(g[a], TB::nd.D[a][q], gd);
+        }
+        if (FLUX == FLUX_BURGERS && fabs(u) > vmax) {
+          vmax = fabs(u);
+          vmax_q = q;
+          vmax_u = u;
         }
         const double fp = FLUX == FLUX_LINADV ? A.vx : A.vx * u;
         const double sq = TB::nd.w[q] * gd * fp;
@@ -489,6 +557,11 @@ struct AdjCell {
             u = fma(s1[bb], TB::nd.L[bb][qy], u);
             gx = fma(gx1[bb], TB::nd.L[bb][qy], gx);
             gy = fma(gy1[bb], TB::nd.D[bb][qy], gy);
+          }
+          if (FLUX == FLUX_BURGERS && fabs(u) > vmax) {
+            vmax = fabs(u);
+            vmax_q = qx + Q * qy;
+            vmax_u = u;
           }
           double fx, fy;
           if constexpr (FLUX == FLUX_LINADV) {
@@ -542,59 +615,15 @@ struct AdjCell {
           vyl[k] = A.vy;
         }
       }
-#pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        const int axis = f >> 1;
-        const bool plus = f & 1;
-        const double s = plus ? 1.0 : -1.0;
-        double tm[N], tp[N], sm[N], sp[N];
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-          double t = 0.0, tn = 0.0, gt = 0.0, gn = 0.0;
-#pragma unroll
-          for (int i = 0; i < N; ++i) {
-            const int j = axis == 0 ? i + N * k : k + N * i;
-            const double so = plus ? 1.0 : TB::dg.sgn[i];
-            const double sn = plus ? TB::dg.sgn[i] : 1.0;
-            t = fma(so, c[j], t);
-            tn = fma(sn, b[j * S + C::off(f)], tn);
-            gt = fma(so, g[j], gt);
-            gn = fma(sn * g2h * TB::dg.minv[i] * TB::dg.minv[k], bv[j * S + C::off(f)], gn);
-          }
-          tm[k] = t;
-          tp[k] = tn;
-          sm[k] = gt;
-          sp[k] = gn;
-        }
-        double acc[N];
-#pragma unroll
-        for (int k = 0; k < N; ++k) acc[k] = 0.0;
-#pragma unroll
-        for (int r = 0; r < Q; ++r) {
-          double um = tm[0], up = tp[0], gm = sm[0], gp = sp[0];
-#pragma unroll
-          for (int k = 1; k < N; ++k) {
-            um = fma(tm[k], TB::nd.L[k][r], um);
-            up = fma(tp[k], TB::nd.L[k][r], up);
-            gm = fma(sm[k], TB::nd.L[k][r], gm);
-            gp = fma(sp[k], TB::nd.L[k][r], gp);
-          }
-          const double vax = axis == 0 ? vxl[r] : vyl[r];
-          const double dl = TB::nd.w[r] * (gm - gp) * dllf(s, vax, um, up);
-#pragma unroll
-          for (int k = 0; k < N; ++k) acc[k] = fma(TB::nd.L[k][r], dl, acc[k]);
-        }
-#pragma unroll
-        for (int k = 0; k < N; ++k)
-#pragma unroll
-          for (int i = 0; i < N; ++i) {
-            const int j = axis == 0 ? i + N * k : k + N * i;
-            const double so = plus ? 1.0 : TB::dg.sgn[i];
-            G[j] = fma(-so, acc[k], G[j]);
-          }
-        // one face live at a time (keeps the register count down)
-        __builtin_amdgcn_sched_barrier(0);
-      }
+      // one face live at a time (keeps the register count down)
+      face2d<0>(A, b, bv, c, g, vxl, vyl, G);
+      __builtin_amdgcn_sched_barrier(0);
+      face2d<1>(A, b, bv, c, g, vxl, vyl, G);
+      __builtin_amdgcn_sched_barrier(0);
+      face2d<2>(A, b, bv, c, g, vxl, vyl, G);
+      __builtin_amdgcn_sched_barrier(0);
+      face2d<3>(A, b, bv, c, g, vxl, vyl, G);
+      __builtin_amdgcn_sched_barrier(0);
     }
 
     // ---- dissipation: - kd Khat g, and through lambda_e
@@ -602,12 +631,18 @@ struct AdjCell {
       double gam = 1.0;
       const double* zo = nullptr;
       if constexpr (MODE == MODE_WENO) {
-        zo = Ad.z + cell * (size_t)Z::SIZE;
-        gam = zo[Z::GA];
+        zo = Ad.z + cell;
+        gam = zo[Z::GA * zs];
       }
       int qm;
-      double um;
-      double lam = lambda(A, c, xc, yc, qm, um);
+      double um, lam;
+      if constexpr (FLUX == FLUX_BURGERS) {
+        qm = vmax_q;
+        um = vmax_u;
+        lam = A.anorm * vmax;
+      } else {
+        lam = lambda(A, c, xc, yc, qm, um);
+      }
       const bool over = A.lam_over > 0.0;
       if (over) lam = A.lam_over;
       sub_khat(gam * lam * (1.0 / P), g, G);
@@ -625,16 +660,16 @@ struct AdjCell {
       if constexpr (MODE == MODE_WENO) {
         double d[NL], bc[NL];
 #pragma unroll
-        for (int j = 0; j < NL; ++j) d[j] = zo[j];
+        for (int j = 0; j < NL; ++j) d[j] = zo[j * zs];
         bvec(c, bc);
-        const double om0 = zo[Z::OM], bb0 = zo[Z::BB];
+        const double om0 = zo[Z::OM * zs], bb0 = zo[Z::BB * zs];
 #pragma unroll
         for (int j = 1; j < NL; ++j) G[j] = fma(1.0 - om0, d[j], fma(2.0 * bb0, bc[j], G[j]));
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
           if (!has[f]) continue;
           // neighbour across face f; this cell is its candidate of face f^1
-          const double* zn = Ad.z + neighbour_cell(ix, iy, f, A.nx, DIM == 2 ? A.ny : 1) * (size_t)Z::SIZE;
+          const double* zn = Ad.z + neighbour_cell(ix, iy, f, A.nx, DIM == 2 ? A.ny : 1);
           const int fo = f ^ 1;
           double cd[NL], cb[NL];
           if (fo == 0) cand_regs<0>(c, cd);
@@ -645,9 +680,9 @@ struct AdjCell {
           }
           double bcd[NL];
           bvec(cd, bcd);
-          const double omf = zn[Z::OM + fo + 1], bbf = zn[Z::BB + fo + 1];
+          const double omf = zn[(Z::OM + fo + 1) * zs], bbf = zn[(Z::BB + fo + 1) * zs];
 #pragma unroll
-          for (int j = 0; j < NL; ++j) cb[j] = j == 0 ? 0.0 : fma(-omf, zn[j], 2.0 * bbf * bcd[j]);
+          for (int j = 0; j < NL; ++j) cb[j] = j == 0 ? 0.0 : fma(-omf, zn[j * zs], 2.0 * bbf * bcd[j]);
           if (fo == 0) cand_T<0>(cb, G);
           if (fo == 1) cand_T<1>(cb, G);
           if constexpr (DIM == 2) {
@@ -703,7 +738,7 @@ __global__ void __launch_bounds__(DIM == 2 ? TX * TY : TX) adj_sensor_kernel(con
   for (int j = 0; j < NL; ++j) lds[j * S + sc] = c[j];
   __syncthreads();
   if (!active) return;
-  AC::sensor_adjoint(A, lds + sc, c, gx, gy, v, Ad.z + cell * (size_t)AC::Z::SIZE);
+  AC::sensor_adjoint(A, lds + sc, c, gx, gy, v, Ad.z + cell, (size_t)A.nx * (DIM == 2 ? A.ny : 1));
 }
 
 // Pass B kernel: J^T v and the combination.  LDS: 2 * NL * S doubles (state
