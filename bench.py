@@ -91,7 +91,7 @@ def cpu_baseline(w, budget_s=15.0):
     t0 = time.perf_counter()
     U = O.step(U, dt)
     one = time.perf_counter() - t0
-    n = max(1, min(50, int(budget_s / max(one, 1e-3)) - 1))
+    n = max(1, min(400, int(budget_s / max(one, 1e-3)) - 1))
     t0 = time.perf_counter()
     for _ in range(n):
         U = O.step(U, dt)
@@ -248,14 +248,30 @@ def bench_adjoint(n=512, steps=400, ndir=32, nsnaps=None, seed=0):
     return res
 
 
+STAGE_SOURCES = ("dg_kernels.hpp", "dg_tables.hpp", "dg_stage.hip")
+
+
+def stage_source_digest():
+    """SHA-256 over the sources the stage kernel is compiled from."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in STAGE_SOURCES:
+        with open(os.path.join(ROOT, "paper_2309_12019_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def traffic_for(wname):
-    """HBM bytes per stage launch from the committed rocprofv3 counter summary,
-    if one exists for this workload (else None)."""
+    """HBM bytes per stage launch from the committed rocprofv3 counter summary
+    for this workload; None if there is none or if the kernel sources changed
+    since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "stage_traffic.json")
     if not os.path.exists(path):
         return None
     try:
         d = json.load(open(path))
+        if d.get("kernel_source_sha256") != stage_source_digest():
+            return None
         return d.get(wname, {}).get("bytes_per_launch")
     except Exception:
         return None
