@@ -1,18 +1,23 @@
-"""Benchmark of the fused SSP-RK3 stage path on one MI355X.
+"""Benchmark of the dissipative-WENO RKDG hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rot2d_256_p2]
 
-A step is one SSP-RK3 step (three fused stage launches, each evaluating the
-whole stabilised DG operator: traces, volume and face quadrature with the LLF
-flux, HWENO reconstruction, sensor, dissipation, mass inverse and the RK
-combination) over the whole mesh of the workload.  K steps run as one dg_run
-call (HIP graph replay) with the state already resident in HBM; the timed
-region is bracketed by device synchronisation.
+A step is one SSP-RK3 step over the whole mesh of the workload: the three
+stages each evaluate the whole stabilised DG operator (traces, volume and face
+quadrature with the LLF flux, HWENO reconstruction, sensor, dissipation, mass
+inverse) and the RK combination.  K steps run as one dg_run call (HIP graph
+replay) with the state already resident in HBM; the timed region is bracketed
+by device synchronisation.  dg_run uses the library's automatic choice: the
+fused step kernel (one launch per step) on small meshes, three per-stage
+launches otherwise.
 
 Printed: one JSON line with the metric (FP64 DOF-updates per second per RK
-stage), the roofline of the stage kernel (algorithmic HBM bytes per launch over
-its average duration, from HIP events on the stream the kernels run on), and
-the CPU oracle timed on a bounded sample of the same workload.
+stage), the roofline of the dominant kernel from HIP events on the stream the
+kernels run on (fused step kernel: FP64 flops per launch over its duration
+against the FP64 vector peak; per-stage kernel: algorithmic HBM bytes per
+launch over its duration against 8 TB/s), the per-stage kernel's HBM roofline
+on the same workload when the fused kernel is the default, and the CPU oracle
+timed on a bounded sample of the same workload.
 """
 import argparse
 import json
@@ -40,16 +45,28 @@ def workload(name):
     return table[name]()
 
 
+# FP64 flops per cell and stage that the per-stage kernel executes
+# (rocprofv3 SQ_INSTS_VALU_{FMA,ADD,MUL,TRANS}_F64 per wave, one lane per
+# cell, FMA counted twice; profiles/stage_kernel_hbm_counters.md): the
+# per-unit figure of the arithmetic roofline.  Keyed by (dim, p, flux, mode).
+FLOPS_PER_CELL_STAGE = {(2, 2, 0, 2): 1160.0, (2, 3, 0, 2): 2376.0, (2, 2, 1, 2): 1415.0}
+FP64_PEAK_TFLOPS = 78.6
+
+
 def stage_bytes_per_dof():
     """Algorithmic HBM bytes per DOF per stage: stage 1 reads U^n and writes
     U^(1) (16 B); stages 2 and 3 also read U^n (24 B); mean 64/3 B."""
     return (16.0 + 24.0 + 24.0) / 3.0
 
 
-def time_gpu(w, steps, warmup):
+def time_gpu(w, steps, warmup, fused=None):
+    """Time `steps` SSP-RK3 steps of dg_run; fused: None keeps the library's
+    automatic choice of the fused step kernel, 0 / 1 forces it off / on."""
     import torch
     from paper_2309_12019_amd import dgweno
     g = dgweno.DG.from_workload(w)
+    if fused is not None:
+        g.set_fused(fused)
     U0 = g.initial_state(w)
     dt = w.dt()
     # dg_run replays graphs cached per (state buffer, dt, chunk length): one
@@ -75,7 +92,7 @@ def time_gpu(w, steps, warmup):
     bad = g.count_nonfinite(U)
     if bad:
         raise RuntimeError(f"{bad} non-finite values after the timed run")
-    return dict(wall=wall, event_ms=ev_ms, ndof=w.ndof, steps=steps, tile=g.tile())
+    return dict(wall=wall, event_ms=ev_ms, ndof=w.ndof, steps=steps, tile=g.tile(), fused=g.fused())
 
 
 def cpu_baseline(w, budget_s=15.0):
@@ -327,13 +344,39 @@ def main():
     w = workload(args.workload)
     r = time_gpu(w, args.steps, args.warmup)
     sec = r["event_ms"] / 1e3
-    launches = 3 * args.steps
     dof_rate = 3.0 * w.ndof * args.steps / sec
     bpd = stage_bytes_per_dof()
-    bytes_per_launch = bpd * w.ndof
-    avg_launch = sec / launches
-    achieved = bytes_per_launch / avg_launch / 1e9
-    traffic = traffic_for(args.workload)
+    key = (w.dim, w.p, w.flux, w.mode)
+
+    def stage_roofline(sec_, steps_):
+        """HBM roofline of the per-stage kernel: 64/3 algorithmic bytes per DOF
+        per launch, three launches per step."""
+        avg = sec_ / (3 * steps_)
+        ach = bpd * w.ndof / avg / 1e9
+        return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach / HBM_PEAK_GBS, "traffic": traffic_for(args.workload),
+                "kernel": f"stage_kernel<{w.dim},{w.p},{w.flux},{w.mode}>",
+                "bytes_per_dof": bpd, "avg_launch_us": avg * 1e6}
+
+    if r["fused"]:
+        # one fused launch per step: U^n in, U^(n+1) out (16 B per DOF), three
+        # stages of arithmetic; the arithmetic roof binds (about 24 flop/B)
+        avg = sec / args.steps
+        flops = 3.0 * FLOPS_PER_CELL_STAGE[key] * w.ncells if key in FLOPS_PER_CELL_STAGE else None
+        ach = flops / avg / 1e12 if flops else None
+        roof = {"bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / FP64_PEAK_TFLOPS if ach else None,
+                "traffic": traffic_for(args.workload + ":step"),
+                "kernel": f"step_kernel<{w.dim},{w.p},{w.flux},{w.mode}> (fused SSP-RK3 step)",
+                "flops_per_launch": flops, "avg_launch_us": avg * 1e6,
+                "hbm_bytes_per_launch": 16.0 * w.ndof,
+                "hbm_frac": 16.0 * w.ndof / avg / 1e9 / HBM_PEAK_GBS}
+        rs = time_gpu(w, args.steps, args.warmup, fused=0)
+        stage_roof = stage_roofline(rs["event_ms"] / 1e3, args.steps)
+        stage_roof["value"] = 3.0 * w.ndof * args.steps / (rs["event_ms"] / 1e3)
+    else:
+        roof = stage_roofline(sec, args.steps)
+        stage_roof = None
     line = {
         "metric": METRIC,
         "value": dof_rate,
@@ -350,22 +393,23 @@ def main():
         "config": {"workload": w.name, "dim": w.dim, "cells": w.ncells, "p": w.p, "dofs": w.ndof,
                    "flux": "linear advection" if w.flux == 0 else "Burgers",
                    "mode": ["DG", "LO", "WENO"][w.mode], "ssp_rk3_steps": args.steps,
-                   "dt": w.dt(), "tile": list(r["tile"])},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": f"stage_kernel<{w.dim},{w.p},{w.flux},{w.mode}>",
-                     "bytes_per_dof": bpd, "avg_launch_us": avg_launch * 1e6},
+                   "dt": w.dt(), "tile": list(r["tile"]), "fused_step": r["fused"]},
+        "roofline": roof,
         "wall_s": r["wall"],
     }
+    if stage_roof:
+        line["stage_kernel_roofline"] = stage_roof
     extra = {}
     for name in [s for s in args.extra.split(",") if s]:
         we = workload(name)
         k = min(we.steps, 100)
         re_ = time_gpu(we, k, 5)
         s_ = re_["event_ms"] / 1e3
-        extra[name] = {"value": 3.0 * we.ndof * k / s_, "steps": k, "dofs": we.ndof,
-                       "avg_launch_us": s_ / (3 * k) * 1e6,
-                       "hbm_frac": bpd * we.ndof / (s_ / (3 * k)) / 1e9 / HBM_PEAK_GBS}
+        launches = k if re_["fused"] else 3 * k
+        extra[name] = {"value": 3.0 * we.ndof * k / s_, "steps": k, "dofs": we.ndof, "fused_step": re_["fused"],
+                       "us_per_step": s_ / k * 1e6, "avg_launch_us": s_ / launches * 1e6}
+        if not re_["fused"]:
+            extra[name]["hbm_frac"] = bpd * we.ndof / (s_ / launches) / 1e9 / HBM_PEAK_GBS
     if extra:
         line["extra"] = extra
     if not args.no_batch:

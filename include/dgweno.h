@@ -142,6 +142,18 @@ int dg_check_finite(dg_ctx* ctx, const double* U, int64_t* count);
 int dg_set_tile(dg_ctx* ctx, int32_t tx, int32_t ty);
 int dg_get_tile(const dg_ctx* ctx, int32_t* tx, int32_t* ty);
 
+/* Fused step kernel (eq. (ssp), all three stages in one launch): a tile
+ * loads U^n on itself and three rings of cells around it and evaluates the
+ * stages on shrinking rings in LDS, so one step moves U^n and U^(n+1) through
+ * HBM once.  Same per-cell arithmetic as the per-stage kernel, so results are
+ * bitwise the same.  Used by dg_step and dg_run.  mode: -1 automatic (default: on
+ * in 1D, and in 2D for meshes of at most one 16x16 tile per compute unit,
+ * where per-stage launches are latency bound), 0 off, 1 on.  Errors:
+ * DG_EINVAL for another mode, DG_EUNSUPPORTED for mode 1 when the three
+ * tiles exceed LDS (2D degree 4).  dg_get_fused writes 1 if steps use it. */
+int dg_set_fused(dg_ctx* ctx, int32_t mode);
+int dg_get_fused(const dg_ctx* ctx, int32_t* active);
+
 /* Replace the stream the context queues work on. */
 int dg_set_stream(dg_ctx* ctx, void* stream);
 

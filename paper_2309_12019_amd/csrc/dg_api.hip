@@ -9,6 +9,7 @@
 #include <map>
 #include <new>
 #include <tuple>
+#include <utility>
 #include <vector>
 
 #include "../../include/dgweno.h"
@@ -55,6 +56,9 @@ struct dg_ctx {
   long long ncells = 0;
   int tx = 0, ty = 1;
   int max_lds = 65536;
+  int cus = 256;
+  int fused_mode = -1;   // fused step kernel: -1 automatic, 0 off, 1 on
+  bool fused = false;    // whether steps use the fused kernel
   double h = 0;
   hipStream_t stream = nullptr;
   hipStream_t capture = nullptr;  // private stream used only to record graphs
@@ -141,7 +145,50 @@ int rk3_step_to(dg_ctx* c, hipStream_t st, const double* Un, double* Uout, doubl
   return stage(c, st, U2, Un, Uout, nullptr, 1.0 / 3.0, 2.0 / 3.0, dt, 0);
 }
 
+// One fused SSP-RK3 step (one launch) from Un into Uout != Un.
+int step_fused(dg_ctx* c, hipStream_t st, const double* Un, double* Uout, double dt) {
+  LaunchReq r{};
+  r.kind = dgk::LAUNCH_STEP;
+  r.flux = c->d.flux;
+  r.mode = c->d.mode;
+  r.args = base_args(c);
+  r.args.uin = Un;
+  r.args.un = Un;
+  r.args.out = Uout;
+  r.args.dt = dt;
+  r.stream = st;
+  hipError_t e = c->launch(&r);
+  if (e != hipSuccess) return hip_fail(e, "step kernel launch");
+  return DG_OK;
+}
+
+// len SSP-RK3 steps on U in place.  With the fused kernel the steps
+// alternate between U and the scratch buffer U1 (the kernel cannot write the
+// array it reads), and an odd count ends with one copy back into U.
+int rk3_steps(dg_ctx* c, hipStream_t st, double* U, double dt, int len) {
+  if (!c->fused) {
+    for (int s = 0; s < len; ++s) {
+      int rc = rk3_step_to(c, st, U, U, dt);
+      if (rc) return rc;
+    }
+    return DG_OK;
+  }
+  double* cur = U;
+  double* other = c->U1;
+  for (int s = 0; s < len; ++s) {
+    int rc = step_fused(c, st, cur, other, dt);
+    if (rc) return rc;
+    std::swap(cur, other);
+  }
+  if (cur != U) {
+    hipError_t e = hipMemcpyAsync(U, cur, sizeof(double) * (size_t)c->ncells * c->nl, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "step copy");
+  }
+  return DG_OK;
+}
+
 int rk3_step(dg_ctx* c, hipStream_t st, double* U, double dt, double* U1 = nullptr, double* U2 = nullptr) {
+  if (!U1 && !U2) return rk3_steps(c, st, U, dt, 1);
   return rk3_step_to(c, st, U, U, dt, U1, U2);
 }
 
@@ -373,6 +420,32 @@ int dg_validate_desc(const dg_mesh_desc* desc) {
   return validate(desc);
 }
 
+// Whether the fused step kernel fits this problem (its three LDS tiles), and
+// the automatic choice (measured on MI355X): in 1D always (1.4-1.8x at 4096 to
+// 10^6 cells); in 2D while the mesh has at most one 16x16 tile per compute
+// unit (1.2-1.5x at 128^2 and 256^2), since with more tiles the recomputed
+// rings and the one-workgroup-per-CU occupancy of the fused kernel cost more
+// than the launches and HBM passes it saves (0.7-0.86x from 384^2 up).
+bool fused_fits(const dg_ctx* c) {
+  const int tx = c->d.dim == 1 ? dgk::kStepTile1D : dgk::kStepTile2D;
+  const int ty = c->d.dim == 1 ? 1 : dgk::kStepTile2D;
+  return sizeof(double) * (size_t)dgk::step_lds_doubles(c->d.dim, c->nl, tx, ty) <= (size_t)c->max_lds;
+}
+
+void resolve_fused(dg_ctx* c) {
+  if (c->fused_mode == 0 || !fused_fits(c)) {
+    c->fused = false;
+    return;
+  }
+  if (c->fused_mode == 1) {
+    c->fused = true;
+    return;
+  }
+  const long long t = c->d.dim == 1 ? dgk::kStepTile1D : dgk::kStepTile2D;
+  const long long tiles = c->d.dim == 1 ? (c->d.nx + t - 1) / t : ((c->d.nx + t - 1) / t) * ((c->d.ny + t - 1) / t);
+  c->fused = c->d.dim == 1 || tiles <= (long long)c->cus;
+}
+
 int dg_init_mesh(const dg_mesh_desc* desc, dg_ctx** out) {
   g_err[0] = 0;
   if (!out) return fail(DG_EINVAL, "out is NULL");
@@ -406,6 +479,9 @@ int dg_init_mesh(const dg_mesh_desc* desc, dg_ctx** out) {
     c->ty = 16;
     if (stage_lds_bytes(2, c->nl, 16, 16) > (size_t)c->max_lds) c->tx = c->ty = 8;
   }
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0) c->cus = cus;
+  resolve_fused(c);
   const size_t bytes = sizeof(double) * (size_t)c->ncells * c->nl;
   if ((e = hipMalloc(&c->U1, bytes)) != hipSuccess || (e = hipMalloc(&c->U2, bytes)) != hipSuccess) {
     dg_destroy(c);
@@ -515,7 +591,7 @@ static int run_graph(dg_ctx* c, double* U, double dt, int len, hipGraphExec_t* o
   hipError_t e = hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
   int rc = DG_OK;
-  for (int s = 0; s < len && rc == DG_OK; ++s) rc = rk3_step(c, c->capture, U, dt);
+  rc = rk3_steps(c, c->capture, U, dt, len);
   e = hipStreamEndCapture(c->capture, &g);
   if (rc) {
     if (g) (void)hipGraphDestroy(g);
@@ -602,6 +678,23 @@ int dg_set_tile(dg_ctx* c, int32_t tx, int32_t ty) {
   c->tx = tx;
   c->ty = c->d.dim == 2 ? ty : 1;
   drop_graphs(c);
+  return DG_OK;
+}
+
+int dg_set_fused(dg_ctx* c, int32_t mode) {
+  if (!c) return fail(DG_EINVAL, "ctx is NULL");
+  if (mode < -1 || mode > 1) return fail(DG_EINVAL, "mode must be -1 (automatic), 0 (off) or 1 (on)");
+  if (mode == 1 && !fused_fits(c))
+    return fail(DG_EUNSUPPORTED, "the fused step kernel's LDS tiles exceed the device limit for this degree");
+  c->fused_mode = mode;
+  resolve_fused(c);
+  drop_graphs(c);
+  return DG_OK;
+}
+
+int dg_get_fused(const dg_ctx* c, int32_t* active) {
+  if (!c || !active) return fail(DG_EINVAL, "NULL argument");
+  *active = c->fused ? 1 : 0;
   return DG_OK;
 }
 

@@ -614,6 +614,165 @@ __global__ void __launch_bounds__(DIM == 2 ? TX * TY : TX) stage_kernel(const St
 }
 
 // ---------------------------------------------------------------------------
+// Fused SSP-RK3 step: the three stages of eq. (ssp) in one launch.  A tile of
+// TX x TY cells (TY = 1 in 1D) loads U^n on itself and three rings of cells
+// around it (tile A); stage 1 evaluates U^(1) on the tile and two rings (tile
+// B), stage 2 U^(2) on the tile and one ring (tile C), stage 3 U^(n+1) on the
+// tile, straight to HBM.  Every cell value of every stage is computed with
+// the same per-cell arithmetic as the per-stage kernel, so the result is the
+// same bit for bit; the rings are recomputed by each tile that needs them.
+// Slots outside a non-periodic boundary hold the exterior state in every
+// stage, as in the per-stage kernel.
+// ---------------------------------------------------------------------------
+template <int DIM, int TX, int TY>
+struct StepGeom {
+  static constexpr int R = DIM == 2 ? TY : 1;
+  // tile with k rings: width, rows, slots, plane stride (odd)
+  template <int K>
+  struct T {
+    static constexpr int W = TX + 2 * K;
+    static constexpr int H = DIM == 2 ? TY + 2 * K : 1;
+    static constexpr int N = W * H;
+    static constexpr int S = N | 1;
+  };
+  using A = T<3>;
+  using B = T<2>;
+  using C = T<1>;
+  static constexpr int NT = DIM == 2 ? 2 * TX * TY : TX + 64;  // threads (= step_threads)
+};
+
+__host__ __device__ constexpr int step_threads(int dim, int tx, int ty) { return dim == 2 ? 2 * tx * ty : tx + 64; }
+
+__host__ __device__ inline int step_lds_doubles(int dim, int nl, int tx, int ty) {
+  int tot = 0;
+  for (int k = 1; k <= 3; ++k) {
+    const int w = tx + 2 * k, h = dim == 2 ? ty + 2 * k : 1;
+    tot += (w * h) | 1;
+  }
+  return nl * tot;
+}
+
+// Mesh cell of coordinates (gx, gy) before wrapping, any distance outside the
+// mesh: wrapped coordinates on periodic axes; false outside a non-periodic
+// boundary.  (In 1D the row is 0.)
+template <int DIM>
+__host__ __device__ inline bool step_cell(const StageArgs& A, int gx, int gy, int& wx, int& wy) {
+  const int nx = A.nx, ny = DIM == 2 ? A.ny : 1;
+  if (DIM == 1) gy = 0;
+  if (gx < 0 || gx >= nx) {
+    if (!A.per_x) return false;
+    gx %= nx;
+    if (gx < 0) gx += nx;
+  }
+  if (DIM == 2 && (gy < 0 || gy >= ny)) {
+    if (!A.per_y) return false;
+    gy %= ny;
+    if (gy < 0) gy += ny;
+  }
+  wx = gx;
+  wy = gy;
+  return true;
+}
+
+// Output slot o of the stage whose output tile has KO rings: its local
+// coordinates, the slot of the same cell in the input tile (KO + 1 rings) and
+// in tile A (3 rings), and its mesh coordinates before wrapping.
+template <int DIM, int TX, int TY, int KO>
+__host__ __device__ inline void step_slot(int o, int ix0, int iy0, int& islot, int& aslot, int& gx, int& gy) {
+  using G = StepGeom<DIM, TX, TY>;
+  using TO = typename G::template T<KO>;
+  using TI = typename G::template T<KO + 1>;
+  const int ox = o % TO::W, oy = o / TO::W;
+  gx = ix0 - KO + ox;
+  gy = DIM == 2 ? iy0 - KO + oy : 0;
+  if constexpr (DIM == 2) {
+    islot = (oy + 1) * TI::W + ox + 1;
+    aslot = (oy + 3 - KO) * G::A::W + ox + 3 - KO;
+  } else {
+    islot = ox + 1;
+    aslot = ox + 3 - KO;
+  }
+}
+
+// One stage of the fused step: for every cell of the output tile (KO rings)
+// evaluate the operator on the input tile (KO + 1 rings) and combine
+// a U^n + b (U^(k-1) + dt L); KO = 0 writes the tile's mesh cells to HBM.
+template <int DIM, int P, int FLUX, int MODE, int TX, int TY, int KO>
+__device__ inline void step_stage(const StageArgs& A, const double* tin, const double* ta, double* tout, int ix0,
+                                  int iy0, double a, double b) {
+  using G = StepGeom<DIM, TX, TY>;
+  using TI = typename G::template T<KO + 1>;
+  using TO = typename G::template T<KO>;
+  using C = Cell<DIM, P, FLUX, MODE, TI::S, TI::W>;
+  constexpr int NL = C::NL;
+  const int nx = A.nx, ny = DIM == 2 ? A.ny : 1;
+#pragma unroll 1
+  for (int o = threadIdx.x; o < TO::N; o += G::NT) {
+    int islot, aslot, gx, gy, wx, wy;
+    step_slot<DIM, TX, TY, KO>(o, ix0, iy0, islot, aslot, gx, gy);
+    if constexpr (KO == 0) {
+      if (gx >= nx || gy >= ny) continue;  // past a ragged edge
+    }
+    if (!step_cell<DIM>(A, gx, gy, wx, wy)) {
+      // outside a non-periodic boundary: the exterior state
+#pragma unroll
+      for (int j = 0; j < NL; ++j) tout[j * TO::S + o] = j == 0 ? A.bc : 0.0;
+      continue;
+    }
+    double c[NL], L[NL], gam;
+#pragma unroll
+    for (int j = 0; j < NL; ++j) c[j] = tin[j * TI::S + islot];
+    C::rhs(A, tin + islot, c, wx, wy, L, gam);
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+      double v = b * fma(A.dt, L[j], c[j]);
+      if (a != 0.0) v = fma(a, ta[j * G::A::S + aslot], v);
+      if constexpr (KO == 0)
+        A.out[((size_t)wy * nx + wx) * NL + j] = v;
+      else
+        tout[j * TO::S + o] = v;
+    }
+  }
+}
+
+// The fused step kernel.  Grid: (ceil(nx/TX), ceil(ny/TY)); StepGeom::NT
+// threads; LDS: step_lds_doubles.  A.uin = U^n, A.out = U^(n+1), two
+// different arrays (tiles run concurrently and read U^n of their neighbours).
+template <int DIM, int P, int FLUX, int MODE, int TX, int TY>
+__global__ void __launch_bounds__(step_threads(DIM, TX, TY)) step_kernel(const StageArgs A) {
+  using G = StepGeom<DIM, TX, TY>;
+  constexpr int NL = DIM == 1 ? P + 1 : (P + 1) * (P + 1);
+  extern __shared__ double lds[];
+  double* ta = lds;
+  double* tb = ta + NL * G::A::S;
+  double* tc = tb + NL * G::B::S;
+  const int ix0 = blockIdx.x * TX, iy0 = DIM == 2 ? blockIdx.y * TY : 0;
+  // U^n on the tile and three rings
+#pragma unroll 1
+  for (int o = threadIdx.x; o < G::A::N; o += G::NT) {
+    const int ox = o % G::A::W, oy = o / G::A::W;
+    int wx, wy;
+    double v[NL];
+    if (step_cell<DIM>(A, ix0 - 3 + ox, DIM == 2 ? iy0 - 3 + oy : 0, wx, wy)) {
+      const double* src = A.uin + ((size_t)wy * A.nx + wx) * NL;
+#pragma unroll
+      for (int j = 0; j < NL; ++j) v[j] = src[j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < NL; ++j) v[j] = j == 0 ? A.bc : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < NL; ++j) ta[j * G::A::S + o] = v[j];
+  }
+  __syncthreads();
+  step_stage<DIM, P, FLUX, MODE, TX, TY, 2>(A, ta, ta, tb, ix0, iy0, 0.0, 1.0);
+  __syncthreads();
+  step_stage<DIM, P, FLUX, MODE, TX, TY, 1>(A, tb, ta, tc, ix0, iy0, 0.75, 0.25);
+  __syncthreads();
+  step_stage<DIM, P, FLUX, MODE, TX, TY, 0>(A, tc, ta, nullptr, ix0, iy0, 1.0 / 3.0, 2.0 / 3.0);
+}
+
+// ---------------------------------------------------------------------------
 // Batched stage: many independent problems of one kernel class (dimension,
 // degree, flux, mode, tile) in one persistent launch.  Each workgroup walks
 // the tile list with a grid stride (the list order is the schedule); a tile

@@ -6,12 +6,16 @@
 namespace dgk {
 
 enum LaunchKind { LAUNCH_STAGE = 0, LAUNCH_PROJECT = 1, LAUNCH_LAMBDA = 2, LAUNCH_BATCH = 3,
-                  LAUNCH_ADJ_SENSOR = 4, LAUNCH_ADJ_GRAD = 5 };
+                  LAUNCH_ADJ_SENSOR = 4, LAUNCH_ADJ_GRAD = 5, LAUNCH_STEP = 6 };
+
+// the fused step kernel's tiles
+constexpr int kStepTile1D = 256;
+constexpr int kStepTile2D = 16;
 
 struct LaunchReq {
   int kind;
   int flux, mode;
-  StageArgs args;       // LAUNCH_STAGE, LAUNCH_LAMBDA
+  StageArgs args;       // LAUNCH_STAGE, LAUNCH_STEP, LAUNCH_LAMBDA
   const double* src;    // LAUNCH_PROJECT: nodal values; LAUNCH_LAMBDA: state
   double* dst;          // LAUNCH_PROJECT: coefficients; LAUNCH_LAMBDA: block maxima
   long long ncells;

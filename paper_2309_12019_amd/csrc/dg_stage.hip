@@ -41,6 +41,33 @@ hipError_t launch_stage_fm(const StageArgs& A, hipStream_t st) {
   }
 }
 
+template <int FLUX, int MODE>
+hipError_t launch_step_fm(const StageArgs& A, hipStream_t st) {
+  constexpr int NL = DGK_DIM == 1 ? DGK_P + 1 : (DGK_P + 1) * (DGK_P + 1);
+  constexpr int TX = DGK_DIM == 1 ? kStepTile1D : kStepTile2D;
+  constexpr int TY = DGK_DIM == 1 ? 1 : kStepTile2D;
+  using G = StepGeom<DGK_DIM, TX, TY>;
+  auto k = step_kernel<DGK_DIM, DGK_P, FLUX, MODE, TX, TY>;
+  const size_t lds = sizeof(double) * (size_t)step_lds_doubles(DGK_DIM, NL, TX, TY);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  dim3 grid((A.nx + TX - 1) / TX, DGK_DIM == 2 ? (A.ny + TY - 1) / TY : 1);
+  hipLaunchKernelGGL(k, grid, dim3(G::NT), lds, st, A);
+  return hipGetLastError();
+}
+
+template <int FLUX>
+hipError_t launch_step_f(int mode, const StageArgs& A, hipStream_t s) {
+  switch (mode) {
+    case MODE_DG: return launch_step_fm<FLUX, MODE_DG>(A, s);
+    case MODE_LO: return launch_step_fm<FLUX, MODE_LO>(A, s);
+    default: return launch_step_fm<FLUX, MODE_WENO>(A, s);
+  }
+}
+
 template <int FLUX, int MODE, int TX, int TY>
 hipError_t launch_batch_tile(const BatchStageArgs& B, int grid, hipStream_t st) {
   constexpr int NL = DGK_DIM == 1 ? DGK_P + 1 : (DGK_P + 1) * (DGK_P + 1);
@@ -141,6 +168,10 @@ extern "C" hipError_t DGK_CAT(dgk_launch, DGK_DIM, DGK_P)(const LaunchReq* r) {
     case LAUNCH_STAGE: {
       if (r->flux == FLUX_LINADV) return launch_stage_f<FLUX_LINADV>(r->mode, A, r->stream);
       return launch_stage_f<FLUX_BURGERS>(r->mode, A, r->stream);
+    }
+    case LAUNCH_STEP: {
+      if (r->flux == FLUX_LINADV) return launch_step_f<FLUX_LINADV>(r->mode, A, r->stream);
+      return launch_step_f<FLUX_BURGERS>(r->mode, A, r->stream);
     }
     case LAUNCH_BATCH: {
       if (r->flux == FLUX_LINADV) return launch_batch_f<FLUX_LINADV>(r);

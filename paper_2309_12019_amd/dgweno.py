@@ -62,6 +62,8 @@ EXPORTS = {
                                     ctypes.POINTER(ctypes.c_double)]),
     "dg_check_finite": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "dg_set_tile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
+    "dg_set_fused": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "dg_get_fused": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     "dg_get_tile": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_int32)]),
     "dg_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
@@ -257,6 +259,15 @@ class DG:
 
     def set_tile(self, tx: int, ty: int = 1) -> None:
         _check(self.lib.dg_set_tile(self.h, int(tx), int(ty)))
+
+    def set_fused(self, mode: int) -> None:
+        """Fused step kernel: -1 automatic, 0 off, 1 on (dg_set_fused)."""
+        _check(self.lib.dg_set_fused(self.h, int(mode)))
+
+    def fused(self) -> bool:
+        a = ctypes.c_int32()
+        _check(self.lib.dg_get_fused(self.h, ctypes.byref(a)))
+        return bool(a.value)
 
     def tile(self) -> Tuple[int, int]:
         a, b = ctypes.c_int32(), ctypes.c_int32()

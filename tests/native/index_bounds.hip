@@ -68,6 +68,74 @@ void check(int nx, int ny, int per_x, int per_y) {
       }
 }
 
+// The fused step kernel: tile A loads U^n on the tile and three rings (each
+// slot from the cell it stands for, wrapped or exterior); every stage's
+// output slot maps to the same mesh cell in its input tile and in tile A, its
+// face neighbours lie inside the input tile, and the last stage writes each
+// mesh cell of the tile exactly once.
+template <int DIM, int TX, int TY, int KO>
+void check_step_stage(const StageArgs& A, int ix0, int iy0, size_t ncells, int nl, int* written) {
+  using G = StepGeom<DIM, TX, TY>;
+  using TO = typename G::template T<KO>;
+  using TI = typename G::template T<KO + 1>;
+  for (int o = 0; o < TO::N; ++o) {
+    int islot, aslot, gx, gy, wx, wy;
+    step_slot<DIM, TX, TY, KO>(o, ix0, iy0, islot, aslot, gx, gy);
+    CHECK(islot >= 0 && islot < TI::N && aslot >= 0 && aslot < G::A::N, "step stage %d: slot out of range", KO);
+    // same mesh cell in the input tile and in tile A
+    const int ix_in = ix0 - (KO + 1) + islot % TI::W, iy_in = DIM == 2 ? iy0 - (KO + 1) + islot / TI::W : 0;
+    const int ix_a = ix0 - 3 + aslot % G::A::W, iy_a = DIM == 2 ? iy0 - 3 + aslot / G::A::W : 0;
+    CHECK(ix_in == gx && iy_in == gy && ix_a == gx && iy_a == gy, "step stage %d: slot maps to another cell", KO);
+    const int offs[4] = {-1, 1, -TI::W, TI::W};
+    for (int f = 0; f < 2 * DIM; ++f) {
+      const int nb = islot + offs[f];
+      CHECK(nb >= 0 && nb < TI::N, "step stage %d: neighbour slot out of the input tile", KO);
+      const int nx_ = nb % TI::W;
+      CHECK(DIM == 2 || (nx_ == islot % TI::W + (f ? 1 : -1)), "1D neighbour wraps a row");
+      if (DIM == 2 && f < 2) CHECK(nb / TI::W == islot / TI::W, "x neighbour in another row");
+    }
+    if (KO == 0 && (gx >= A.nx || gy >= (DIM == 2 ? A.ny : 1))) continue;
+    if (step_cell<DIM>(A, gx, gy, wx, wy)) {
+      CHECK(wx >= 0 && wx < A.nx && wy >= 0 && wy < (DIM == 2 ? A.ny : 1), "step: wrapped cell out of range");
+      if (KO == 0) {
+        const size_t cell = (size_t)wy * A.nx + wx;
+        CHECK(cell < ncells && (cell + 1) * nl <= ncells * nl, "step: output out of range");
+        if (cell < ncells) written[cell]++;
+      }
+    } else {
+      CHECK(KO > 0, "step: a tile cell inside the mesh classified as exterior");
+    }
+  }
+}
+
+template <int DIM, int TX, int TY>
+void check_step(int nx, int ny, int per_x, int per_y) {
+  using G = StepGeom<DIM, TX, TY>;
+  StageArgs A{};
+  A.nx = nx;
+  A.ny = DIM == 2 ? ny : 1;
+  A.per_x = per_x;
+  A.per_y = DIM == 2 ? per_y : 0;
+  const size_t ncells = (size_t)A.nx * A.ny;
+  static int written[600 * 600];
+  for (size_t e = 0; e < ncells; ++e) written[e] = 0;
+  const int gx_blocks = (nx + TX - 1) / TX, gy_blocks = DIM == 2 ? (ny + TY - 1) / TY : 1;
+  for (int by = 0; by < gy_blocks; ++by)
+    for (int bx = 0; bx < gx_blocks; ++bx) {
+      const int ix0 = bx * TX, iy0 = DIM == 2 ? by * TY : 0;
+      for (int o = 0; o < G::A::N; ++o) {
+        const int ox = o % G::A::W, oy = o / G::A::W;
+        int wx, wy;
+        if (step_cell<DIM>(A, ix0 - 3 + ox, DIM == 2 ? iy0 - 3 + oy : 0, wx, wy))
+          CHECK(wx >= 0 && wx < A.nx && wy >= 0 && wy < A.ny, "step: tile A load out of range (%d, %d)", wx, wy);
+      }
+      check_step_stage<DIM, TX, TY, 2>(A, ix0, iy0, ncells, 9, written);
+      check_step_stage<DIM, TX, TY, 1>(A, ix0, iy0, ncells, 9, written);
+      check_step_stage<DIM, TX, TY, 0>(A, ix0, iy0, ncells, 9, written);
+    }
+  for (size_t e = 0; e < ncells; ++e) CHECK(written[e] == 1, "step: cell %zu written %d times", e, written[e]);
+}
+
 template <int DIM, int TX, int TY>
 void sweep() {
   const int sizes[] = {1, 2, 3, 7, 8, 9, 15, 16, 17, 31, 63, 64, 65, 100, 255, 256, 257, 300, 513};
@@ -80,7 +148,19 @@ void sweep() {
         }
 }
 
+void sweep_step() {
+  const int sizes[] = {1, 2, 3, 5, 15, 16, 17, 31, 33, 64, 100, 257, 513};
+  for (int nx : sizes)
+    for (int px = 0; px < 2; ++px) {
+      check_step<1, kStepTile1D, 1>(nx, 1, px, 0);
+      for (int ny : sizes)
+        for (int py = 0; py < 2; ++py)
+          if ((size_t)nx * ny <= 600 * 600) check_step<2, kStepTile2D, kStepTile2D>(nx, ny, px, py);
+    }
+}
+
 int main() {
+  sweep_step();
   sweep<1, 256, 1>();
   sweep<1, 64, 1>();
   sweep<2, 16, 16>();
