@@ -250,13 +250,13 @@ def bench_adjoint(n=512, steps=400, ndir=32, nsnaps=None, seed=0):
         d /= d.norm()
         ad = float((grad * d).sum())
         row = {"ad": ad}
-        for tag, delta in (("1e-4", 1e-4 * umax), ("1e-6", 1e-6 * umax), ("1e-8", 1e-8 * umax)):
+        for tag, delta in (("1e-4", 1e-4 * umax), ("1e-6", 1e-6 * umax), ("1e-7", 1e-7 * umax), ("1e-8", 1e-8 * umax)):
             fd1 = dJ(d, delta) / (2 * delta)
             fd2 = dJ(d, delta / 2) / delta
             fd = (4 * fd2 - fd1) / 3
             row[tag] = abs(fd - ad) / abs(ad)
         rows.append(row)
-    for tag in ("1e-4", "1e-6", "1e-8"):
+    for tag in ("1e-4", "1e-6", "1e-7", "1e-8"):
         errs = [r[tag] for r in rows]
         res[f"fd_delta_{tag}_umax"] = {"directions": ndir, "max_rel_err": max(errs),
                                        "median_rel_err": float(np.median(errs)),
