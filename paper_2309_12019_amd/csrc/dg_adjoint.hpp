@@ -736,7 +736,7 @@ __global__ void __launch_bounds__(DIM == 2 ? TX * TY : TX) adj_sensor_kernel(con
   }
 #pragma unroll
   for (int j = 0; j < NL; ++j) lds[j * S + sc] = c[j];
-  __syncthreads();
+  tile_barrier();
   if (!active) return;
   AC::sensor_adjoint(A, lds + sc, c, gx, gy, v, Ad.z + cell, (size_t)A.nx * (DIM == 2 ? A.ny : 1));
 }
@@ -772,7 +772,7 @@ __global__ void __launch_bounds__(DIM == 2 ? TX * TY : TX) adj_grad_kernel(const
     lds[j * S + sc] = c[j];
     ldsv[j * S + sc] = v[j];
   }
-  __syncthreads();
+  tile_barrier();
   if (!active) return;
   double Gr[NL];
   AC::grad(Ad, lds + sc, ldsv + sc, c, v, gx, gy, cell, Gr);

@@ -66,6 +66,18 @@ __host__ __device__ inline int tile_lds_doubles(int dim, int nl, int tx, int ty)
   return nl * (ns | 1);   // the tile with its face halo
 }
 
+// Workgroup barrier around LDS traffic between lanes.  For workgroups of a
+// single wave (8x8 and 64-cell tiles) the compiler removes s_barrier, and with
+// it the ordering of one lane's LDS accesses relative to another lane's: it
+// may move a lane's LDS reads of its neighbours' slots above the writes of
+// those slots, which it sees as different addresses.  The asm statement is a
+// full compiler memory barrier and waits for the wave's LDS operations, so
+// LDS writes before it and reads after it keep their order in every case.
+__device__ inline void tile_barrier() {
+  __syncthreads();
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+}
+
 // x mod n for x in [-1, n + tile]: cheap for the common single wrap
 __host__ __device__ inline int wrap_index(int x, int n) {
   if (x < 0) return x + n;
@@ -581,7 +593,7 @@ __device__ inline void stage_tile(const StageArgs& A, double* lds, int ix0, int 
   if (halo) load_slot<DIM, NL, S>(A, lds, hs, hgx, hgy);
 #pragma unroll
   for (int j = 0; j < NL; ++j) lds[j * S + sc] = c[j];
-  __syncthreads();
+  tile_barrier();
   if (active) {
     double L[NL], gam;
     C::rhs(A, lds + sc, c, gx, gy, L, gam);
@@ -764,11 +776,11 @@ __global__ void __launch_bounds__(step_threads(DIM, TX, TY)) step_kernel(const S
 #pragma unroll
     for (int j = 0; j < NL; ++j) ta[j * G::A::S + o] = v[j];
   }
-  __syncthreads();
+  tile_barrier();
   step_stage<DIM, P, FLUX, MODE, TX, TY, 2>(A, ta, ta, tb, ix0, iy0, 0.0, 1.0);
-  __syncthreads();
+  tile_barrier();
   step_stage<DIM, P, FLUX, MODE, TX, TY, 1>(A, tb, ta, tc, ix0, iy0, 0.75, 0.25);
-  __syncthreads();
+  tile_barrier();
   step_stage<DIM, P, FLUX, MODE, TX, TY, 0>(A, tc, ta, nullptr, ix0, iy0, 1.0 / 3.0, 2.0 / 3.0);
 }
 
@@ -811,7 +823,7 @@ __global__ void __launch_bounds__(DIM == 2 ? TX * TY : TX) batch_stage_kernel(co
     A.b = B.b;
     A.rhs_only = 0;
     stage_tile<DIM, P, FLUX, MODE, TX, TY>(A, lds, tl.ix0, tl.iy0);
-    __syncthreads();  // the next tile reuses LDS
+    tile_barrier();  // the next tile reuses LDS
   }
 }
 
@@ -917,10 +929,10 @@ __global__ void __launch_bounds__(256) lambda_kernel(const StageArgs A, const do
     }
   }
   red[threadIdx.x] = lam;
-  __syncthreads();
+  tile_barrier();
   for (int s = blockDim.x / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
-    __syncthreads();
+    tile_barrier();
   }
   if (threadIdx.x == 0) block_max[blockIdx.x] = red[0];
 }

@@ -154,3 +154,40 @@ def test_batch_argument_errors():
     bad.p = 7
     with pytest.raises(dgweno.DGError):
         dgweno.Batch([bad])
+
+
+@pytest.mark.parametrize("p", [2, 3, 4])
+def test_batch_one_wave_tiles_match_single_runs(p):
+    """2D rotation problems of one degree in a batch on 8x8 tiles (one wave
+    per workgroup) advance exactly as alone, with
+    the rotation centre off the grid lines (faces where v.n changes sign) and
+    a rough state; the batch runs twice (a run-to-run difference would show a
+    race or a stale register)."""
+    _note(f"[batch] one-wave tiles p={p}")
+    dgweno = _dg()
+    ws = []
+    for i, n in enumerate((40, 34, 23, 17)):
+        w = inputs.rot2d(n, p, seed=11 + i, steps=4)
+        w.cy = 0.4537
+        ws.append(w)
+    B = dgweno.Batch.from_workloads(ws)
+    arena = B.empty()
+    _initial(ws, B, arena)
+    gen = torch.Generator(device=arena.device).manual_seed(5)
+    arena += 0.02 * torch.randn(arena.shape, generator=gen, device=arena.device, dtype=arena.dtype)
+    U0 = arena.clone()
+    singles = []
+    for w, v in zip(ws, B.views(U0)):
+        g = dgweno.DG.from_workload(w)
+        g.set_fused(0)
+        U = v.clone()
+        g.run(U, w.dt(), 4)
+        singles.append(U)
+    B.set_schedule(0, 8, 8, 1, 0)
+    dts = [w.dt() for w in ws]
+    for _ in range(2):
+        arena.copy_(U0)
+        B.run(arena, dts, 4)
+        torch.cuda.synchronize()
+        for w, v, r in zip(ws, B.views(arena), singles):
+            assert torch.equal(v, r), w.name

@@ -174,20 +174,31 @@ def test_run_equals_repeated_step_bitwise():
 
 
 @pytest.mark.parametrize("kind", ["rot2d", "burgers2d", "adv1d"])
-def test_tile_shape_independence(kind):
-    """Per-cell arithmetic does not depend on the workgroup tile."""
-    _note(f"[tiles] {kind}")
-    w = _mesh(kind, 2, 2, n1=1000, n2=(72, 40))
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_tile_shape_independence(kind, p):
+    """Per-cell arithmetic does not depend on the workgroup tile (one-wave 8x8
+    and 64-cell tiles included), on a rough state that switches the sensor on
+    and, for the rotation, with faces on which v.n changes sign (the centre of
+    rotation off the grid lines), where the LLF flux takes the quadrature
+    branch."""
+    _note(f"[tiles] {kind} p={p}")
+    w = _mesh(kind, p, 2, n1=1000, n2=(72, 40))
+    if kind == "rot2d":
+        w.cy = 0.4537
     g = _dg().DG.from_workload(w)
+    g.set_fused(0)
     U0 = g.initial_state(w)
+    gen = torch.Generator(device=U0.device).manual_seed(3)
+    U0 = U0 + 0.02 * U0.abs().max() * torch.randn(U0.shape, generator=gen, device=U0.device, dtype=U0.dtype)
     outs = []
     tiles = [(256, 1), (64, 1)] if w.dim == 1 else [(16, 16), (8, 8)]
     for tx, ty in tiles:
         g.set_tile(tx, ty)
-        U = U0.clone()
-        g.run(U, w.dt(), 5)
-        L = g.rhs(U)
-        outs.append((U, L))
+        for _ in range(2):
+            U = U0.clone()
+            g.run(U, w.dt(), 5)
+            L = g.rhs(U)
+            outs.append((U, L))
     torch.cuda.synchronize()
     for U, L in outs[1:]:
         assert torch.equal(U, outs[0][0]) and torch.equal(L, outs[0][1])
