@@ -269,12 +269,17 @@ STAGE_SOURCES = ("dg_kernels.hpp", "dg_tables.hpp", "dg_stage.hip")
 
 
 def stage_source_digest():
-    """SHA-256 over the sources the stage kernel is compiled from."""
+    """SHA-256 over the code (comments and blank space removed) of the sources
+    the stage kernels are compiled from."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for name in STAGE_SOURCES:
-        with open(os.path.join(ROOT, "paper_2309_12019_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_2309_12019_amd", "csrc", name)) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()
 
 

@@ -1,10 +1,12 @@
-// Device code: the fused per-stage kernel of the dissipative-WENO RKDG scheme.
+// Device code of the dissipative-WENO RKDG scheme: the per-stage kernel, the
+// fused SSP-RK3 step kernel, the batched stage kernel and the projection and
+// wave-speed kernels.
 //
-// One thread owns one cell.  A workgroup owns a tile of tx x ty cells; it
-// stages the tile and its one-cell face halo from HBM into LDS (coalesced,
-// cell-major in HBM, transposed to coefficient-major in LDS so that lanes
-// reading the same coefficient of consecutive cells hit consecutive banks),
-// evaluates for each cell
+// One thread owns one cell.  A workgroup owns a tile of tx x ty cells; each
+// thread loads its own cell's coefficients into registers (cell-major in HBM)
+// and publishes them into a coefficient-major LDS tile (lanes reading one
+// coefficient of consecutive cells hit consecutive banks), the first threads
+// load the one-cell face halo, and each thread evaluates for its cell
 //   * the HWENO reconstruction and smoothness sensor gamma_e (Sec. 4),
 //   * the volume integral of eq. (weak2) by sum factorisation,
 //   * the four (two in 1D) face integrals with the LLF flux (Sec. 2),
@@ -12,7 +14,8 @@
 //   * the inverse of the (diagonal) mass matrix,
 // and writes either dU/dt or the SSP-RK3 stage combination (eq. ssp)
 //   out = a U^n + b (U^(k-1) + dt dU/dt)
-// back through LDS with coalesced stores.
+// straight to HBM.  The fused step kernel runs the three stages of a step on
+// shrinking rings of a larger tile held in LDS.
 #pragma once
 
 #include <hip/hip_runtime.h>
