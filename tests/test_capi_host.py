@@ -103,3 +103,25 @@ def test_checkpoint_recomputation_decreases_with_slots(lib):
     # binomial bound: with s slots and t sweeps, C(s+t, s) steps are reversible
     # with at most t recomputations of each step
     assert dgweno.revolve_stats(200, 8)["recomputed_steps"] <= 3 * 200
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    """The product path has no CPU fallback: a missing library is an error."""
+    from paper_2309_12019_amd import dgweno
+    saved = dgweno._lib
+    dgweno._lib = None
+    try:
+        with pytest.raises(ImportError):
+            dgweno.load(str(tmp_path / "libdgweno_missing.so"))
+    finally:
+        dgweno._lib = saved
+
+
+def test_product_code_does_not_import_the_oracle():
+    """Only tests, the smoke check and the benchmark's CPU-baseline leg may
+    use the oracle; the package itself never does."""
+    pkg = os.path.join(ROOT, "paper_2309_12019_amd")
+    for name in os.listdir(pkg):
+        if name.endswith(".py"):
+            text = open(os.path.join(pkg, name)).read()
+            assert not re.search(r"^\s*(import|from)\s+oracle", text, re.M), name
