@@ -28,7 +28,22 @@ def _cases():
     for p in (1, 2, 3, 4):
         out.append(("adv1d_300", lambda p=p: inputs.adv1d(300, p)))
         out.append(("burgers1d_5", lambda p=p: inputs.burgers1d(5, p)))
+    def adv1d_inflow(p):
+        w = inputs.adv1d(77, p)
+        w.periodic_x = False
+        w.bc_value = 0.3
+        return w
+
+    def burgers2d_mixed(p):
+        w = inputs.burgers2d(29, p, seed=4, ny=19, steps=1)
+        w.periodic_y = False
+        w.bc_value = -0.1
+        return w
+
+    for p in (1, 2, 3, 4):
+        out.append(("adv1d_77_inflow", lambda p=p: adv1d_inflow(p)))
     for p in (1, 2, 3):
+        out.append(("burgers2d_29x19_periodic_x_only", lambda p=p: burgers2d_mixed(p)))
         def rot(p=p):
             w = inputs.rot2d(40, p, seed=1, ny=36)
             w.cy = 0.45
