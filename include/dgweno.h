@@ -150,7 +150,10 @@ int dg_get_tile(const dg_ctx* ctx, int32_t* tx, int32_t* ty);
  * in 1D, and in 2D for meshes of at most one 16x16 tile per compute unit,
  * where per-stage launches are latency bound), 0 off, 1 on.  Errors:
  * DG_EINVAL for another mode, DG_EUNSUPPORTED for mode 1 when the three
- * tiles exceed LDS (2D degree 4).  dg_get_fused writes 1 if steps use it. */
+ * tiles exceed LDS (2D degree 4).  dg_get_fused writes 1 if steps use it.
+ * Mode 0 also makes the adjoint (below) launch its two passes of every stage
+ * separately instead of sharing launches between consecutive stages; the
+ * result is bitwise the same either way. */
 int dg_set_fused(dg_ctx* ctx, int32_t mode);
 int dg_get_fused(const dg_ctx* ctx, int32_t* active);
 
@@ -167,7 +170,8 @@ const char* dg_last_error(void);
  * the sensor min(1, ratio)^q and its threshold, lambda_e and the LLF wave
  * speed; where a max/min switches the derivative of the active branch is
  * used (ties: split evenly).  The first adjoint call on a context allocates
- * three state-sized buffers and one sensor-record buffer.
+ * two state-sized buffers and two sensor-record buffers (DG_EUNSUPPORTED if
+ * the adjoint kernels' tile exceeds LDS).
  * ------------------------------------------------------------------------ */
 
 /* out = J(U)^T v: the transpose Jacobian of dU/dt = L(U) (dg_rhs) applied to

@@ -30,6 +30,8 @@ struct AdjArgs {
   const double* X;    // optional [cells][NL]
   const double* Y;    // optional [cells][NL]
   double alpha, beta, g1, g2;
+  const double* unext;  // pass B + A launch: the state whose sensor is reversed next
+  double* znext;        // pass B + A launch: its records (not the buffer z)
 };
 
 // Doubles per cell in the sensor record (the layout is ZRec's).
@@ -281,6 +283,9 @@ struct AdjCell {
 
   // Pass A: the sensor of one cell, forward and reverse, seeded with
   // gamma_bar = -(lambda / p) g . Khat c.  Writes the cell's record.
+  // SB: scheduling barriers between the candidates (one candidate live at a
+  // time; off where the kernel's register budget is set by other work).
+  template <bool SB>
   __device__ static inline void sensor_adjoint(const StageArgs& A, const double* b, const double (&c)[NL], int ix,
                                                int iy, const double (&v)[NL], double* zrec, size_t zs) {
     bool has[NF];
@@ -301,7 +306,7 @@ struct AdjCell {
       beta[f + 1] = C::qform(cd);
       al[f + 1] = has[f] ? A.wnb * C::weight(A, beta[f + 1]) : 0.0;
       m += has[f];
-      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (SB) __builtin_amdgcn_sched_barrier(0);
     }
     al[0] = (1.0 - m * A.wnb) * C::weight(A, beta[0]);
     double ssum = 0.0;
@@ -321,7 +326,7 @@ struct AdjCell {
       C::template cand_any<0>(f, b, cd);
 #pragma unroll
       for (int j = 1; j < NL; ++j) d[j] = fma(om[f + 1], cd[j], d[j]);
-      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (SB) __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int j = 1; j < NL; ++j) d[j] = c[j] - d[j];
@@ -378,7 +383,7 @@ struct AdjCell {
 #pragma unroll
       for (int j = 1; j < NL; ++j) t = fma(db[j], cd[j], t);
       omb[f + 1] = -t;
-      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (SB) __builtin_amdgcn_sched_barrier(0);
     }
     double dot = 0.0;
 #pragma unroll
@@ -711,6 +716,21 @@ __device__ inline void load_cell_v(const AdjArgs& Ad, int gx, int gy, double (&v
   }
 }
 
+// The coefficients of the cell at (gx, gy) before wrapping in the state U, or
+// the exterior state outside a non-periodic boundary.
+template <int DIM, int NL>
+__device__ inline void load_cell_at(const StageArgs& A, const double* U, int gx, int gy, double (&v)[NL]) {
+  size_t cell;
+  if (slot_cell<DIM>(A, gx, gy, cell)) {
+    const double* src = U + cell * NL;
+#pragma unroll
+    for (int j = 0; j < NL; ++j) v[j] = src[j];
+  } else {
+#pragma unroll
+    for (int j = 0; j < NL; ++j) v[j] = j == 0 ? A.bc : 0.0;
+  }
+}
+
 // Pass A kernel: sensor records.  LDS: NL * S doubles (state tile + halo).
 // Each thread keeps its own cell's coefficients and cotangent in registers
 // and publishes the coefficients for its neighbours.
@@ -738,7 +758,7 @@ __global__ void __launch_bounds__(DIM == 2 ? TX * TY : TX) adj_sensor_kernel(con
   for (int j = 0; j < NL; ++j) lds[j * S + sc] = c[j];
   tile_barrier();
   if (!active) return;
-  AC::sensor_adjoint(A, lds + sc, c, gx, gy, v, Ad.z + cell, (size_t)A.nx * (DIM == 2 ? A.ny : 1));
+  AC::template sensor_adjoint<true>(A, lds + sc, c, gx, gy, v, Ad.z + cell, (size_t)A.nx * (DIM == 2 ? A.ny : 1));
 }
 
 // Pass B kernel: J^T v and the combination.  LDS: 2 * NL * S doubles (state
@@ -785,6 +805,76 @@ __global__ void __launch_bounds__(DIM == 2 ? TX * TY : TX) adj_grad_kernel(const
     if (Ad.Y) o = fma(Ad.g2, Ad.Y[cell * NL + j], o);
     dst[j] = o;
   }
+}
+
+// Pass B of one RK stage followed by pass A of the stage before it, in one
+// launch: out = alpha v + beta J(U)^T v + g1 X + g2 Y with U = Ad.s.uin, then
+// the sensor records of U' = Ad.unext seeded with this cell's out (the
+// cotangent the next pass B takes as v), written to Ad.znext.  Pass A needs
+// the seed of its own cell only, so no other tile's result is waited for.
+// The records read (Ad.z) and written (Ad.znext) are different buffers.
+// LDS as pass B's; the state plane is reloaded with U' once pass B is done.
+template <int DIM, int P, int FLUX, int MODE, int TX, int TY>
+__global__ void __launch_bounds__(DIM == 2 ? TX * TY : TX) adj_grad_sensor_kernel(const AdjArgs Ad) {
+  using G = TileGeom<DIM, TX, TY>;
+  using AC = AdjCell<DIM, P, FLUX, MODE, G::S, G::W>;
+  constexpr int NL = AC::NL, S = G::S;
+  extern __shared__ double lds[];
+  double* ldsv = lds + NL * S;
+  const StageArgs& A = Ad.s;
+  const int ix0 = blockIdx.x * TX, iy0 = DIM == 2 ? blockIdx.y * TY : 0;
+  const int t = threadIdx.x;
+  int sc, gx, gy, hs, hgx, hgy;
+  const bool halo = tile_slots<DIM, TX, TY>(t, ix0, iy0, sc, gx, gy, hs, hgx, hgy);
+  const bool active = gx < A.nx && gy < (DIM == 2 ? A.ny : 1);
+  const size_t cell = (size_t)gy * A.nx + gx;
+  double c[NL], v[NL];
+  load_cell<DIM, NL>(A, gx, gy, c);
+  load_cell_v<DIM, NL>(Ad, gx, gy, v);
+  if (halo) {
+    double hv[NL];
+    load_slot<DIM, NL, S>(A, lds, hs, hgx, hgy);
+    load_cell_v<DIM, NL>(Ad, hgx, hgy, hv);
+#pragma unroll
+    for (int j = 0; j < NL; ++j) ldsv[j * S + hs] = hv[j];
+  }
+#pragma unroll
+  for (int j = 0; j < NL; ++j) {
+    lds[j * S + sc] = c[j];
+    ldsv[j * S + sc] = v[j];
+  }
+  // U' of the cell and of its halo slot, loaded now so that the loads
+  // overlap pass B
+  double cn[NL], hn[NL];
+  load_cell_at<DIM, NL>(A, Ad.unext, gx, gy, cn);
+  if (halo) load_cell_at<DIM, NL>(A, Ad.unext, hgx, hgy, hn);
+  tile_barrier();
+  double o[NL];
+  if (active) {
+    double Gr[NL];
+    AC::grad(Ad, lds + sc, ldsv + sc, c, v, gx, gy, cell, Gr);
+    double* dst = Ad.out + cell * NL;
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+      double oj = Ad.beta * Gr[j];
+      if (Ad.alpha != 0.0) oj = fma(Ad.alpha, ldsv[j * S + sc], oj);
+      if (Ad.X) oj = fma(Ad.g1, Ad.X[cell * NL + j], oj);
+      if (Ad.Y) oj = fma(Ad.g2, Ad.Y[cell * NL + j], oj);
+      dst[j] = oj;
+      o[j] = oj;
+    }
+  }
+  tile_barrier();  // every thread is done with the state plane
+#pragma unroll
+  for (int j = 0; j < NL; ++j) lds[j * S + sc] = cn[j];
+  if (halo) {
+#pragma unroll
+    for (int j = 0; j < NL; ++j) lds[j * S + hs] = hn[j];
+  }
+  tile_barrier();
+  if (active)
+    AC::template sensor_adjoint<false>(A, lds + sc, cn, gx, gy, o, Ad.znext + cell,
+                                       (size_t)A.nx * (DIM == 2 ? A.ny : 1));
 }
 
 }  // namespace dgk

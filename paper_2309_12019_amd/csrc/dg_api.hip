@@ -71,7 +71,9 @@ struct dg_ctx {
   // adjoint buffers, allocated on first use
   double* A1 = nullptr;   // cotangent of U^(2)
   double* A2 = nullptr;   // cotangent of U^(1)
-  double* Z = nullptr;    // sensor records
+  double* Zmem = nullptr;  // both record buffers (one allocation)
+  double* Z = nullptr;     // sensor records
+  double* Z2 = nullptr;    // second record buffer: launches that read one set and write another
 };
 
 namespace {
@@ -247,32 +249,44 @@ int zrec_size(int dim, int nl) { return dgk::zrec_doubles(dim, nl); }
 
 int ensure_adjoint(dg_ctx* c) {
   if (c->A1) return DG_OK;
+  // the adjoint kernels' tiles hold the state and the cotangent
+  const int atx = c->d.dim == 2 ? dgk::kAdjTileX : c->tx, aty = c->d.dim == 2 ? dgk::kAdjTileY : 1;
+  const size_t alds = 2 * sizeof(double) * (size_t)dgk::tile_lds_doubles(c->d.dim, c->nl, atx, aty);
+  if (alds > (size_t)c->max_lds)
+    return fail(DG_EUNSUPPORTED, "the adjoint tile needs %zu bytes of LDS (limit %d)", alds, c->max_lds);
   const size_t n = (size_t)c->ncells * c->nl;
   const size_t nz = (size_t)c->ncells * zrec_size(c->d.dim, c->nl);
   hipError_t e;
   if ((e = hipMalloc(&c->A1, n * sizeof(double))) != hipSuccess ||
       (e = hipMalloc(&c->A2, n * sizeof(double))) != hipSuccess ||
-      (e = hipMalloc(&c->Z, nz * sizeof(double))) != hipSuccess) {
+      (e = hipMalloc(&c->Zmem, 2 * nz * sizeof(double))) != hipSuccess) {
     if (c->A1) (void)hipFree(c->A1);
     if (c->A2) (void)hipFree(c->A2);
     c->A1 = c->A2 = nullptr;
-    c->Z = nullptr;
+    c->Zmem = c->Z = c->Z2 = nullptr;
     return fail(DG_ENOMEM, "adjoint buffers: %s", hipGetErrorString(e));
   }
+  c->Z = c->Zmem;
+  c->Z2 = c->Zmem + nz;
   return DG_OK;
 }
 
-// out = alpha v + beta J(U)^T v + g1 X + g2 Y
-int adjoint_stage(dg_ctx* c, hipStream_t st, const double* U, const double* v, double* out, double alpha,
-                  double beta, const double* X, double g1, const double* Y, double g2) {
+// One adjoint launch (kind: pass A, pass B, or pass B + the next pass A):
+// records z of U seeded with v (pass A); out = alpha v + beta J(U)^T v +
+// g1 X + g2 Y from the records z (pass B); then the records znext of unext
+// seeded with out (pass B + A).
+int adj_launch(dg_ctx* c, hipStream_t st, int kind, const double* U, const double* v, double* z, double* out,
+               double alpha, double beta, const double* X, double g1, const double* Y, double g2,
+               const double* unext = nullptr, double* znext = nullptr) {
   LaunchReq r{};
+  r.kind = kind;
   r.flux = c->d.flux;
   r.mode = c->d.mode;
   r.stream = st;
   r.adj.s = base_args(c);
   r.adj.s.uin = U;
   r.adj.v = v;
-  r.adj.z = c->Z;
+  r.adj.z = z;
   r.adj.out = out;
   r.adj.X = X;
   r.adj.Y = Y;
@@ -280,20 +294,38 @@ int adjoint_stage(dg_ctx* c, hipStream_t st, const double* U, const double* v, d
   r.adj.beta = beta;
   r.adj.g1 = g1;
   r.adj.g2 = g2;
-  hipError_t e;
-  if (c->d.mode == DG_MODE_WENO) {
-    r.kind = dgk::LAUNCH_ADJ_SENSOR;
-    if ((e = c->launch(&r)) != hipSuccess) return hip_fail(e, "adjoint sensor launch");
-  }
-  r.kind = dgk::LAUNCH_ADJ_GRAD;
-  if ((e = c->launch(&r)) != hipSuccess) return hip_fail(e, "adjoint launch");
+  r.adj.unext = unext;
+  r.adj.znext = znext;
+  hipError_t e = c->launch(&r);
+  if (e != hipSuccess) return hip_fail(e, "adjoint launch");
   return DG_OK;
 }
 
+// out = alpha v + beta J(U)^T v + g1 X + g2 Y (pass A, when the operator has a
+// sensor, then pass B)
+int adjoint_stage(dg_ctx* c, hipStream_t st, const double* U, const double* v, double* out, double alpha,
+                  double beta, const double* X, double g1, const double* Y, double g2) {
+  int rc;
+  if (c->d.mode == DG_MODE_WENO &&
+      (rc = adj_launch(c, st, dgk::LAUNCH_ADJ_SENSOR, U, v, c->Z, nullptr, 0, 0, nullptr, 0, nullptr, 0)))
+    return rc;
+  return adj_launch(c, st, dgk::LAUNCH_ADJ_GRAD, U, v, c->Z, out, alpha, beta, X, g1, Y, g2);
+}
+
+// Whether the adjoint runs pass B of a stage and pass A of the stage before
+// it in one launch (the stabilised operator; switched off with the fused
+// step kernel, for comparison).
+bool adj_fused(const dg_ctx* c) { return c->d.mode == DG_MODE_WENO && c->fused_mode != 0; }
+
 // lam_in = (d step(Un) / d Un)^T lam_out for eq. (ssp).  The stage states
 // U^(1), U^(2) are recomputed from Un unless given (S1, S2).
+// With adj_fused: `zpend` says that the records of U^(2) seeded with lam_out
+// are already in c->Z (written by the previous adjoint step's last launch);
+// `next_S2`, when given, is U^(2) of the step reversed next, whose records
+// (seeded with lam_in) the last launch writes for that step.
 int rk3_adjoint(dg_ctx* c, hipStream_t st, const double* Un, double dt, const double* lam_out, double* lam_in,
-                const double* S1 = nullptr, const double* S2 = nullptr) {
+                const double* S1 = nullptr, const double* S2 = nullptr, bool zpend = false,
+                const double* next_S2 = nullptr) {
   int rc;
   if (!S1 || !S2) {
     if ((rc = stage(c, st, Un, Un, c->U1, nullptr, 0.0, 1.0, dt, 0))) return rc;
@@ -302,12 +334,32 @@ int rk3_adjoint(dg_ctx* c, hipStream_t st, const double* Un, double dt, const do
     S2 = c->U2;
   }
   const double a2 = 0.75, b2 = 0.25, a3 = 1.0 / 3.0, b3 = 2.0 / 3.0;
-  // stage 3: U = a3 Un + b3 (U2 + dt L(U2))  ->  lam_U2 = b3 mu + b3 dt J(U2)^T mu
-  if ((rc = adjoint_stage(c, st, S2, lam_out, c->A1, b3, b3 * dt, nullptr, 0, nullptr, 0))) return rc;
-  // stage 2: U2 = a2 Un + b2 (U1 + dt L(U1))
-  if ((rc = adjoint_stage(c, st, S1, c->A1, c->A2, b2, b2 * dt, nullptr, 0, nullptr, 0))) return rc;
-  // stage 1: U1 = Un + dt L(Un); lam_n = lam_U1 + dt J(Un)^T lam_U1 + a2 lam_U2 + a3 mu
-  return adjoint_stage(c, st, Un, c->A2, lam_in, 1.0, dt, c->A1, a2, lam_out, a3);
+  if (!adj_fused(c)) {
+    // stage 3: U = a3 Un + b3 (U2 + dt L(U2))  ->  lam_U2 = b3 mu + b3 dt J(U2)^T mu
+    if ((rc = adjoint_stage(c, st, S2, lam_out, c->A1, b3, b3 * dt, nullptr, 0, nullptr, 0))) return rc;
+    // stage 2: U2 = a2 Un + b2 (U1 + dt L(U1))
+    if ((rc = adjoint_stage(c, st, S1, c->A1, c->A2, b2, b2 * dt, nullptr, 0, nullptr, 0))) return rc;
+    // stage 1: U1 = Un + dt L(Un); lam_n = lam_U1 + dt J(Un)^T lam_U1 + a2 lam_U2 + a3 mu
+    return adjoint_stage(c, st, Un, c->A2, lam_in, 1.0, dt, c->A1, a2, lam_out, a3);
+  }
+  using dgk::LAUNCH_ADJ_GRAD;
+  using dgk::LAUNCH_ADJ_GRAD_SENSOR;
+  using dgk::LAUNCH_ADJ_SENSOR;
+  // the same three stage adjoints, each pass B sharing a launch with the pass
+  // A of the stage before it (records alternate between c->Z and c->Z2)
+  if (!zpend && (rc = adj_launch(c, st, LAUNCH_ADJ_SENSOR, S2, lam_out, c->Z, nullptr, 0, 0, nullptr, 0, nullptr, 0)))
+    return rc;
+  if ((rc = adj_launch(c, st, LAUNCH_ADJ_GRAD_SENSOR, S2, lam_out, c->Z, c->A1, b3, b3 * dt, nullptr, 0, nullptr, 0,
+                       S1, c->Z2)))
+    return rc;
+  if ((rc = adj_launch(c, st, LAUNCH_ADJ_GRAD_SENSOR, S1, c->A1, c->Z2, c->A2, b2, b2 * dt, nullptr, 0, nullptr, 0,
+                       Un, c->Z)))
+    return rc;
+  if (!next_S2) return adj_launch(c, st, LAUNCH_ADJ_GRAD, Un, c->A2, c->Z, lam_in, 1.0, dt, c->A1, a2, lam_out, a3);
+  rc = adj_launch(c, st, LAUNCH_ADJ_GRAD_SENSOR, Un, c->A2, c->Z, lam_in, 1.0, dt, c->A1, a2, lam_out, a3, next_S2,
+                  c->Z2);
+  std::swap(c->Z, c->Z2);  // the next step finds its first records in c->Z
+  return rc;
 }
 
 // ---- binomial checkpointing (revolve-style) --------------------------------
@@ -380,6 +432,24 @@ size_t rv_split(const std::vector<RvAction>& a) {
 void drop_graphs(dg_ctx* c) {
   for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
   c->graphs.clear();
+}
+
+// Steps whose stage states the forward sweep records: every step advanced
+// before the first reverse action (the step index of each slot is tracked
+// through the stores and restores), and the final step to U^N.
+std::vector<char> rv_stage_steps(const std::vector<RvAction>& a, int nsteps, int nsnaps) {
+  std::vector<char> have(nsteps, 0);
+  std::vector<int> slot_step(nsnaps + 1, 0);
+  const size_t split = rv_split(a);
+  int cur = 0;
+  for (size_t i = 0; i < split; ++i) {
+    if (a[i].op == RV_RESTORE) cur = slot_step[a[i].a];
+    if (a[i].op == RV_STORE) slot_step[a[i].a] = cur;
+    if (a[i].op == RV_ADVANCE)
+      for (int k = 0; k < a[i].a; ++k) have[cur++] = 1;
+  }
+  have[nsteps - 1] = 1;
+  return have;
 }
 
 }  // namespace
@@ -509,7 +579,7 @@ void dg_destroy(dg_ctx* c) {
   if (c->red) (void)hipFree(c->red);
   if (c->A1) (void)hipFree(c->A1);
   if (c->A2) (void)hipFree(c->A2);
-  if (c->Z) (void)hipFree(c->Z);
+  if (c->Zmem) (void)hipFree(c->Zmem);
   if (c->capture) (void)hipStreamDestroy(c->capture);
   delete c;
 }
@@ -749,23 +819,6 @@ int dg_revolve_stats(int32_t nsteps, int32_t nsnaps, int64_t* stats) {
   return DG_OK;
 }
 
-// Steps whose stage states the forward sweep records: every step advanced
-// before the first reverse action (the step index of each slot is tracked
-// through the stores and restores), and the final step to U^N.
-std::vector<char> rv_stage_steps(const std::vector<RvAction>& a, int nsteps, int nsnaps) {
-  std::vector<char> have(nsteps, 0);
-  std::vector<int> slot_step(nsnaps + 1, 0);
-  const size_t split = rv_split(a);
-  int cur = 0;
-  for (size_t i = 0; i < split; ++i) {
-    if (a[i].op == RV_RESTORE) cur = slot_step[a[i].a];
-    if (a[i].op == RV_STORE) slot_step[a[i].a] = cur;
-    if (a[i].op == RV_ADVANCE)
-      for (int k = 0; k < a[i].a; ++k) have[cur++] = 1;
-  }
-  have[nsteps - 1] = 1;
-  return have;
-}
 
 int dg_adjoint_forward(dg_ctx* c, const double* U0, double* UT, double dt, int32_t nsteps, int32_t nsnaps,
                        double* ckpt, double* stages) {
@@ -833,27 +886,44 @@ int dg_adjoint_backward(dg_ctx* c, double dt, int32_t nsteps, int32_t nsnaps, do
   auto a = rv_schedule(nsteps, nsnaps);
   std::vector<char> have = stages ? rv_stage_steps(a, nsteps, nsnaps) : std::vector<char>(nsteps, 0);
   hipError_t e = hipSuccess;
-  // A restored checkpoint is copied into the work buffer, where the adjoint
-  // step reads it (the copy also leaves it in the last-level cache).
+  const double* state = work;  // where the current state lives (a slot or the work buffer)
+  bool zpend = false;          // the next adjoint step's first records are in place
   for (size_t i = rv_split(a); i < a.size() && rc == DG_OK; ++i) {
     switch (a[i].op) {
       case RV_RESTORE:
-        e = hipMemcpyAsync(work, ckpt + (size_t)a[i].a * n, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+        state = ckpt + (size_t)a[i].a * n;  // read in place
         break;
       case RV_STORE:
-        e = hipMemcpyAsync(ckpt + (size_t)a[i].a * n, work, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+        if (state != ckpt + (size_t)a[i].a * n) {
+          e = hipMemcpyAsync(ckpt + (size_t)a[i].a * n, state, n * sizeof(double), hipMemcpyDeviceToDevice,
+                             c->stream);
+          state = ckpt + (size_t)a[i].a * n;
+        }
         break;
       case RV_ADVANCE:
-        for (int k = 0; k < a[i].a && rc == DG_OK; ++k) rc = rk3_step(c, c->stream, work, dt);
+        // the first step out of a slot writes into the work buffer
+        for (int k = 0; k < a[i].a && rc == DG_OK; ++k) {
+          if (state != work) {
+            rc = rk3_step_to(c, c->stream, state, work, dt);
+            state = work;
+          } else {
+            rc = rk3_step(c, c->stream, work, dt);
+          }
+        }
         break;
       case RV_ADJOINT: {
-        // lam <- (d step / d U^k)^T lam, with U^k in the work buffer
+        // lam <- (d step / d U^k)^T lam
         const int k = a[i].a;
+        // the stage states of the step reversed next, when kept, let the last
+        // launch of this step also start that one
+        const double* next_S2 =
+            adj_fused(c) && k > 0 && have[k - 1] ? stages + (size_t)(2 * (k - 1) + 1) * n : nullptr;
         if (have[k])
-          rc = rk3_adjoint(c, c->stream, work, dt, lam, lam, stages + (size_t)(2 * k) * n,
-                           stages + (size_t)(2 * k + 1) * n);
+          rc = rk3_adjoint(c, c->stream, state, dt, lam, lam, stages + (size_t)(2 * k) * n,
+                           stages + (size_t)(2 * k + 1) * n, zpend, next_S2);
         else
-          rc = rk3_adjoint(c, c->stream, work, dt, lam, lam);
+          rc = rk3_adjoint(c, c->stream, state, dt, lam, lam, nullptr, nullptr, zpend, next_S2);
+        zpend = next_S2 != nullptr;
         break;
       }
     }

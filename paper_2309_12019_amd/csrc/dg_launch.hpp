@@ -6,11 +6,16 @@
 namespace dgk {
 
 enum LaunchKind { LAUNCH_STAGE = 0, LAUNCH_PROJECT = 1, LAUNCH_LAMBDA = 2, LAUNCH_BATCH = 3,
-                  LAUNCH_ADJ_SENSOR = 4, LAUNCH_ADJ_GRAD = 5, LAUNCH_STEP = 6 };
+                  LAUNCH_ADJ_SENSOR = 4, LAUNCH_ADJ_GRAD = 5, LAUNCH_STEP = 6, LAUNCH_ADJ_GRAD_SENSOR = 7 };
 
 // the fused step kernel's tiles
 constexpr int kStepTile1D = 256;
 constexpr int kStepTile2D = 16;
+// the adjoint kernels' 2D tile (rows of 32 cells: longer contiguous runs of
+// the cell-major state than 16x16 for the same 256 threads); 1D adjoint
+// launches use the stage kernel's tile
+constexpr int kAdjTileX = 32;
+constexpr int kAdjTileY = 8;
 
 struct LaunchReq {
   int kind;

@@ -112,16 +112,30 @@ hipError_t launch_adj_tile(const LaunchReq* r) {
   dim3 block(DGK_DIM == 2 ? TX * TY : TX);
   const bool sens = r->kind == LAUNCH_ADJ_SENSOR;
   const size_t lds = sizeof(double) * (size_t)NL * S * (sens ? 1 : 2);
-  const void* k = sens ? reinterpret_cast<const void*>(adj_sensor_kernel<DGK_DIM, DGK_P, FLUX, MODE, TX, TY>)
-                       : reinterpret_cast<const void*>(adj_grad_kernel<DGK_DIM, DGK_P, FLUX, MODE, TX, TY>);
+  const void* k;
+  if (r->kind == LAUNCH_ADJ_GRAD_SENSOR) {
+    // only the stabilised operator has a sensor to reverse
+    if constexpr (MODE != MODE_WENO)
+      return hipErrorInvalidValue;
+    else
+      k = reinterpret_cast<const void*>(adj_grad_sensor_kernel<DGK_DIM, DGK_P, FLUX, MODE, TX, TY>);
+  } else {
+    k = sens ? reinterpret_cast<const void*>(adj_sensor_kernel<DGK_DIM, DGK_P, FLUX, MODE, TX, TY>)
+             : reinterpret_cast<const void*>(adj_grad_kernel<DGK_DIM, DGK_P, FLUX, MODE, TX, TY>);
+  }
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  if (sens)
+  if (r->kind == LAUNCH_ADJ_GRAD_SENSOR) {
+    if constexpr (MODE == MODE_WENO)
+      hipLaunchKernelGGL((adj_grad_sensor_kernel<DGK_DIM, DGK_P, FLUX, MODE, TX, TY>), grid, block, lds, r->stream,
+                         Ad);
+  } else if (sens) {
     hipLaunchKernelGGL((adj_sensor_kernel<DGK_DIM, DGK_P, FLUX, MODE, TX, TY>), grid, block, lds, r->stream, Ad);
-  else
+  } else {
     hipLaunchKernelGGL((adj_grad_kernel<DGK_DIM, DGK_P, FLUX, MODE, TX, TY>), grid, block, lds, r->stream, Ad);
+  }
   return hipGetLastError();
 }
 
@@ -131,8 +145,7 @@ hipError_t launch_adj_fm(const LaunchReq* r) {
     if (r->adj.s.tx == 64) return launch_adj_tile<FLUX, MODE, 64, 1>(r);
     return launch_adj_tile<FLUX, MODE, 256, 1>(r);
   } else {
-    if (r->adj.s.tx == 8) return launch_adj_tile<FLUX, MODE, 8, 8>(r);
-    return launch_adj_tile<FLUX, MODE, 16, 16>(r);
+    return launch_adj_tile<FLUX, MODE, kAdjTileX, kAdjTileY>(r);
   }
 }
 
@@ -178,7 +191,8 @@ extern "C" hipError_t DGK_CAT(dgk_launch, DGK_DIM, DGK_P)(const LaunchReq* r) {
       return launch_batch_f<FLUX_BURGERS>(r);
     }
     case LAUNCH_ADJ_SENSOR:
-    case LAUNCH_ADJ_GRAD: {
+    case LAUNCH_ADJ_GRAD:
+    case LAUNCH_ADJ_GRAD_SENSOR: {
       if (r->flux == FLUX_LINADV) return launch_adj_f<FLUX_LINADV>(r);
       return launch_adj_f<FLUX_BURGERS>(r);
     }

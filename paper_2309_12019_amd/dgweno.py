@@ -261,7 +261,8 @@ class DG:
         _check(self.lib.dg_set_tile(self.h, int(tx), int(ty)))
 
     def set_fused(self, mode: int) -> None:
-        """Fused step kernel: -1 automatic, 0 off, 1 on (dg_set_fused)."""
+        """Fused step kernel: -1 automatic, 0 off, 1 on (dg_set_fused); 0 also
+        gives the adjoint separate launches for its two passes."""
         _check(self.lib.dg_set_fused(self.h, int(mode)))
 
     def fused(self) -> bool:

@@ -165,6 +165,7 @@ int main() {
   sweep<1, 64, 1>();
   sweep<2, 16, 16>();
   sweep<2, 8, 8>();
+  sweep<2, kAdjTileX, kAdjTileY>();  // the adjoint kernels' 2D tile
   std::printf("%s (%d failures)\n", failures ? "FAIL" : "ok", failures);
   return failures ? 1 : 0;
 }

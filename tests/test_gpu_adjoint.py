@@ -188,3 +188,33 @@ def test_autograd_function_and_finite_differences():
         fd = (4 * fd2 - fd1) / 3
         ad = float((grad * d).sum())
         assert abs(fd - ad) <= 1e-6 * abs(ad)
+
+
+@pytest.mark.parametrize("kind,p", [("burgers2d", 2), ("rot2d", 3), ("burgers1d", 2), ("adv1d", 4)])
+def test_shared_launches_equal_separate_passes_bitwise(kind, p):
+    """Pass B of a stage sharing its launch with pass A of the stage before it
+    (and, with stage states kept, with the next step's first pass A) gives the
+    same gradient bit for bit as separate pass A and pass B launches
+    (switched with the fused-kernel mode); checkpoint budgets with and without
+    stage states mix both kinds of steps."""
+    _note(f"[shared launches] {kind} p={p}")
+    w = _mesh(kind, p, 2)
+    O = oracle_for(w)
+    U0 = _state(w, O, 21).cuda().contiguous()
+    g = _dg().DG.from_workload(w)
+    nsteps = 7
+    out = {}
+    for mode in (-1, 0):
+        g.set_fused(mode)
+        for nsnaps, keep in ((nsteps, True), (2, True), (2, False)):
+            ck = g.checkpoints(nsnaps)
+            stg = g.stage_checkpoints(nsteps) if keep else None
+            UT = g.adjoint_forward(U0, w.dt(), nsteps, nsnaps, ck, stages=stg)
+            lam = (UT * 0.5 + 0.25).contiguous()
+            g.adjoint_backward(w.dt(), nsteps, nsnaps, ck, lam, stages=stg)
+            torch.cuda.synchronize()
+            out[(mode, nsnaps, keep)] = lam.cpu()
+    g.set_fused(-1)
+    ref = out[(0, nsteps, True)]
+    for key, val in out.items():
+        assert torch.equal(val, ref), key
