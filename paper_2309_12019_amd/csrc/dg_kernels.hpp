@@ -198,7 +198,11 @@ struct Cell {
   // gamma_e of eqs. (sensor)/(gensensor) with the HWENO reconstruction.
   // One pass over the candidates: each candidate's indicator gives its
   // unnormalised weight alpha_l at once, so c* = sum_l alpha_l c^(l) / sum alpha
-  // accumulates while the candidate is in registers.
+  // accumulates while the candidate is in registers.  SB: one candidate live
+  // at a time (see below); without it the compiler may keep the neighbours'
+  // coefficients in registers for the faces, where registers are not what
+  // limits the occupancy.
+  template <bool SB>
   __device__ static inline double sensor(const StageArgs& A, const double* b, const bool (&has)[NF],
                                          const double (&c)[NL]) {
     const double beta0 = qform(c);
@@ -220,7 +224,7 @@ struct Cell {
       for (int j = 1; j < NL; ++j) acc[j] = fma(al, cd[j], acc[j]);
       // keep one candidate live at a time (the scheduler would otherwise
       // hoist every candidate's LDS reads and double the register count)
-      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (SB) __builtin_amdgcn_sched_barrier(0);
     }
     const double inv = rcp(asum);
     // c - c*: the constant coefficient of every candidate is c_0, and the
@@ -255,7 +259,9 @@ struct Cell {
   }
 
   // dU/dt of one cell and gamma_e; c holds the cell's own coefficients (the
-  // same values as its LDS slot b), the neighbours are read from LDS
+  // same values as its LDS slot b), the neighbours are read from LDS.  SB as
+  // for sensor(); the arithmetic is the same either way.
+  template <bool SB = true>
   __device__ static inline void rhs(const StageArgs& A, const double* b, const double (&c)[NL], int ix, int iy,
                                     double (&L)[NL], double& gam_out) {
     bool has[NF];
@@ -271,7 +277,7 @@ struct Cell {
     else if constexpr (MODE == MODE_LO)
       gam = 1.0;
     else
-      gam = sensor(A, b, has, c);
+      gam = sensor<SB>(A, b, has, c);
     gam_out = gam;
 
     const double hh = 0.5 * A.h;
@@ -737,7 +743,9 @@ __device__ inline void step_stage(const StageArgs& A, const double* tin, const d
     double c[NL], L[NL], gam;
 #pragma unroll
     for (int j = 0; j < NL; ++j) c[j] = tin[j * TI::S + islot];
-    C::rhs(A, tin + islot, c, wx, wy, L, gam);
+    // 2D: LDS allows one workgroup per CU, so up to P = 2 the registers freed
+    // by the scheduling barrier do not raise the occupancy
+    C::template rhs<(DIM == 1 || P > 2)>(A, tin + islot, c, wx, wy, L, gam);
 #pragma unroll
     for (int j = 0; j < NL; ++j) {
       double v = b * fma(A.dt, L[j], c[j]);
