@@ -258,35 +258,49 @@ struct Cell {
     }
   }
 
+  // gamma_e of the cell at mesh coordinates (ix, iy) in this stabilisation mode
+  template <bool SB>
+  __device__ static inline double gamma_of(const StageArgs& A, const double* b, const double (&c)[NL], int ix,
+                                           int iy) {
+    if constexpr (MODE == MODE_DG) {
+      return 0.0;
+    } else if constexpr (MODE == MODE_LO) {
+      return 1.0;
+    } else {
+      bool has[NF];
+      has[0] = A.per_x || ix > 0;
+      has[1] = A.per_x || ix < A.nx - 1;
+      if constexpr (DIM == 2) {
+        has[2] = A.per_y || iy > 0;
+        has[3] = A.per_y || iy < A.ny - 1;
+      }
+      return sensor<SB>(A, b, has, c);
+    }
+  }
+
   // dU/dt of one cell and gamma_e; c holds the cell's own coefficients (the
   // same values as its LDS slot b), the neighbours are read from LDS.  SB as
-  // for sensor(); the arithmetic is the same either way.
+  // for sensor(); the arithmetic is the same either way.  The three parts
+  // (gamma_of, residual, finish) may also run on different threads.
   template <bool SB = true>
   __device__ static inline void rhs(const StageArgs& A, const double* b, const double (&c)[NL], int ix, int iy,
                                     double (&L)[NL], double& gam_out) {
-    bool has[NF];
-    has[0] = A.per_x || ix > 0;
-    has[1] = A.per_x || ix < A.nx - 1;
-    if constexpr (DIM == 2) {
-      has[2] = A.per_y || iy > 0;
-      has[3] = A.per_y || iy < A.ny - 1;
-    }
-    double gam;
-    if constexpr (MODE == MODE_DG)
-      gam = 0.0;
-    else if constexpr (MODE == MODE_LO)
-      gam = 1.0;
-    else
-      gam = sensor<SB>(A, b, has, c);
+    const double gam = gamma_of<SB>(A, b, c, ix, iy);
     gam_out = gam;
+    double R[NL], lam;
+    residual(A, b, c, ix, iy, R, lam);
+    finish(A, c, gam, lam, R, L);
+  }
 
+  // Volume minus face terms of the weak form (R) and the cell's wave speed
+  // lambda_e (before the override)
+  __device__ static inline void residual(const StageArgs& A, const double* b, const double (&c)[NL], int ix, int iy,
+                                         double (&R)[NL], double& lam) {
     const double hh = 0.5 * A.h;
     const double xc = A.x0 + (ix + 0.5) * A.h;
     const double yc = DIM == 2 ? A.y0 + (iy + 0.5) * A.h : 0.0;
-    double R[NL];
 #pragma unroll
     for (int j = 0; j < NL; ++j) R[j] = 0.0;
-    double lam;
 
     if constexpr (DIM == 1) {
       // ---- volume
@@ -450,8 +464,12 @@ struct Cell {
       }
     }
 
-    // ---- dissipation gamma nu int grad(phi).grad(u_h) and M^-1:
-    // L = (2/h) Mhat^-1 [ vol - face - (gamma lambda / p) Khat c ]
+  }
+
+  // Dissipation gamma nu int grad(phi).grad(u_h) and M^-1:
+  // L = (2/h) Mhat^-1 [ vol - face - (gamma lambda / p) Khat c ]
+  __device__ static inline void finish(const StageArgs& A, const double (&c)[NL], double gam, double lam,
+                                       const double (&R)[NL], double (&L)[NL]) {
     if (A.lam_over > 0.0) lam = A.lam_over;
     const double kd = gam * lam * (1.0 / P);
     const double g2h = 2.0 / A.h;
@@ -670,7 +688,34 @@ __host__ __device__ inline int step_lds_doubles(int dim, int nl, int tx, int ty)
     const int w = tx + 2 * k, h = dim == 2 ? ty + 2 * k : 1;
     tot += (w * h) | 1;
   }
-  return nl * tot;
+  return nl * tot + step_threads(dim, tx, ty) / 2;  // + the gamma exchange of split stages
+}
+
+// A stage of the fused step whose output tile has at most half as many
+// cells as the workgroup has threads leaves waves idle (stage 3 of a 16x16
+// tile: 256 cells, 512 threads).  Such a stage splits cells over two
+// threads: one evaluates gamma_e, the other the residual, then (after a
+// barrier) the dissipation, mass inverse and RK combination.  The first
+// split_full(n, nt) cells (a multiple of 64) are evaluated whole by one
+// thread each; the rest are split, each role on whole waves, so that no wave
+// holds two roles.  n when nothing splits: then every thread takes whole
+// cells, as in the per-stage kernel.
+__host__ __device__ constexpr int split_full(int n, int nt) {
+  for (int f = 0; f <= nt / 2 && f < n; f += 64) {
+    const int ws = (n - f + 63) / 64;
+    if (64 * (f / 64 + 2 * ws) <= nt) return f;
+  }
+  return n;
+}
+
+// Role of thread t in a stage of n output cells and nt threads when the
+// stage splits (split_full(n, nt) < n): 0 the whole cell o, 1 gamma of cell o,
+// 2 the rest of cell o; o >= n: no cell.  The split cells' gamma goes to slot
+// o - split_full(n, nt) of the exchange buffer (fewer than nt / 2 slots).
+__host__ __device__ constexpr void split_role(int t, int n, int nt, int& role, int& o) {
+  const int f = split_full(n, nt), ws = (n - f + 63) / 64;
+  role = t < f ? 0 : (t < f + 64 * ws ? 1 : 2);
+  o = role == 2 ? t - 64 * ws : t;
 }
 
 // Mesh cell of coordinates (gx, gy) before wrapping, any distance outside the
@@ -720,32 +765,21 @@ __host__ __device__ inline void step_slot(int o, int ix0, int iy0, int& islot, i
 // a U^n + b (U^(k-1) + dt L); KO = 0 writes the tile's mesh cells to HBM.
 template <int DIM, int P, int FLUX, int MODE, int TX, int TY, int KO>
 __device__ inline void step_stage(const StageArgs& A, const double* tin, const double* ta, double* tout, int ix0,
-                                  int iy0, double a, double b) {
+                                  int iy0, double a, double b, double* gx_lds) {
   using G = StepGeom<DIM, TX, TY>;
   using TI = typename G::template T<KO + 1>;
   using TO = typename G::template T<KO>;
   using C = Cell<DIM, P, FLUX, MODE, TI::S, TI::W>;
   constexpr int NL = C::NL;
+  // 2D: LDS allows one workgroup per CU, so up to P = 2 the registers freed
+  // by the scheduling barrier do not raise the occupancy
+  constexpr bool SB = DIM == 1 || P > 2;
+  constexpr int NF_ = split_full(TO::N, G::NT);  // cells evaluated whole
+  constexpr bool SPLIT = MODE == MODE_WENO && NF_ < TO::N;
   const int nx = A.nx, ny = DIM == 2 ? A.ny : 1;
-#pragma unroll 1
-  for (int o = threadIdx.x; o < TO::N; o += G::NT) {
-    int islot, aslot, gx, gy, wx, wy;
-    step_slot<DIM, TX, TY, KO>(o, ix0, iy0, islot, aslot, gx, gy);
-    if constexpr (KO == 0) {
-      if (gx >= nx || gy >= ny) continue;  // past a ragged edge
-    }
-    if (!step_cell<DIM>(A, gx, gy, wx, wy)) {
-      // outside a non-periodic boundary: the exterior state
-#pragma unroll
-      for (int j = 0; j < NL; ++j) tout[j * TO::S + o] = j == 0 ? A.bc : 0.0;
-      continue;
-    }
-    double c[NL], L[NL], gam;
-#pragma unroll
-    for (int j = 0; j < NL; ++j) c[j] = tin[j * TI::S + islot];
-    // 2D: LDS allows one workgroup per CU, so up to P = 2 the registers freed
-    // by the scheduling barrier do not raise the occupancy
-    C::template rhs<(DIM == 1 || P > 2)>(A, tin + islot, c, wx, wy, L, gam);
+
+  // RK combination of cell o and its store (to the output tile, or to HBM)
+  auto store = [&](int o, int aslot, int wx, int wy, const double (&c)[NL], const double (&L)[NL]) {
 #pragma unroll
     for (int j = 0; j < NL; ++j) {
       double v = b * fma(A.dt, L[j], c[j]);
@@ -754,6 +788,63 @@ __device__ inline void step_stage(const StageArgs& A, const double* tin, const d
         A.out[((size_t)wy * nx + wx) * NL + j] = v;
       else
         tout[j * TO::S + o] = v;
+    }
+  };
+  // the slots of cell o; false if it has no equation (past a ragged edge, or
+  // outside a non-periodic boundary, where `ext` writes the exterior state)
+  auto locate = [&](int o, bool ext, int& islot, int& aslot, int& wx, int& wy) {
+    int gx, gy;
+    step_slot<DIM, TX, TY, KO>(o, ix0, iy0, islot, aslot, gx, gy);
+    if constexpr (KO == 0) {
+      if (gx >= nx || gy >= ny) return false;
+    }
+    if (!step_cell<DIM>(A, gx, gy, wx, wy)) {
+      if (ext) {
+#pragma unroll
+        for (int j = 0; j < NL; ++j) tout[j * TO::S + o] = j == 0 ? A.bc : 0.0;
+      }
+      return false;
+    }
+    return true;
+  };
+
+  if constexpr (!SPLIT) {
+#pragma unroll 1
+    for (int o = threadIdx.x; o < TO::N; o += G::NT) {
+      int islot, aslot, wx, wy;
+      if (!locate(o, true, islot, aslot, wx, wy)) continue;
+      double c[NL], L[NL], gam;
+#pragma unroll
+      for (int j = 0; j < NL; ++j) c[j] = tin[j * TI::S + islot];
+      C::template rhs<SB>(A, tin + islot, c, wx, wy, L, gam);
+      store(o, aslot, wx, wy, c, L);
+    }
+  } else {
+    // roles by thread: [0, NF_) whole cells; the next waves gamma of the split
+    // cells; the waves after those the rest of the same cells
+    int role, o;
+    split_role(threadIdx.x, TO::N, G::NT, role, o);
+    int islot = 0, aslot = 0, wx = 0, wy = 0;
+    const bool valid = o < TO::N && locate(o, role != 1, islot, aslot, wx, wy);
+    double c[NL], R[NL], lam = 0.0;
+    if (valid) {
+#pragma unroll
+      for (int j = 0; j < NL; ++j) c[j] = tin[j * TI::S + islot];
+      if (role == 0) {
+        double L[NL], gam;
+        C::template rhs<SB>(A, tin + islot, c, wx, wy, L, gam);
+        store(o, aslot, wx, wy, c, L);
+      } else if (role == 1) {
+        gx_lds[o - NF_] = C::template gamma_of<SB>(A, tin + islot, c, wx, wy);
+      } else {
+        C::residual(A, tin + islot, c, wx, wy, R, lam);
+      }
+    }
+    tile_barrier();  // every thread: gamma of the split cells is in LDS
+    if (valid && role == 2) {
+      double L[NL];
+      C::finish(A, c, gx_lds[o - NF_], lam, R, L);
+      store(o, aslot, wx, wy, c, L);
     }
   }
 }
@@ -769,6 +860,7 @@ __global__ void __launch_bounds__(step_threads(DIM, TX, TY)) step_kernel(const S
   double* ta = lds;
   double* tb = ta + NL * G::A::S;
   double* tc = tb + NL * G::B::S;
+  double* gx = tc + NL * G::C::S;  // gamma of the split cells of a stage (NT / 2)
   const int ix0 = blockIdx.x * TX, iy0 = DIM == 2 ? blockIdx.y * TY : 0;
   // U^n on the tile and three rings
 #pragma unroll 1
@@ -788,11 +880,11 @@ __global__ void __launch_bounds__(step_threads(DIM, TX, TY)) step_kernel(const S
     for (int j = 0; j < NL; ++j) ta[j * G::A::S + o] = v[j];
   }
   tile_barrier();
-  step_stage<DIM, P, FLUX, MODE, TX, TY, 2>(A, ta, ta, tb, ix0, iy0, 0.0, 1.0);
+  step_stage<DIM, P, FLUX, MODE, TX, TY, 2>(A, ta, ta, tb, ix0, iy0, 0.0, 1.0, gx);
   tile_barrier();
-  step_stage<DIM, P, FLUX, MODE, TX, TY, 1>(A, tb, ta, tc, ix0, iy0, 0.75, 0.25);
+  step_stage<DIM, P, FLUX, MODE, TX, TY, 1>(A, tb, ta, tc, ix0, iy0, 0.75, 0.25, gx);
   tile_barrier();
-  step_stage<DIM, P, FLUX, MODE, TX, TY, 0>(A, tc, ta, nullptr, ix0, iy0, 1.0 / 3.0, 2.0 / 3.0);
+  step_stage<DIM, P, FLUX, MODE, TX, TY, 0>(A, tc, ta, nullptr, ix0, iy0, 1.0 / 3.0, 2.0 / 3.0, gx);
 }
 
 // ---------------------------------------------------------------------------

@@ -108,6 +108,39 @@ void check_step_stage(const StageArgs& A, int ix0, int iy0, size_t ncells, int n
   }
 }
 
+// The split stages of the fused step: every output cell is evaluated whole
+// by exactly one thread, or has exactly one gamma thread and one thread for
+// the rest; each wave holds one role; the gamma slots stay inside the
+// exchange buffer (nt / 2 doubles).
+template <int DIM, int TX, int TY, int KO>
+void check_split() {
+  using G = StepGeom<DIM, TX, TY>;
+  using TO = typename G::template T<KO>;
+  constexpr int n = TO::N, nt = G::NT, f = split_full(n, nt);
+  if (f >= n) return;  // this stage does not split
+  static int whole[4096], gam[4096], rest[4096];
+  for (int o = 0; o < n; ++o) whole[o] = gam[o] = rest[o] = 0;
+  int wave_role[64];
+  for (int w = 0; w < 64; ++w) wave_role[w] = -1;
+  for (int t = 0; t < nt; ++t) {
+    int role, o;
+    split_role(t, n, nt, role, o);
+    if (o < n) {
+      CHECK(o >= 0, "split: negative cell");
+      if (role == 0) whole[o]++;
+      if (role == 1) gam[o]++;
+      if (role == 2) rest[o]++;
+      if (role != 0) CHECK(o - f >= 0 && o - f < nt / 2, "split: gamma slot %d out of range", o - f);
+    }
+    const int w = t / 64;
+    CHECK(wave_role[w] < 0 || wave_role[w] == role, "split: wave %d holds two roles", w);
+    wave_role[w] = role;
+  }
+  for (int o = 0; o < n; ++o)
+    CHECK((whole[o] == 1 && gam[o] == 0 && rest[o] == 0) || (whole[o] == 0 && gam[o] == 1 && rest[o] == 1),
+          "split: cell %d covered %d/%d/%d times", o, whole[o], gam[o], rest[o]);
+}
+
 template <int DIM, int TX, int TY>
 void check_step(int nx, int ny, int per_x, int per_y) {
   using G = StepGeom<DIM, TX, TY>;
@@ -160,6 +193,14 @@ void sweep_step() {
 }
 
 int main() {
+  check_split<2, kStepTile2D, kStepTile2D, 2>();
+  check_split<2, kStepTile2D, kStepTile2D, 1>();
+  check_split<2, kStepTile2D, kStepTile2D, 0>();
+  check_split<1, kStepTile1D, 1, 2>();
+  check_split<1, kStepTile1D, 1, 1>();
+  check_split<1, kStepTile1D, 1, 0>();
+  static_assert(split_full(256, 512) == 0 && split_full(324, 512) == 256 && split_full(400, 512) == 400,
+                "16x16 fused step: stage 3 splits every cell, stage 2 the cells past 256, stage 1 none");
   sweep_step();
   sweep<1, 256, 1>();
   sweep<1, 64, 1>();
