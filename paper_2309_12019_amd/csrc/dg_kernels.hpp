@@ -463,7 +463,6 @@ struct Cell {
           }
       }
     }
-
   }
 
   // Dissipation gamma nu int grad(phi).grad(u_h) and M^-1:
@@ -711,7 +710,7 @@ __host__ __device__ constexpr int split_full(int n, int nt) {
 // Role of thread t in a stage of n output cells and nt threads when the
 // stage splits (split_full(n, nt) < n): 0 the whole cell o, 1 gamma of cell o,
 // 2 the rest of cell o; o >= n: no cell.  The split cells' gamma goes to slot
-// o - split_full(n, nt) of the exchange buffer (fewer than nt / 2 slots).
+// o - split_full(n, nt) of the exchange buffer (at most nt / 2 slots).
 __host__ __device__ constexpr void split_role(int t, int n, int nt, int& role, int& o) {
   const int f = split_full(n, nt), ws = (n - f + 63) / 64;
   role = t < f ? 0 : (t < f + 64 * ws ? 1 : 2);
