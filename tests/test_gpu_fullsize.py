@@ -108,3 +108,39 @@ def test_full_size_run_invariants(name):
     else:
         # rotation with zero inflow: the data stay away from the boundary
         assert abs(m1 - m0) <= 1e-10 * scale
+
+
+def test_full_size_adjoint_at_sampled_cells():
+    """The adjoint at the adjoint benchmark's size (512^2 P2 Burgers, 32x8
+    adjoint tiles, pass B sharing launches with pass A): J^T v of the operator
+    and the adjoint of one SSP-RK3 step on the whole mesh, against the oracle's
+    reverse mode on windows around sampled cells.  (J^T v)_e involves the
+    operator on the face neighbours of e, each of which depends on its own face
+    neighbours: a window of radius 2.  The step adjoint at e involves the step
+    on cells within three face steps of e, each depending on cells within
+    three more: radius 6."""
+    w = inputs.burgers2d(512, 2, seed=0, steps=400)
+    _note(f"[full size] adjoint burgers2d 512x512 p2: {w.ndof} DOFs, sampled cells")
+    U = _input(w)
+    rng = np.random.default_rng(33)
+    v = torch.from_numpy(rng.standard_normal(U.shape))
+    lam = torch.from_numpy(rng.standard_normal(U.shape))
+    g = _dg().DG.from_workload(w)
+    JTv = g.rhs_vjp(U.cuda().contiguous(), v.cuda().contiguous())
+    lin = g.step_adjoint(U.cuda().contiguous(), w.dt(), lam.cuda().contiguous())
+    torch.cuda.synchronize()
+    JTv, lin = JTv.cpu(), lin.cpu()
+    sJ, sS = float(JTv.abs().max()), float(lin.abs().max())
+    worst_J = worst_S = 0.0
+    for k, (ix, iy) in enumerate(_samples(w, 10, 8)):
+        e = iy * w.nx + ix
+        Ow, idx, c = oracle_window(w, ix, iy, 2)
+        Ur = U[idx].clone().requires_grad_(True)
+        (ref,) = torch.autograd.grad(Ow.rhs(Ur), Ur, v[idx])
+        worst_J = max(worst_J, float((JTv[e] - ref[c]).abs().max()) / sJ)
+        if k % 3 == 0:
+            Ow, idx, c = oracle_window(w, ix, iy, 6)
+            ref = Ow.step_vjp(U[idx], w.dt(), lam[idx])
+            worst_S = max(worst_S, float((lin[e] - ref[c]).abs().max()) / sS)
+    _note(f"    J^T v {worst_J:.2e}, step adjoint {worst_S:.2e}")
+    assert worst_J <= 1e-11 and worst_S <= 1e-11
