@@ -844,10 +844,14 @@ __global__ void __launch_bounds__(DIM == 2 ? TX * TY : TX) adj_grad_sensor_kerne
     ldsv[j * S + sc] = v[j];
   }
   // U' of the cell and of its halo slot, loaded now so that the loads
-  // overlap pass B
+  // overlap pass B (up to P = 2; from P = 3 on the registers they would hold
+  // through pass B make it spill)
+  constexpr bool early = P <= 2;
   double cn[NL], hn[NL];
-  load_cell_at<DIM, NL>(A, Ad.unext, gx, gy, cn);
-  if (halo) load_cell_at<DIM, NL>(A, Ad.unext, hgx, hgy, hn);
+  if constexpr (early) {
+    load_cell_at<DIM, NL>(A, Ad.unext, gx, gy, cn);
+    if (halo) load_cell_at<DIM, NL>(A, Ad.unext, hgx, hgy, hn);
+  }
   tile_barrier();
   double o[NL];
   if (active) {
@@ -864,6 +868,10 @@ __global__ void __launch_bounds__(DIM == 2 ? TX * TY : TX) adj_grad_sensor_kerne
       o[j] = oj;
     }
   }
+  if constexpr (!early) {
+    load_cell_at<DIM, NL>(A, Ad.unext, gx, gy, cn);
+    if (halo) load_cell_at<DIM, NL>(A, Ad.unext, hgx, hgy, hn);
+  }
   tile_barrier();  // every thread is done with the state plane
 #pragma unroll
   for (int j = 0; j < NL; ++j) lds[j * S + sc] = cn[j];
@@ -872,9 +880,11 @@ __global__ void __launch_bounds__(DIM == 2 ? TX * TY : TX) adj_grad_sensor_kerne
     for (int j = 0; j < NL; ++j) lds[j * S + hs] = hn[j];
   }
   tile_barrier();
+  // without the candidate barriers up to P = 2 (registers there are set by
+  // pass B); from P = 3 on pass A would raise the register count
   if (active)
-    AC::template sensor_adjoint<false>(A, lds + sc, cn, gx, gy, o, Ad.znext + cell,
-                                       (size_t)A.nx * (DIM == 2 ? A.ny : 1));
+    AC::template sensor_adjoint<(P > 2)>(A, lds + sc, cn, gx, gy, o, Ad.znext + cell,
+                                         (size_t)A.nx * (DIM == 2 ? A.ny : 1));
 }
 
 }  // namespace dgk
