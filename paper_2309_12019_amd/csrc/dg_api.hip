@@ -497,6 +497,7 @@ int dg_validate_desc(const dg_mesh_desc* desc) {
 // rings and the one-workgroup-per-CU occupancy of the fused kernel cost more
 // than the launches and HBM passes it saves (0.7-0.86x from 384^2 up).
 bool fused_fits(const dg_ctx* c) {
+  if (c->d.dim == 2 && c->d.p == 4) return false;  // not built (its tiles exceed LDS)
   const int tx = c->d.dim == 1 ? dgk::kStepTile1D : dgk::kStepTile2D;
   const int ty = c->d.dim == 1 ? 1 : dgk::kStepTile2D;
   return sizeof(double) * (size_t)dgk::step_lds_doubles(c->d.dim, c->nl, tx, ty) <= (size_t)c->max_lds;

@@ -43,20 +43,26 @@ hipError_t launch_stage_fm(const StageArgs& A, hipStream_t st) {
 
 template <int FLUX, int MODE>
 hipError_t launch_step_fm(const StageArgs& A, hipStream_t st) {
-  constexpr int NL = DGK_DIM == 1 ? DGK_P + 1 : (DGK_P + 1) * (DGK_P + 1);
-  constexpr int TX = DGK_DIM == 1 ? kStepTile1D : kStepTile2D;
-  constexpr int TY = DGK_DIM == 1 ? 1 : kStepTile2D;
-  using G = StepGeom<DGK_DIM, TX, TY>;
-  auto k = step_kernel<DGK_DIM, DGK_P, FLUX, MODE, TX, TY>;
-  const size_t lds = sizeof(double) * (size_t)step_lds_doubles(DGK_DIM, NL, TX, TY);
-  if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
+  if constexpr (DGK_DIM == 2 && DGK_P == 4) {
+    // the three tiles (242 KB) exceed the LDS of a workgroup: not built (the
+    // library never selects the fused step here)
+    return hipErrorInvalidValue;
+  } else {
+    constexpr int NL = DGK_DIM == 1 ? DGK_P + 1 : (DGK_P + 1) * (DGK_P + 1);
+    constexpr int TX = DGK_DIM == 1 ? kStepTile1D : kStepTile2D;
+    constexpr int TY = DGK_DIM == 1 ? 1 : kStepTile2D;
+    using G = StepGeom<DGK_DIM, TX, TY>;
+    auto k = step_kernel<DGK_DIM, DGK_P, FLUX, MODE, TX, TY>;
+    const size_t lds = sizeof(double) * (size_t)step_lds_doubles(DGK_DIM, NL, TX, TY);
+    if (lds > 65536) {
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    dim3 grid((A.nx + TX - 1) / TX, DGK_DIM == 2 ? (A.ny + TY - 1) / TY : 1);
+    hipLaunchKernelGGL(k, grid, dim3(G::NT), lds, st, A);
+    return hipGetLastError();
   }
-  dim3 grid((A.nx + TX - 1) / TX, DGK_DIM == 2 ? (A.ny + TY - 1) / TY : 1);
-  hipLaunchKernelGGL(k, grid, dim3(G::NT), lds, st, A);
-  return hipGetLastError();
 }
 
 template <int FLUX>
