@@ -130,9 +130,18 @@ int dg_run(dg_ctx* ctx, double* U, double dt, int32_t nsteps);
  * over the mesh.  Synchronous; writes the host double *dt_host. */
 int dg_stable_dt(dg_ctx* ctx, const double* U, double cfl, double* dt_host);
 
-/* Check U (device) for NaN/Inf.  Synchronous.  Returns DG_OK, or
- * DG_ENONFINITE and the number of non-finite entries in *count (may be NULL). */
+/* Check U (device) for NaN/Inf: counted on the device, summed on the host.
+ * Synchronous.  Returns DG_OK, or DG_ENONFINITE and the number of non-finite
+ * entries in *count (may be NULL). */
 int dg_check_finite(dg_ctx* ctx, const double* U, int64_t* count);
+
+/* Not part of the method: a plain streaming device copy dst[0..n) =
+ * src[0..n) queued on `stream` (NULL: the default stream), 16 bytes per lane
+ * where both pointers are 16-byte aligned.  Its bandwidth is the measured
+ * ceiling the stage kernels' HBM traffic is read against.  src, dst: device,
+ * caller-owned, must not overlap.  Errors: DG_EINVAL for n < 0, NULL pointers
+ * with n > 0, or overlapping ranges. */
+int dg_stream_copy(const double* src, double* dst, int64_t n, void* stream);
 
 /* Launch shape of the stage kernel: cells per workgroup, one of the compiled
  * tiles: 1D tx in {256, 64} (ty ignored), 2D (tx, ty) in {(16,16), (8,8)}.

@@ -51,7 +51,7 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
             objs.append(o)
             steps.append([cc, *FLAGS, f"-DDGK_DIM={dim}", f"-DDGK_P={p}", "-c",
                           os.path.join(CSRC, "dg_stage.hip"), "-o", o])
-    for name in ("dg_api", "dg_batch"):
+    for name in ("dg_api", "dg_batch", "dg_util"):
         o = os.path.join(BUILD, f"{name}.o")
         objs.append(o)
         steps.append([cc, *FLAGS, "-c", os.path.join(CSRC, f"{name}.hip"), "-o", o])

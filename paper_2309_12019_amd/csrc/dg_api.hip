@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -730,16 +731,33 @@ int dg_stable_dt(dg_ctx* c, const double* U, double cfl, double* dt_host) {
 
 int dg_check_finite(dg_ctx* c, const double* U, int64_t* count) {
   if (!c || !U) return fail(DG_EINVAL, "NULL argument");
-  const size_t n = (size_t)c->ncells * c->nl;
-  std::vector<double> h(n);
-  hipError_t e;
-  if ((e = hipMemcpyAsync(h.data(), U, n * sizeof(double), hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
+  const long long n = (long long)c->ncells * c->nl;
+  // per-block counts on the device (grid-stride), summed here
+  long long nb = (n + 255) / 256;
+  if (nb > 1024) nb = 1024;
+  if (nb > (long long)c->red_len) nb = (long long)c->red_len;
+  hipError_t e = dgk_count_nonfinite(U, n, c->red, (int)nb, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "finite-check launch");
+  std::vector<double> h((size_t)nb);
+  if ((e = hipMemcpyAsync(h.data(), c->red, (size_t)nb * sizeof(double), hipMemcpyDeviceToHost, c->stream)) !=
+          hipSuccess ||
       (e = hipStreamSynchronize(c->stream)) != hipSuccess)
-    return hip_fail(e, "state readback");
-  int64_t bad = 0;
-  for (double v : h) bad += !std::isfinite(v);
-  if (count) *count = bad;
-  return bad ? fail(DG_ENONFINITE, "%lld non-finite entries", (long long)bad) : DG_OK;
+    return hip_fail(e, "finite-check readback");
+  double bad = 0.0;
+  for (double v : h) bad += v;
+  if (count) *count = (int64_t)bad;
+  return bad > 0.0 ? fail(DG_ENONFINITE, "%lld non-finite entries", (long long)bad) : DG_OK;
+}
+
+int dg_stream_copy(const double* src, double* dst, int64_t n, void* stream) {
+  if (n < 0) return fail(DG_EINVAL, "n must be >= 0");
+  if (n > 0 && (!src || !dst)) return fail(DG_EINVAL, "NULL argument");
+  const uintptr_t s0 = reinterpret_cast<uintptr_t>(src), d0 = reinterpret_cast<uintptr_t>(dst);
+  if (n > 0 && s0 < d0 + (uintptr_t)n * sizeof(double) && d0 < s0 + (uintptr_t)n * sizeof(double))
+    return fail(DG_EINVAL, "src and dst overlap");
+  hipError_t e = dgk_stream_copy(src, dst, (long long)n, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "copy launch");
+  return DG_OK;
 }
 
 int dg_set_tile(dg_ctx* c, int32_t tx, int32_t ty) {

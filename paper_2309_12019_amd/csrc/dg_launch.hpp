@@ -42,4 +42,8 @@ hipError_t dgk_launch_2_1(const dgk::LaunchReq*);
 hipError_t dgk_launch_2_2(const dgk::LaunchReq*);
 hipError_t dgk_launch_2_3(const dgk::LaunchReq*);
 hipError_t dgk_launch_2_4(const dgk::LaunchReq*);
+// dg_util.hip: partial[b] = non-finite entries of U[0..n) in block b's share
+hipError_t dgk_count_nonfinite(const double* U, long long n, double* partial, int nblocks, hipStream_t st);
+// dg_util.hip: dst[0..n) = src[0..n)
+hipError_t dgk_stream_copy(const double* src, double* dst, long long n, hipStream_t st);
 }

@@ -67,6 +67,7 @@ EXPORTS = {
     "dg_get_tile": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_int32)]),
     "dg_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "dg_stream_copy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     "dg_last_error": (ctypes.c_char_p, []),
     "dg_validate_desc": (ctypes.c_int, [ctypes.POINTER(MeshDesc)]),
     "dg_rhs_vjp": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -370,6 +371,17 @@ class Batch:
 
     def set_branches(self, n: int) -> None:
         _check(self.lib.dg_batch_set_branches(self.h, int(n)))
+
+
+def stream_copy(src: torch.Tensor, dst: torch.Tensor) -> None:
+    """dst = src by the library's streaming copy kernel (dg_stream_copy) on
+    the current stream: the measured bandwidth ceiling."""
+    lib = load()
+    if src.numel() != dst.numel():
+        raise ValueError("src and dst differ in size")
+    n = src.numel()
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    _check(lib.dg_stream_copy(_ptr(src, n, "src"), _ptr(dst, n, "dst"), n, stream))
 
 
 def revolve_stats(nsteps: int, nsnaps: int) -> dict:
