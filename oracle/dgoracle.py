@@ -21,7 +21,11 @@ vectorised over cells only; no blocking, fusion or reordering):
 * Sec. 3, eqs. (lostab), (visc), (astab): the element-local dissipation
       s_i = gamma_e nu_e int_K grad(phi_i) . grad(U_h) dx,
       nu_e = lambda_e h_e / (2p),  lambda_e = ||F'(U_h)||_{L^inf(K_e)}.
-  Mode DG uses gamma_e = 0, mode LO gamma_e = 1, mode WENO the sensor below.
+  Mode DG uses gamma_e = 0, mode LO gamma_e = 1, mode WENO the sensor below,
+  mode ZHAO the sensor of Zhao et al. that Sec. 5.6 compares with:
+      gamma_e^Z = sum_l |omega_l / omega~_l - 1|^theta
+                  / (|1 / min_l omega~_l - 1|^theta + m_e)
+  over the candidates that exist, with the same HWENO weights.
 * Sec. 4, eqs. (sensor), (gensensor) and the scaled Sobolev semi-norm:
       gamma_e = min(1, ||U - U*||_e / ||U||_e)^q   (0 below the threshold b),
       ||v||_e^2 = sum_{1<=|k|<=p} h^{2|k|-d} int_K |D^k v|^2 dx,
@@ -42,13 +46,19 @@ project's design notes):
 * Basis: tensor Legendre polynomials on the reference cell [-1,1]^d; the
   method is basis-independent (Sec. 2).
 * Non-periodic faces see a fixed exterior state through the same LLF flux.
+* Mode ZHAO: gamma_e = gamma_e^Z as printed (neither q nor the threshold b
+  applies); min_l omega~_l runs over the candidates that exist; a cell with no
+  face neighbour (m_e = 0) has gamma_e^Z = 0 (its only weight is its linear
+  weight, and the printed quotient is 0/0).
 
 Pins (tests/test_oracle_*.py): Gauss rules, Legendre polynomials, mass and
 stiffness matrices and the semi-norm against closed forms; the operator, sensor
 and wave speed against a brute-force evaluation of the integrals in physical
 coordinates; conservation, zero sensor on reproduced data, symmetries and the
 RK3 amplification polynomial; Table 1 and Table 2 of Sec. 5 (DG and LO
-columns); the reverse mode against finite differences.  The Hermite candidates
+columns); the reverse mode against finite differences; the Zhao et al. sensor
+is 0 on reproduced data, reaches 1 when one neighbour candidate takes all the
+weight, lies in [0, 1] and is shift- and mirror-invariant.  The Hermite candidates
 and nonlinear weights are a reading (the paper defers them to another
 reference): against the paper's WENO columns they are parity unpinned, and only
 the stated behaviour (optimal rates; WENO equal to DG with a threshold) is
@@ -70,6 +80,7 @@ LINADV = 0   # F(u) = v(x) u, v(x) = (vx - omega (y - cy), vy + omega (x - cx))
 BURGERS = 1  # F(u) = a u^2 / 2, a = (vx, vy)
 
 MODE_DG, MODE_LO, MODE_WENO = 0, 1, 2   # labels of Sec. 5
+MODE_ZHAO = 3   # the sensor of Zhao et al. that Sec. 5.6 compares with
 
 
 # --------------------------------------------------------------------------
@@ -105,6 +116,7 @@ class Problem:
     w_nb: float = 1e-2
     eps: float = 1e-6
     r: float = 2.0
+    theta: float = 1.0   # exponent of the Zhao et al. sensor (mode MODE_ZHAO)
     lambda_override: float = 0.0
     quad_vol: int = 0
     quad_face: int = 0
@@ -470,12 +482,28 @@ class Oracle:
                              cands=C, exists=ex, lin=lin)
         return gam
 
+    def zhao_sensor(self, U: torch.Tensor) -> torch.Tensor:
+        """gamma_e^Z (Sec. 5.6, the sensor of Zhao et al.): the deviation of the
+        nonlinear HWENO weights from the linear weights,
+            sum_l |omega_l / omega~_l - 1|^theta / (|1 / min_l omega~_l - 1|^theta + m_e),
+        sums and minimum over the candidates that exist; 0 where m_e = 0."""
+        P = self.P
+        _, d = self.sensor(U, details=True)
+        omega, lin, ex = d["omega"], d["lin"], d["exists"]
+        m_e = ex[:, 1:].sum(1).to(DTYPE)
+        dev = torch.where(ex, torch.abs(omega / lin - 1.0) ** P.theta, torch.zeros_like(omega)).sum(1)
+        lmin = torch.where(ex, lin, torch.full_like(lin, math.inf)).amin(1)
+        den = torch.abs(1.0 / lmin - 1.0) ** P.theta + m_e
+        return torch.where(m_e > 0, dev / torch.where(m_e > 0, den, torch.ones_like(den)), torch.zeros_like(dev))
+
     def gamma(self, U: torch.Tensor) -> torch.Tensor:
         P = self.P
         if P.mode == MODE_DG:
             return torch.zeros(U.shape[0], dtype=DTYPE)
         if P.mode == MODE_LO:
             return torch.ones(U.shape[0], dtype=DTYPE)
+        if P.mode == MODE_ZHAO:
+            return self.zhao_sensor(U)
         return self.sensor(U)
 
     def max_speed(self, U: torch.Tensor) -> torch.Tensor:

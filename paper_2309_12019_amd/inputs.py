@@ -22,6 +22,7 @@ import numpy as np
 
 LINADV, BURGERS = 0, 1
 MODE_DG, MODE_LO, MODE_WENO = 0, 1, 2
+MODE_ZHAO = 3   # the sensor of Zhao et al. compared in Sec. 5.6
 
 
 @dataclasses.dataclass
@@ -50,6 +51,7 @@ class Workload:
     w_nb: float = 1e-2
     eps: float = 1e-6
     r: float = 2.0
+    theta: float = 1.0                 # exponent of the Zhao et al. sensor (MODE_ZHAO)
     lambda_override: float = 0.0
     cfl: float = 0.1
     steps: int = 100

@@ -168,3 +168,86 @@ def test_dg_stability_limits(p, limit):
         mid = 0.5 * (lo + hi)
         lo, hi = (mid, hi) if stable(mid) else (lo, mid)
     assert abs(lo - limit) < 0.002
+
+
+# --- the sensor of Zhao et al. (Sec. 5.6) ---------------------------------
+def _zhao(w):
+    pz = oracle_problem(w)
+    pz.mode = inputs.MODE_ZHAO
+    return type(oracle_for(w))(pz)
+
+
+@pytest.mark.parametrize("dim,p", [(1, 1), (1, 2), (1, 4), (2, 2), (2, 3)])
+def test_zhao_sensor_zero_on_reproduced_data(dim, p):
+    """Data that every candidate reproduces (a global polynomial of degree <= p
+    plus a constant per cell) give equal indicators, hence nonlinear weights
+    equal to the linear ones and gamma^Z = 0."""
+    rng = np.random.default_rng(10 + p)
+    if dim == 1:
+        w = inputs.adv1d(9, p)
+        w.periodic_x = False
+        coef = rng.standard_normal(p + 1)
+        w.ic = lambda x: np.polynomial.polynomial.polyval(x, coef)
+    else:
+        w = inputs.rot2d(6, p)
+        C = rng.standard_normal((p + 1, p + 1))
+        w.ic = lambda x, y: np.polynomial.polynomial.polyval2d(x, y, C)
+    O = _zhao(w)
+    U = oracle_initial(w, O)
+    U[:, 0] += torch.from_numpy(rng.standard_normal(w.ncells))
+    assert float(O.gamma(U).abs().max()) < 1e-12
+
+
+def test_zhao_sensor_reaches_one_when_a_neighbour_candidate_takes_all_weight():
+    """The denominator is the largest value the numerator takes: all weight on
+    the candidate with the smallest linear weight.  A constant left neighbour
+    (indicator 0) next to a steep cell puts nearly all weight on that
+    neighbour's candidate, so gamma^Z -> 1 (up to the eps of the weights)."""
+    w = inputs.adv1d(3, 2)
+    w.periodic_x = False
+    O = _zhao(w)
+    U = torch.tensor([[0.3, 0.0, 0.0], [0.0, 1.0, 0.5], [1.0, 1.0, 0.5]], dtype=torch.float64)
+    g = O.gamma(U)
+    assert abs(float(g[1]) - 1.0) <= 1e-9
+    assert float(g.min()) >= 0.0 and float(g.max()) <= 1.0 + 1e-15
+
+
+def test_zhao_sensor_range_shift_and_mirror():
+    w = inputs.rot2d(7, 2)
+    O = _zhao(w)
+    U = torch.from_numpy(np.random.default_rng(6).standard_normal((w.ncells, w.nloc)))
+    g = O.gamma(U)
+    assert float(g.min()) >= 0.0 and float(g.max()) <= 1.0
+    assert (g > 0).all()
+    U2 = U.clone()
+    U2[:, 0] += 3.7
+    assert torch.allclose(O.gamma(U2), g, rtol=1e-12, atol=1e-14)
+    w1 = inputs.adv1d(17, 3)
+    O1 = _zhao(w1)
+    V = torch.from_numpy(np.random.default_rng(7).standard_normal((w1.ncells, w1.nloc)))
+    sgn = torch.tensor([(-1.0) ** a for a in range(w1.nloc)], dtype=torch.float64)
+    assert torch.allclose(O1.gamma(V.flip(0) * sgn), O1.gamma(V).flip(0), rtol=1e-12)
+
+
+def test_zhao_sensor_without_neighbours_is_zero():
+    """A single cell on a non-periodic line has no candidate but its own: its
+    weight is its linear weight and gamma^Z = 0 (the reading for the printed
+    0/0)."""
+    w = inputs.adv1d(1, 2)
+    w.periodic_x = False
+    O = _zhao(w)
+    U = torch.tensor([[0.2, 0.7, -0.4]], dtype=torch.float64)
+    assert float(O.gamma(U)[0]) == 0.0
+
+
+def test_zhao_sensor_theta():
+    """theta = 2 squares every deviation and the largest one in the denominator."""
+    w = inputs.adv1d(30, 2)
+    O = _zhao(w)
+    U = oracle_initial(w, O)
+    _, d = O.sensor(U, details=True)
+    pz = oracle_problem(w)
+    pz.mode, pz.theta = inputs.MODE_ZHAO, 2.0
+    g2 = type(O)(pz).gamma(U)
+    dev = ((d["omega"] / d["lin"] - 1.0) ** 2).sum(1)
+    assert torch.allclose(g2, dev / ((1.0 / w.w_nb - 1.0) ** 2 + 2.0), rtol=1e-13, atol=1e-300)
