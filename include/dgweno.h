@@ -55,8 +55,12 @@ enum dg_flux { DG_FLUX_LINADV = 0, DG_FLUX_BURGERS = 1 };
 
 /* Scheme labels of Sec. 5: DG (no stabilisation), LO (gamma_e = 1 in
  * eq. astab, i.e. the low-order operator of eq. lostab), WENO (gamma_e from
- * the smoothness sensor). */
-enum dg_mode { DG_MODE_DG = 0, DG_MODE_LO = 1, DG_MODE_WENO = 2 };
+ * the smoothness sensor of eqs. sensor/gensensor).  ZHAO: gamma_e from the
+ * sensor of Zhao et al. that Sec. 5.6 compares with, built on the same HWENO
+ * weights: sum_l |omega_l / omega~_l - 1|^theta / (|1 / min_l omega~_l -
+ * 1|^theta + m_e) over the candidates that exist (0 for a cell without face
+ * neighbours); q and b do not apply.  The adjoint covers DG, LO and WENO. */
+enum dg_mode { DG_MODE_DG = 0, DG_MODE_LO = 1, DG_MODE_WENO = 2, DG_MODE_ZHAO = 3 };
 
 typedef struct dg_mesh_desc {
   int32_t dim;               /* 1 or 2 */
@@ -75,13 +79,14 @@ typedef struct dg_mesh_desc {
   double weno_eps, weno_pow; /* alpha_l = w_l / (eps + beta_l)^pow */
   double lambda_override;    /* > 0: lambda_e := this value in every cell */
   void* stream;              /* hipStream_t the context queues work on (0 = default) */
+  double zhao_theta;         /* exponent theta of the ZHAO sensor, > 0 (Sec. 5.6: 1) */
 } dg_mesh_desc;
 
 typedef struct dg_ctx dg_ctx;   /* opaque, owned by the library */
 
 /* Fill a descriptor with the defaults: 1D, 64 cells on [0,1] periodic, p = 2,
  * LINADV with vel_x = 1, mode WENO, q = 1, b = 0, w_nb = 0.01, eps = 1e-6,
- * pow = 2, no lambda override, default stream.  Never fails. */
+ * pow = 2, no lambda override, default stream, zhao_theta = 1.  Never fails. */
 void dg_default_desc(dg_mesh_desc* desc);
 
 /* Validate `desc` and create a context on the current HIP device: mesh,
@@ -180,7 +185,8 @@ const char* dg_last_error(void);
  * speed; where a max/min switches the derivative of the active branch is
  * used (ties: split evenly).  The first adjoint call on a context allocates
  * two state-sized buffers and two sensor-record buffers (DG_EUNSUPPORTED if
- * the adjoint kernels' tile exceeds LDS).
+ * the adjoint kernels' tile exceeds LDS).  Every adjoint call returns
+ * DG_EUNSUPPORTED for mode ZHAO.
  * ------------------------------------------------------------------------ */
 
 /* out = J(U)^T v: the transpose Jacobian of dU/dt = L(U) (dg_rhs) applied to

@@ -102,6 +102,7 @@ StageArgs base_args(const dg_ctx* c) {
   A.eps = d.weno_eps;
   A.wpow = d.weno_pow;
   A.lam_over = d.lambda_override;
+  A.theta = d.zhao_theta;
   A.tx = c->tx;
   A.ty = d.dim == 2 ? c->ty : 1;
   return A;
@@ -212,8 +213,9 @@ int validate(const dg_mesh_desc* d) {
     if (std::fabs(hx - hy) > 1e-12 * hx) return fail(DG_EINVAL, "2D cells must be square (hx=%g hy=%g)", hx, hy);
   }
   if (d->flux != DG_FLUX_LINADV && d->flux != DG_FLUX_BURGERS) return fail(DG_EINVAL, "unknown flux %d", d->flux);
-  if (d->mode != DG_MODE_DG && d->mode != DG_MODE_LO && d->mode != DG_MODE_WENO)
+  if (d->mode != DG_MODE_DG && d->mode != DG_MODE_LO && d->mode != DG_MODE_WENO && d->mode != DG_MODE_ZHAO)
     return fail(DG_EINVAL, "unknown mode %d", d->mode);
+  if (!(d->zhao_theta > 0.0) || !std::isfinite(d->zhao_theta)) return fail(DG_EINVAL, "zhao_theta must be > 0");
   if (!(d->q >= 1.0) || !std::isfinite(d->q)) return fail(DG_EINVAL, "q must be >= 1");
   if (!(d->b >= 0.0 && d->b <= 1.0)) return fail(DG_EINVAL, "b must be in [0,1]");
   const int m = 2 * d->dim;
@@ -249,6 +251,7 @@ int check_tile(const dg_ctx* c, int tx, int ty) {
 int zrec_size(int dim, int nl) { return dgk::zrec_doubles(dim, nl); }
 
 int ensure_adjoint(dg_ctx* c) {
+  if (c->d.mode == DG_MODE_ZHAO) return fail(DG_EUNSUPPORTED, "the adjoint does not cover the ZHAO sensor");
   if (c->A1) return DG_OK;
   // the adjoint kernels' tiles hold the state and the cotangent
   const int atx = c->d.dim == 2 ? dgk::kAdjTileX : c->tx, aty = c->d.dim == 2 ? dgk::kAdjTileY : 1;
@@ -480,6 +483,7 @@ void dg_default_desc(dg_mesh_desc* d) {
   d->w_nb = 1e-2;
   d->weno_eps = 1e-6;
   d->weno_pow = 2.0;
+  d->zhao_theta = 1.0;
 }
 
 const char* dg_last_error(void) { return g_err; }
@@ -842,6 +846,7 @@ int dg_revolve_stats(int32_t nsteps, int32_t nsnaps, int64_t* stats) {
 int dg_adjoint_forward(dg_ctx* c, const double* U0, double* UT, double dt, int32_t nsteps, int32_t nsnaps,
                        double* ckpt, double* stages) {
   if (!c || !U0 || !UT || !ckpt) return fail(DG_EINVAL, "NULL argument");
+  if (c->d.mode == DG_MODE_ZHAO) return fail(DG_EUNSUPPORTED, "the adjoint does not cover the ZHAO sensor");
   if (nsteps < 1 || nsnaps < 0) return fail(DG_EINVAL, "need nsteps >= 1 and nsnaps >= 0");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite and > 0");
   const size_t n = (size_t)c->ncells * c->nl;

@@ -210,6 +210,7 @@ StageArgs args_of(const dg_mesh_desc& d) {
   A.eps = d.weno_eps;
   A.wpow = d.weno_pow;
   A.lam_over = d.lambda_override;
+  A.theta = d.zhao_theta;
   return A;
 }
 

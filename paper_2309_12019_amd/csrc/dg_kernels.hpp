@@ -28,7 +28,7 @@
 namespace dgk {
 
 enum { FLUX_LINADV = 0, FLUX_BURGERS = 1 };
-enum { MODE_DG = 0, MODE_LO = 1, MODE_WENO = 2 };
+enum { MODE_DG = 0, MODE_LO = 1, MODE_WENO = 2, MODE_ZHAO = 3 };
 
 struct StageArgs {
   const double* uin;  // operator input U^(k-1), [cells][NL]
@@ -44,6 +44,7 @@ struct StageArgs {
   double anorm;                  // ||(vx, vy)||_2 (BURGERS wave speed factor)
   double bc;                     // exterior state at non-periodic faces
   double q, bthr, wnb, eps, wpow, lam_over;
+  double theta;                  // exponent of the Zhao et al. sensor (MODE_ZHAO)
   int tx, ty;                    // tile (one of the compiled shapes; ty = 1 in 1D)
 };
 
@@ -258,6 +259,39 @@ struct Cell {
     }
   }
 
+  // The sensor of Zhao et al. that Sec. 5.6 compares with: the deviation of
+  // the nonlinear HWENO weights (the same alpha_l as in sensor()) from the
+  // linear ones, sum_l |omega_l / omega~_l - 1|^theta over the candidates
+  // that exist, over |1 / min_l omega~_l - 1|^theta + m_e; 0 without face
+  // neighbours.
+  template <bool SB>
+  __device__ static inline double zhao(const StageArgs& A, const double* b, const bool (&has)[NF],
+                                       const double (&c)[NL]) {
+    int m = 0;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) m += has[f];
+    if (m == 0) return 0.0;
+    const double lin0 = 1.0 - m * A.wnb;
+    double al[NF + 1];
+    al[0] = lin0 * weight(A, qform(c));
+    double asum = al[0];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      double cd[NL];
+      cand_any<0>(f, b, cd);
+      al[f + 1] = has[f] ? A.wnb * weight(A, qform(cd)) : 0.0;
+      asum += al[f + 1];
+      if constexpr (SB) __builtin_amdgcn_sched_barrier(0);
+    }
+    const double inv = rcp(asum);
+    auto pw = [&](double x) { return A.theta == 1.0 ? x : pow_cold(x, A.theta); };
+    double dev = pw(fabs(al[0] * inv / lin0 - 1.0));
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+      if (has[f]) dev += pw(fabs(al[f + 1] * inv / A.wnb - 1.0));
+    return dev / (pw(fabs(1.0 / fmin(lin0, A.wnb) - 1.0)) + m);
+  }
+
   // gamma_e of the cell at mesh coordinates (ix, iy) in this stabilisation mode
   template <bool SB>
   __device__ static inline double gamma_of(const StageArgs& A, const double* b, const double (&c)[NL], int ix,
@@ -274,7 +308,10 @@ struct Cell {
         has[2] = A.per_y || iy > 0;
         has[3] = A.per_y || iy < A.ny - 1;
       }
-      return sensor<SB>(A, b, has, c);
+      if constexpr (MODE == MODE_ZHAO)
+        return zhao<SB>(A, b, has, c);
+      else
+        return sensor<SB>(A, b, has, c);
     }
   }
 
@@ -774,7 +811,7 @@ __device__ inline void step_stage(const StageArgs& A, const double* tin, const d
   // by the scheduling barrier do not raise the occupancy
   constexpr bool SB = DIM == 1 || P > 2;
   constexpr int NF_ = split_full(TO::N, G::NT);  // cells evaluated whole
-  constexpr bool SPLIT = MODE == MODE_WENO && NF_ < TO::N;
+  constexpr bool SPLIT = (MODE == MODE_WENO || MODE == MODE_ZHAO) && NF_ < TO::N;
   const int nx = A.nx, ny = DIM == 2 ? A.ny : 1;
 
   // RK combination of cell o and its store (to the output tile, or to HBM)

@@ -70,6 +70,7 @@ hipError_t launch_step_f(int mode, const StageArgs& A, hipStream_t s) {
   switch (mode) {
     case MODE_DG: return launch_step_fm<FLUX, MODE_DG>(A, s);
     case MODE_LO: return launch_step_fm<FLUX, MODE_LO>(A, s);
+    case MODE_ZHAO: return launch_step_fm<FLUX, MODE_ZHAO>(A, s);
     default: return launch_step_fm<FLUX, MODE_WENO>(A, s);
   }
 }
@@ -105,6 +106,7 @@ hipError_t launch_batch_f(const LaunchReq* r) {
   switch (r->mode) {
     case MODE_DG: return launch_batch_fm<FLUX, MODE_DG>(r);
     case MODE_LO: return launch_batch_fm<FLUX, MODE_LO>(r);
+    case MODE_ZHAO: return launch_batch_fm<FLUX, MODE_ZHAO>(r);
     default: return launch_batch_fm<FLUX, MODE_WENO>(r);
   }
 }
@@ -160,6 +162,7 @@ hipError_t launch_adj_f(const LaunchReq* r) {
   switch (r->mode) {
     case MODE_DG: return launch_adj_fm<FLUX, MODE_DG>(r);
     case MODE_LO: return launch_adj_fm<FLUX, MODE_LO>(r);
+    case MODE_ZHAO: return hipErrorInvalidValue;  // no adjoint for this sensor
     default: return launch_adj_fm<FLUX, MODE_WENO>(r);
   }
 }
@@ -169,6 +172,7 @@ hipError_t launch_stage_f(int mode, const StageArgs& A, hipStream_t s) {
   switch (mode) {
     case MODE_DG: return launch_stage_fm<FLUX, MODE_DG>(A, s);
     case MODE_LO: return launch_stage_fm<FLUX, MODE_LO>(A, s);
+    case MODE_ZHAO: return launch_stage_fm<FLUX, MODE_ZHAO>(A, s);
     default: return launch_stage_fm<FLUX, MODE_WENO>(A, s);
   }
 }

@@ -43,6 +43,7 @@ class MeshDesc(ctypes.Structure):
         ("weno_eps", ctypes.c_double), ("weno_pow", ctypes.c_double),
         ("lambda_override", ctypes.c_double),
         ("stream", ctypes.c_void_p),
+        ("zhao_theta", ctypes.c_double),
     ]
 
 
@@ -141,6 +142,7 @@ def desc_from_fields(f: dict) -> MeshDesc:
     d.q, d.b, d.w_nb = f["q"], f["b"], f["w_nb"]
     d.weno_eps, d.weno_pow = f["eps"], f["r"]
     d.lambda_override = f["lambda_override"]
+    d.zhao_theta = f.get("theta", 1.0)
     return d
 
 

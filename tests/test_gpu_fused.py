@@ -51,6 +51,9 @@ def _cases():
         out.append(("rot2d_40x36", rot))
         out.append(("burgers2d_37x21", lambda p=p: inputs.burgers2d(37, p, seed=2, ny=21, steps=1)))
         out.append(("burgers2d_3x5", lambda p=p: inputs.burgers2d(3, p, seed=3, ny=5, steps=1)))
+        out.append(("burgers2d_37x21_zhao",
+                    lambda p=p: inputs.burgers2d(37, p, seed=2, ny=21, steps=1, mode=inputs.MODE_ZHAO)))
+    out.append(("adv1d_300_zhao", lambda: inputs.adv1d(300, 2, mode=inputs.MODE_ZHAO)))
     return out
 
 

@@ -58,7 +58,7 @@ KINDS = ["adv1d", "burgers1d", "rot2d", "burgers2d"]
 
 @pytest.mark.parametrize("kind", KINDS)
 @pytest.mark.parametrize("p", [1, 2, 3, 4])
-@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
 def test_rhs_parity(kind, p, mode):
     _note(f"[rhs parity] {kind} p={p} mode={mode}")
     w = _mesh(kind, p, mode)
@@ -143,6 +143,36 @@ def test_rotation_100_steps(p):
     w.cy = 0.5  # 0.5 = 20 h is a grid line
     O = oracle_for(w)
     _run_parity(w, oracle_initial(w, O), 100, O=O)
+
+
+@pytest.mark.parametrize("kind,p", [("adv1d", 3), ("rot2d", 2), ("burgers2d", 2)])
+def test_zhao_sensor_100_steps(kind, p):
+    """The sensor of Zhao et al. (Sec. 5.6) in place of eq. (sensor): 100 steps,
+    including non-periodic boundaries (rotation) where m_e < 2d."""
+    _note(f"[run parity] {kind} P{p} Zhao sensor, 100 steps")
+    if kind == "adv1d":
+        w = inputs.adv1d(300, p, mode=inputs.MODE_ZHAO)
+    elif kind == "rot2d":
+        w = inputs.rot2d(48, p, seed=3, ny=40, mode=inputs.MODE_ZHAO)
+        w.cy = 0.5
+    else:
+        w = inputs.burgers2d(40, p, seed=0, mode=inputs.MODE_ZHAO)
+    O = oracle_for(w)
+    U0 = oracle_initial(w, O)
+    if kind == "burgers2d":
+        U0 = O.run(U0, w.dt(), w.steps)   # past the shock time, on the oracle
+    _run_parity(w, U0, 100, O=O)
+
+
+def test_zhao_sensor_has_no_adjoint():
+    dgweno = _dg()
+    w = inputs.burgers2d(16, 2, mode=inputs.MODE_ZHAO, steps=1)
+    g = dgweno.DG.from_workload(w)
+    U = g.initial_state(w)
+    with pytest.raises(dgweno.DGError):
+        g.rhs_vjp(U, U.clone())
+    with pytest.raises(dgweno.DGError):
+        g.step_adjoint(U, w.dt(), U.clone())
 
 
 def test_burgers2d_100_steps_after_shock():
