@@ -41,6 +41,8 @@ def workload(name):
         "burgers2d_1024_p2": lambda: inputs.burgers2d(1024, 2, seed=0),
         "adv1d_64_p2": lambda: inputs.adv1d(64, 2, steps=100),
         "rot2d_2048_p2": lambda: inputs.rot2d(2048, 2, seed=0, steps=50),
+        # the sensor of Zhao et al. (Sec. 5.6) in place of eq. (sensor)
+        "rot2d_256_p2_zhao": lambda: inputs.rot2d(256, 2, seed=0, steps=200, mode=inputs.MODE_ZHAO),
         # DRAM-resident (302 MB per state array, beyond the 256 MB last-level
         # cache); its initial data take ~25 s to evaluate on the host, so it
         # is not among the default extras
@@ -354,7 +356,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="rot2d_256_p2")
-    ap.add_argument("--extra", default="rot2d_256_p3,burgers2d_1024_p2",
+    ap.add_argument("--extra", default="rot2d_256_p3,burgers2d_1024_p2,rot2d_256_p2_zhao",
                     help="comma-separated workloads reported alongside (no cpu baseline)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
