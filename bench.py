@@ -180,7 +180,7 @@ def bench_adjoint(n=512, steps=400, ndir=32, nsnaps=None, seed=0):
     initial DOFs of 2D Burgers (n x n, P2, seeded Fourier data, `steps` steps)
     by the checkpointed discrete adjoint; cost relative to the plain forward
     run; central differences (Richardson over delta, delta/2) of the GPU
-    forward run along `ndir` random unit directions at two step sizes."""
+    forward run along `ndir` random unit directions at six step sizes."""
     import numpy as np
     import torch
     from paper_2309_12019_amd import dgweno, inputs
@@ -257,13 +257,14 @@ def bench_adjoint(n=512, steps=400, ndir=32, nsnaps=None, seed=0):
         d /= d.norm()
         ad = float((grad * d).sum())
         row = {"ad": ad}
-        for tag, delta in (("1e-4", 1e-4 * umax), ("1e-6", 1e-6 * umax), ("1e-7", 1e-7 * umax), ("1e-8", 1e-8 * umax)):
+        for tag, delta in (("1e-4", 1e-4 * umax), ("1e-5", 1e-5 * umax), ("3e-6", 3e-6 * umax),
+                           ("1e-6", 1e-6 * umax), ("1e-7", 1e-7 * umax), ("1e-8", 1e-8 * umax)):
             fd1 = dJ(d, delta) / (2 * delta)
             fd2 = dJ(d, delta / 2) / delta
             fd = (4 * fd2 - fd1) / 3
             row[tag] = abs(fd - ad) / abs(ad)
         rows.append(row)
-    for tag in ("1e-4", "1e-6", "1e-7", "1e-8"):
+    for tag in ("1e-4", "1e-5", "3e-6", "1e-6", "1e-7", "1e-8"):
         errs = [r[tag] for r in rows]
         res[f"fd_delta_{tag}_umax"] = {"directions": ndir, "max_rel_err": max(errs),
                                        "median_rel_err": float(np.median(errs)),
