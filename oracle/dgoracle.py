@@ -13,6 +13,8 @@ Galerkin methods for hyperbolic problems" (arXiv 2309.12019).
 What is computed, in the paper's order and notation (all FP64, PyTorch CPU ops,
 vectorised over cells only; no blocking, fusion or reordering):
 
+* Fluxes: linear advection with a constant or rotating velocity, Burgers, and
+  the non-convex KPP flux F(u) = (sin u, cos u) of Sec. 5.5 (2D).
 * Sec. 2, eq. (weak2): the semi-discrete DG operator
       M dU/dt = R(U),
       R_i = int_K grad(phi_i) . F(U_h) dx - int_dK phi_i H(U^-, U^+, n) ds
@@ -58,7 +60,10 @@ coordinates; conservation, zero sensor on reproduced data, symmetries and the
 RK3 amplification polynomial; Table 1 and Table 2 of Sec. 5 (DG and LO
 columns); the reverse mode against finite differences; the Zhao et al. sensor
 is 0 on reproduced data, reaches 1 when one neighbour candidate takes all the
-weight, lies in [0, 1] and is shift- and mirror-invariant.  The Hermite candidates
+weight, lies in [0, 1] and is shift- and mirror-invariant; the KPP flux's
+operator against the brute-force integrals (its LLF wave speed against a
+search along the segment), and the three schemes on the KPP problem against
+the solution ranges Sec. 5.5 prints.  The Hermite candidates
 and nonlinear weights are a reading (the paper defers them to another
 reference): against the paper's WENO columns they are parity unpinned, and only
 the stated behaviour (optimal rates; WENO equal to DG with a threshold) is
@@ -78,6 +83,7 @@ DTYPE = torch.float64
 
 LINADV = 0   # F(u) = v(x) u, v(x) = (vx - omega (y - cy), vy + omega (x - cx))
 BURGERS = 1  # F(u) = a u^2 / 2, a = (vx, vy)
+KPP = 2      # F(u) = (sin u, cos u), the non-convex flux of Sec. 5.5 (2D)
 
 MODE_DG, MODE_LO, MODE_WENO = 0, 1, 2   # labels of Sec. 5
 MODE_ZHAO = 3   # the sensor of Zhao et al. that Sec. 5.6 compares with
@@ -150,6 +156,8 @@ class Problem:
             hy = (self.y1 - self.y0) / self.ny
             if abs(hy - self.h) > 1e-12 * abs(self.h):
                 raise ValueError("2D cells must be square")
+        if self.flux == KPP and self.dim != 2:
+            raise ValueError("the KPP flux is two-dimensional")
 
     def qv(self) -> int:
         """Volume Gauss points per axis (exact for the polynomial part)."""
@@ -157,6 +165,8 @@ class Problem:
             return self.quad_vol
         if self.flux == LINADV:
             return self.p + 1
+        if self.flux == KPP:
+            return self.p + 2
         if self.dim == 1:
             return -(-3 * self.p // 2)
         return -(-(3 * self.p + 1) // 2)
@@ -389,6 +399,8 @@ class Oracle:
         P = self.P
         if P.flux == LINADV:
             return [v * u for v in self.velocity(x, y)]
+        if P.flux == KPP:
+            return [torch.sin(u), torch.cos(u)]
         a = (P.vx,) if P.dim == 1 else (P.vx, P.vy)
         return [ai * 0.5 * u * u for ai in a]
 
@@ -397,18 +409,29 @@ class Oracle:
         P = self.P
         if P.flux == LINADV:
             return [v + 0.0 * u for v in self.velocity(x, y)]
+        if P.flux == KPP:
+            return [torch.cos(u), -torch.sin(u)]
         a = (P.vx,) if P.dim == 1 else (P.vx, P.vy)
         return [ai * u for ai in a]
 
     def llf(self, um, up, axis, side, x, y):
         """Local Lax-Friedrichs flux H(U^-, U^+, n), n = side * e_axis (Sec. 2).
-        F'(w U^- + (1-w) U^+) . n is affine in w for both fluxes, so the
-        maximum of its modulus over [0,1] is attained at an end point."""
+        For the linear and Burgers fluxes F'(w U^- + (1-w) U^+) . n is affine
+        in w, so the maximum of its modulus over [0,1] is attained at an end
+        point.  For KPP it is |cos w| (x faces) or |sin w| (y faces) for w
+        between the two states: 1 where that interval holds a point k pi (x)
+        or pi/2 + k pi (y), else the larger end value (|cos| and |sin| fall
+        and rise between consecutive such points)."""
         Fm = self.flux(um, x, y)[axis] * side
         Fp = self.flux(up, x, y)[axis] * side
         sm = torch.abs(self.dflux(um, x, y)[axis] * side)
         sp = torch.abs(self.dflux(up, x, y)[axis] * side)
         s_plus = torch.maximum(sm, sp)
+        if self.P.flux == KPP:
+            lo, hi = torch.minimum(um, up), torch.maximum(um, up)
+            shift = 0.0 if axis == 0 else 0.5 * math.pi
+            peak = torch.floor((hi - shift) / math.pi) >= torch.ceil((lo - shift) / math.pi)
+            s_plus = torch.where(peak, torch.ones_like(s_plus), s_plus)
         return 0.5 * (Fm + Fp) - 0.5 * s_plus * (up - um)
 
     # ------------------------------------------------------------------

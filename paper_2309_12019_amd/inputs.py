@@ -20,7 +20,7 @@ from typing import Callable, List, Optional
 
 import numpy as np
 
-LINADV, BURGERS = 0, 1
+LINADV, BURGERS, KPP = 0, 1, 2
 MODE_DG, MODE_LO, MODE_WENO = 0, 1, 2
 MODE_ZHAO = 3   # the sensor of Zhao et al. compared in Sec. 5.6
 
@@ -82,6 +82,9 @@ class Workload:
             far = max(math.hypot(x - self.cx, y - self.cy)
                       for x in (self.x0, self.x1) for y in (self.y0, self.y1))
             return math.hypot(abs(self.vx), abs(self.vy)) + abs(self.omega) * far
+        if self.flux == KPP:
+            # ||F'(u)||_2 = 1; a larger lambda override also bounds the step
+            return max(1.0, self.lambda_override)
         a = abs(self.vx) if self.dim == 1 else math.hypot(self.vx, self.vy)
         return a * self.umax
 
@@ -190,6 +193,12 @@ class HumpAndCylinder:
         return u + o.fl(inside & ~slot)
 
 
+def kpp_disc(x, y):
+    """7 pi / 2 on the unit disc about the origin, pi / 4 outside (Sec. 5.5)."""
+    o = _Ops(x)
+    return o.where(x * x + y * y <= 1.0, 3.5 * np.pi, 0.25 * np.pi)
+
+
 class FourierModes:
     """u0 = sum_j a_j cos(2 pi k_j . x + phi_j): 16 modes, integer wave vectors
     with 1 <= |k| <= 8 drawn uniformly, a_j ~ N(0,1)/|k_j|^2, phi_j ~ U[0, 2pi)."""
@@ -293,3 +302,16 @@ def batch_mix(seed: int = 0, count: int = 512, steps: int = 100) -> List[Workloa
         w.name = f"b{i}_{w.name}"
         out.append(w)
     return out
+
+
+def kpp2d(n: int = 128, p: int = 2, mode: int = MODE_WENO, steps: Optional[int] = None,
+          cfl: float = 0.1, lam: float = 2.0, t_end: float = 1.0) -> Workload:
+    """The KPP problem of Sec. 5.5: u_t + div (sin u, cos u) = 0 on
+    (-2, 2) x (-2.5, 1.5), n x n cells, lambda_e fixed at `lam` (the paper
+    uses 2), the outer state pi/4 outside the mesh, run to t_end."""
+    w = Workload(name=f"kpp2d_{n}_p{p}", dim=2, nx=n, ny=n, x0=-2.0, x1=2.0, y0=-2.5, y1=1.5,
+                 periodic_x=False, periodic_y=False, p=p, flux=KPP, vx=0.0, vy=0.0,
+                 bc_value=0.25 * np.pi, mode=mode, lambda_override=lam, cfl=cfl, ic=kpp_disc,
+                 umax=3.5 * np.pi)
+    w.steps = steps if steps is not None else int(math.ceil(t_end / w.dt()))
+    return w

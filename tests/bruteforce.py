@@ -11,8 +11,11 @@ evaluates, for every cell K_e:
   sensor gamma_e built from the continued neighbour polynomials (Sec. 4)
 * dU/dt = M^{-1}(R - s)
 
-Integrands that are not polynomials (the Burgers LLF wave speed, lambda_e) use
-the same Gauss point counts as the method, taken from numpy.
+Integrands that are not polynomials (the Burgers LLF wave speed, lambda_e,
+every integrand of the KPP flux) use the same Gauss point counts as the
+method, taken from numpy.  The LLF wave speed s+ is the maximum of |F'.n|
+along the segment between the two states, found by sampling the segment and
+refining the best sample by ternary search.
 """
 
 import math
@@ -108,6 +111,8 @@ class Brute:
 
     def F(self, u, x, y):
         w = self.w
+        if w.flux == 2:
+            return (np.sin(u), np.cos(u))
         if w.flux == 0:
             vx, vy = self.vel(x, y)
             return (vx * u,) if self.d == 1 else (vx * u, vy * u)
@@ -115,6 +120,8 @@ class Brute:
 
     def dF(self, u, x, y):
         w = self.w
+        if w.flux == 2:
+            return (np.cos(u), -np.sin(u))
         if w.flux == 0:
             vx, vy = self.vel(x, y)
             return (vx + 0 * u,) if self.d == 1 else (vx + 0 * u, vy + 0 * u)
@@ -133,8 +140,8 @@ class Brute:
         c = self.centre(e)
         n = self.n1 ** self.d
         R = np.zeros(n)
-        # volume (polynomial integrand: high-order rule)
-        x, y, W = self.cell_rule(e, HIGH)
+        # volume (polynomial integrand: high-order rule; KPP: the method's rule)
+        x, y, W = self.cell_rule(e, qv if w.flux == 2 else HIGH)
         u = self.value(U[e], c, x, y)
         Fx = self.F(u, x, y)
         for j in range(n):
@@ -149,7 +156,7 @@ class Brute:
                     yf = None
                     wf = np.array([1.0])
                 else:
-                    nq = qf if w.flux == 1 else HIGH
+                    nq = qf if w.flux in (1, 2) else HIGH
                     t, wt = _gauss(nq)
                     if ax == 0:
                         xf = np.full(nq, c[0] + side * self.h / 2)
@@ -172,6 +179,21 @@ class Brute:
                 xs = np.broadcast_to(xf, seg.shape)
                 ys = None if yf is None else np.broadcast_to(yf, seg.shape)
                 sp = np.max(np.abs(self.dF(seg, xs, ys)[ax] * side), axis=0)
+                best = np.argmax(np.abs(self.dF(seg, xs, ys)[ax] * side), axis=0)
+                for q in range(um.shape[0]):
+                    def f(t, q=q):
+                        s_ = np.array([t * um[q] + (1 - t) * up[q]])
+                        xq = np.array([xf[q]])
+                        yq = None if yf is None else np.array([yf[q]])
+                        return float(np.abs(self.dF(s_, xq, yq)[ax] * side)[0])
+                    a_, b_ = max(0.0, wgrid[max(best[q] - 1, 0), 0]), min(1.0, wgrid[min(best[q] + 1, 2000), 0])
+                    for _ in range(100):
+                        m1, m2 = a_ + (b_ - a_) / 3, b_ - (b_ - a_) / 3
+                        if f(m1) < f(m2):
+                            a_ = m1
+                        else:
+                            b_ = m2
+                    sp[q] = max(sp[q], f(0.5 * (a_ + b_)))
                 H = 0.5 * (Fm + Fp) - 0.5 * sp * (up - um)
                 for j in range(n):
                     R[j] -= np.sum(wf * H * self.value(self.unit(j), c, xf, yf))

@@ -26,7 +26,9 @@ for p in (1, 2, 3):
     CASES.append(("rot2d", p, inputs.MODE_WENO))
     CASES.append(("burgers2d", p, inputs.MODE_WENO))
 CASES += [("rot2d", 2, inputs.MODE_LO), ("burgers2d", 2, inputs.MODE_DG),
-          ("adv2d", 2, inputs.MODE_WENO), ("rot2d_per", 2, inputs.MODE_WENO)]
+          ("adv2d", 2, inputs.MODE_WENO), ("rot2d_per", 2, inputs.MODE_WENO),
+          ("kpp2d", 1, inputs.MODE_WENO), ("kpp2d", 2, inputs.MODE_DG), ("kpp2d", 2, inputs.MODE_WENO),
+          ("kpp2d_per", 3, inputs.MODE_LO)]
 
 
 def _workload(kind, p, mode):
@@ -46,6 +48,10 @@ def _workload(kind, p, mode):
         w = inputs.rot2d(3, p, mode=mode)
         w.omega, w.vx, w.vy = 0.0, 0.6, -1.1
         w.periodic_x, w.bc_value = True, 0.4
+    elif kind.startswith("kpp2d"):
+        w = inputs.kpp2d(3, p, mode=mode, steps=1, lam=0.0)
+        if kind == "kpp2d_per":
+            w.periodic_x = w.periodic_y = True
     else:
         w = inputs.burgers2d(3, p, steps=1)
         w.mode = mode
@@ -59,6 +65,8 @@ def test_rhs_matches_bruteforce(kind, p, mode):
     O = oracle_for(w)
     for seed, smooth in ((1, False), (2, True)):
         U = _random_state(w, seed, smooth)
+        if kind.startswith("kpp2d"):
+            U = 3.0 * U   # states several pi apart: s+ peaks inside the segments
         L, gam = O.rhs(torch.from_numpy(U), with_gamma=True)
         lam = O.max_speed(torch.from_numpy(U))
         Lb, gb, lb = Brute(w).rhs(U, O.P.qv(), O.P.qf())

@@ -136,3 +136,31 @@ def test_table2_weno_equals_dg_with_threshold(N):
     vanishes on smooth data, so the p = 2 WENO errors equal the DG errors, as the
     p = 2 WENO column of Table 2 shows from E_h = 32 on."""
     assert abs(_burgers_weno_b(2, N, 0.05) / _burgers_error(2, N, inputs.MODE_DG) - 1) < 1e-9
+
+
+def test_kpp_qualitative_behaviour_of_the_three_schemes():
+    """Sec. 5.5 (KPP, t = 1, p = 2, lambda_e = 2): the paper prints the range of
+    u_h for each scheme (tests/golden/kpp_ranges.json, 128^2 cells).  DG leaves
+    the range of the initial data [pi/4, 7 pi/2] by tens; LO stays inside it
+    (its printed range is that interval to three decimals); WENO stays within
+    a small overshoot of it (printed: up to 11.066).  On 32^2 cells (the oracle's
+    bounded cost) the same three behaviours hold."""
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "kpp_ranges.json")))
+    lo0, hi0 = g["initial_range"]
+    assert abs(lo0 - math.pi / 4) < 1e-15 and abs(hi0 - 3.5 * math.pi) < 1e-14
+    rng = {}
+    for mode, name in ((inputs.MODE_DG, "DG"), (inputs.MODE_LO, "LO"), (inputs.MODE_WENO, "WENO")):
+        w = inputs.kpp2d(32, 2, mode=mode)
+        O = oracle_for(w)
+        U = O.run(oracle_initial(w, O), w.dt(), w.steps)
+        vals, _ = O.evaluate(U, 4)
+        rng[name] = (float(vals.min()), float(vals.max()))
+    pdg, plo, pweno = (g["printed_range"][k] for k in ("DG", "LO", "WENO"))
+    # DG: far outside, as printed
+    assert pdg[0] < lo0 - 10 and pdg[1] > hi0 + 10
+    assert rng["DG"][0] < lo0 - 1 and rng["DG"][1] > hi0 + 1
+    # LO: inside the initial range, as printed (three decimals)
+    assert plo[0] >= round(lo0, 3) - 1e-3 and plo[1] <= round(hi0, 3) + 1e-3
+    assert rng["LO"][0] >= lo0 - 1e-3 and rng["LO"][1] <= hi0 + 1e-3
+    # WENO: within the printed overshoot of the initial range
+    assert rng["WENO"][0] >= pweno[0] - 1e-2 and rng["WENO"][1] <= pweno[1] + 1e-2
