@@ -9,6 +9,9 @@
  *   DG_FLUX_LINADV : F(u) = v(x) u,  v = (vel_x - omega (y - rot_cy),
  *                                         vel_y + omega (x - rot_cx))
  *   DG_FLUX_BURGERS: F(u) = a u^2 / 2, a = (vel_x, vel_y)
+ *   DG_FLUX_KPP    : F(u) = (sin u, cos u), the non-convex flux of Sec. 5.5
+ *                    (2D only; LLF wave speed max |F'(w) . n| over w between
+ *                    the two states, exactly; p + 2 quadrature points)
  * discretised in the broken space V_p (Sec. 2): tensor Legendre polynomials
  * of degree p per axis on every cell.  The library evaluates
  *   dU/dt = M^{-1} (R(U) - s(U))
@@ -51,7 +54,7 @@ enum dg_status {
   DG_EUNSUPPORTED = -5  /* valid but not built (e.g. an unsupported size) */
 };
 
-enum dg_flux { DG_FLUX_LINADV = 0, DG_FLUX_BURGERS = 1 };
+enum dg_flux { DG_FLUX_LINADV = 0, DG_FLUX_BURGERS = 1, DG_FLUX_KPP = 2 };
 
 /* Scheme labels of Sec. 5: DG (no stabilisation), LO (gamma_e = 1 in
  * eq. astab, i.e. the low-order operator of eq. lostab), WENO (gamma_e from
@@ -186,7 +189,7 @@ const char* dg_last_error(void);
  * used (ties: split evenly).  The first adjoint call on a context allocates
  * two state-sized buffers and two sensor-record buffers (DG_EUNSUPPORTED if
  * the adjoint kernels' tile exceeds LDS).  Every adjoint call returns
- * DG_EUNSUPPORTED for mode ZHAO.
+ * DG_EUNSUPPORTED for mode ZHAO and for the KPP flux.
  * ------------------------------------------------------------------------ */
 
 /* out = J(U)^T v: the transpose Jacobian of dU/dt = L(U) (dg_rhs) applied to

@@ -212,7 +212,9 @@ int validate(const dg_mesh_desc* d) {
     const double hx = (d->x1 - d->x0) / d->nx, hy = (d->y1 - d->y0) / d->ny;
     if (std::fabs(hx - hy) > 1e-12 * hx) return fail(DG_EINVAL, "2D cells must be square (hx=%g hy=%g)", hx, hy);
   }
-  if (d->flux != DG_FLUX_LINADV && d->flux != DG_FLUX_BURGERS) return fail(DG_EINVAL, "unknown flux %d", d->flux);
+  if (d->flux != DG_FLUX_LINADV && d->flux != DG_FLUX_BURGERS && d->flux != DG_FLUX_KPP)
+    return fail(DG_EINVAL, "unknown flux %d", d->flux);
+  if (d->flux == DG_FLUX_KPP && d->dim != 2) return fail(DG_EINVAL, "the KPP flux is two-dimensional");
   if (d->mode != DG_MODE_DG && d->mode != DG_MODE_LO && d->mode != DG_MODE_WENO && d->mode != DG_MODE_ZHAO)
     return fail(DG_EINVAL, "unknown mode %d", d->mode);
   if (!(d->zhao_theta > 0.0) || !std::isfinite(d->zhao_theta)) return fail(DG_EINVAL, "zhao_theta must be > 0");
@@ -252,6 +254,7 @@ int zrec_size(int dim, int nl) { return dgk::zrec_doubles(dim, nl); }
 
 int ensure_adjoint(dg_ctx* c) {
   if (c->d.mode == DG_MODE_ZHAO) return fail(DG_EUNSUPPORTED, "the adjoint does not cover the ZHAO sensor");
+  if (c->d.flux == DG_FLUX_KPP) return fail(DG_EUNSUPPORTED, "the adjoint does not cover the KPP flux");
   if (c->A1) return DG_OK;
   // the adjoint kernels' tiles hold the state and the cotangent
   const int atx = c->d.dim == 2 ? dgk::kAdjTileX : c->tx, aty = c->d.dim == 2 ? dgk::kAdjTileY : 1;
@@ -847,6 +850,7 @@ int dg_adjoint_forward(dg_ctx* c, const double* U0, double* UT, double dt, int32
                        double* ckpt, double* stages) {
   if (!c || !U0 || !UT || !ckpt) return fail(DG_EINVAL, "NULL argument");
   if (c->d.mode == DG_MODE_ZHAO) return fail(DG_EUNSUPPORTED, "the adjoint does not cover the ZHAO sensor");
+  if (c->d.flux == DG_FLUX_KPP) return fail(DG_EUNSUPPORTED, "the adjoint does not cover the KPP flux");
   if (nsteps < 1 || nsnaps < 0) return fail(DG_EINVAL, "need nsteps >= 1 and nsnaps >= 0");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite and > 0");
   const size_t n = (size_t)c->ncells * c->nl;

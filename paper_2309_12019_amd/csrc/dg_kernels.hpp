@@ -27,7 +27,7 @@
 
 namespace dgk {
 
-enum { FLUX_LINADV = 0, FLUX_BURGERS = 1 };
+enum { FLUX_LINADV = 0, FLUX_BURGERS = 1, FLUX_KPP = 2 };  // KPP: 2D only
 enum { MODE_DG = 0, MODE_LO = 1, MODE_WENO = 2, MODE_ZHAO = 3 };
 
 struct StageArgs {
@@ -100,6 +100,9 @@ __device__ inline double rcp(double x) {
 
 // general powers (cold paths: exponents other than the defaults)
 __device__ __noinline__ double pow_cold(double x, double y) { return pow(x, y); }
+// sin and cos of the KPP flux, out of line: inlined at every quadrature node
+// their argument reduction would set the register count of the whole kernel
+__device__ __noinline__ void sincos_cold(double x, double* s, double* c) { sincos(x, s, c); }
 
 // sqrt(x) for x > 0: hardware estimate and one Newton correction
 __device__ inline double sqrt_pos(double x) {
@@ -245,6 +248,23 @@ struct Cell {
     if (!(ratio >= A.bthr)) return 0.0;
     const double r1 = fmin(1.0, ratio);
     return A.q == 1.0 ? r1 : pow_cold(r1, A.q);
+  }
+
+  // KPP flux F(u) = (sin u, cos u) of Sec. 5.5: H(um, up, n), n = s e_axis,
+  // with s+ = max |F'(w) . n| over w between the states, i.e. max |cos w|
+  // (x faces) or |sin w| (y faces): 1 where that interval holds a peak
+  // (k pi, resp. pi/2 + k pi), else the larger end value
+  __device__ static inline double llf_kpp(int axis, double s, double um, double up) {
+    constexpr double kPi = 3.141592653589793238462643383279502884;
+    double sm, cm, sp, cp;
+    sincos_cold(um, &sm, &cm);
+    sincos_cold(up, &sp, &cp);
+    const double Fm = axis == 0 ? sm : cm, Fp = axis == 0 ? sp : cp;
+    const double dm = axis == 0 ? fabs(cm) : fabs(sm), dp = axis == 0 ? fabs(cp) : fabs(sp);
+    const double shift = axis == 0 ? 0.0 : 0.5 * kPi;
+    const bool peak = floor((fmax(um, up) - shift) / kPi) >= ceil((fmin(um, up) - shift) / kPi);
+    const double splus = peak ? 1.0 : fmax(dm, dp);
+    return 0.5 * (s * Fm + s * Fp) - 0.5 * splus * (up - um);
   }
 
   // numerical flux H(um, up, n), n = s e_axis, v = normal velocity component
@@ -413,6 +433,8 @@ struct Cell {
           if constexpr (FLUX == FLUX_LINADV) {
             Fx = vxl[qy] * u;
             Fy = vyl[qx] * u;
+          } else if constexpr (FLUX == FLUX_KPP) {
+            sincos_cold(u, &Fx, &Fy);
           } else {
             const double hu2 = 0.5 * u * u;
             Fx = A.vx * hu2;
@@ -449,6 +471,8 @@ struct Cell {
           my = fmax(my, vyl[k] * vyl[k]);
         }
         lam = sqrt_pos(mx + my);
+      } else if constexpr (FLUX == FLUX_KPP) {
+        lam = 1.0;  // ||F'(u)||_2 = ||(cos u, -sin u)||_2
       } else {
         lam = A.anorm * umax;
       }
@@ -483,7 +507,11 @@ struct Cell {
             up = fma(tp[k], TB::nd.L[k][r], up);
           }
           const double vax = axis == 0 ? vxl[r] : vyl[r];
-          const double H = llf(A, s, vax, um, up);
+          double H;
+          if constexpr (FLUX == FLUX_KPP)
+            H = llf_kpp(axis, s, um, up);
+          else
+            H = llf(A, s, vax, um, up);
 #pragma unroll
           for (int k = 0; k < N; ++k) {
             const double cw = TB::nd.w[r] * TB::nd.L[k][r];
@@ -1032,6 +1060,8 @@ __global__ void __launch_bounds__(256) lambda_kernel(const StageArgs A, const do
     const double hh = 0.5 * A.h;
     if (A.lam_over > 0.0) {
       lam = A.lam_over;
+    } else if constexpr (FLUX == FLUX_KPP) {
+      lam = 1.0;  // ||(cos u, -sin u)||_2
     } else if constexpr (FLUX == FLUX_LINADV) {
       if constexpr (DIM == 1) {
         lam = fabs(A.vx);

@@ -190,21 +190,29 @@ extern "C" hipError_t DGK_CAT(dgk_launch, DGK_DIM, DGK_P)(const LaunchReq* r) {
   switch (r->kind) {
     case LAUNCH_STAGE: {
       if (r->flux == FLUX_LINADV) return launch_stage_f<FLUX_LINADV>(r->mode, A, r->stream);
-      return launch_stage_f<FLUX_BURGERS>(r->mode, A, r->stream);
+      if (r->flux == FLUX_BURGERS) return launch_stage_f<FLUX_BURGERS>(r->mode, A, r->stream);
+      if constexpr (DGK_DIM == 2) return launch_stage_f<FLUX_KPP>(r->mode, A, r->stream);
+      return hipErrorInvalidValue;
     }
     case LAUNCH_STEP: {
       if (r->flux == FLUX_LINADV) return launch_step_f<FLUX_LINADV>(r->mode, A, r->stream);
-      return launch_step_f<FLUX_BURGERS>(r->mode, A, r->stream);
+      if (r->flux == FLUX_BURGERS) return launch_step_f<FLUX_BURGERS>(r->mode, A, r->stream);
+      if constexpr (DGK_DIM == 2) return launch_step_f<FLUX_KPP>(r->mode, A, r->stream);
+      return hipErrorInvalidValue;
     }
     case LAUNCH_BATCH: {
       if (r->flux == FLUX_LINADV) return launch_batch_f<FLUX_LINADV>(r);
-      return launch_batch_f<FLUX_BURGERS>(r);
+      if (r->flux == FLUX_BURGERS) return launch_batch_f<FLUX_BURGERS>(r);
+      if constexpr (DGK_DIM == 2) return launch_batch_f<FLUX_KPP>(r);
+      return hipErrorInvalidValue;
     }
     case LAUNCH_ADJ_SENSOR:
     case LAUNCH_ADJ_GRAD:
     case LAUNCH_ADJ_GRAD_SENSOR: {
+      // the adjoint covers the linear and Burgers fluxes
       if (r->flux == FLUX_LINADV) return launch_adj_f<FLUX_LINADV>(r);
-      return launch_adj_f<FLUX_BURGERS>(r);
+      if (r->flux == FLUX_BURGERS) return launch_adj_f<FLUX_BURGERS>(r);
+      return hipErrorInvalidValue;
     }
     case LAUNCH_PROJECT: {
       const long long n = r->ncells;
@@ -218,9 +226,14 @@ extern "C" hipError_t DGK_CAT(dgk_launch, DGK_DIM, DGK_P)(const LaunchReq* r) {
       if (r->flux == FLUX_LINADV)
         hipLaunchKernelGGL((lambda_kernel<DGK_DIM, DGK_P, FLUX_LINADV>), grid, block, 0, r->stream, A, r->src,
                            r->dst);
-      else
+      else if (r->flux == FLUX_BURGERS)
         hipLaunchKernelGGL((lambda_kernel<DGK_DIM, DGK_P, FLUX_BURGERS>), grid, block, 0, r->stream, A, r->src,
                            r->dst);
+      else if constexpr (DGK_DIM == 2)
+        hipLaunchKernelGGL((lambda_kernel<DGK_DIM, DGK_P, FLUX_KPP>), grid, block, 0, r->stream, A, r->src,
+                           r->dst);
+      else
+        return hipErrorInvalidValue;
       return hipGetLastError();
     }
   }

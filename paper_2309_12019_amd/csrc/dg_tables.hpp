@@ -281,8 +281,10 @@ constexpr SenTab<DIM, P> make_sen() {
 // Gauss points per axis used for volume and face quadrature: exact for the
 // polynomial part of the integrands.  Linear flux: degree 2p+1 -> p+1 points.
 // Burgers: 1D degree 3p-1 -> ceil(3p/2); 2D degree 3p -> ceil((3p+1)/2).
+// KPP (sin and cos of u_h: no exact rule): p+2.
 constexpr int quad_points(int dim, int p, int flux) {
   if (flux == 0) return p + 1;
+  if (flux == 2) return p + 2;
   return dim == 1 ? (3 * p + 1) / 2 : (3 * p + 2) / 2;
 }
 

@@ -54,6 +54,8 @@ def _cases():
         out.append(("burgers2d_37x21_zhao",
                     lambda p=p: inputs.burgers2d(37, p, seed=2, ny=21, steps=1, mode=inputs.MODE_ZHAO)))
     out.append(("adv1d_300_zhao", lambda: inputs.adv1d(300, 2, mode=inputs.MODE_ZHAO)))
+    for p in (1, 2, 3):
+        out.append(("kpp2d_40", lambda p=p: inputs.kpp2d(40, p, steps=1)))
     return out
 
 

@@ -42,6 +42,8 @@ def _mesh(kind, p, mode, n1=600, n2=(40, 36)):
         w.cy = 0.45  # keeps v.n single-signed on every face (y = 0.45 is a grid line)
     elif kind == "burgers2d":
         w = inputs.burgers2d(n2[0], p, mode=mode, ny=n2[1], steps=1)
+    elif kind == "kpp2d":
+        w = inputs.kpp2d(n2[0], p, mode=mode, steps=1, lam=0.0)   # lambda_e from F' (= 1)
     else:
         raise ValueError(kind)
     return w
@@ -53,7 +55,7 @@ def _state(w, O, seed):
     return U + 0.01 * torch.from_numpy(rng.standard_normal(U.shape)) * U.abs().max()
 
 
-KINDS = ["adv1d", "burgers1d", "rot2d", "burgers2d"]
+KINDS = ["adv1d", "burgers1d", "rot2d", "burgers2d", "kpp2d"]
 
 
 @pytest.mark.parametrize("kind", KINDS)
@@ -162,6 +164,26 @@ def test_zhao_sensor_100_steps(kind, p):
     if kind == "burgers2d":
         U0 = O.run(U0, w.dt(), w.steps)   # past the shock time, on the oracle
     _run_parity(w, U0, 100, O=O)
+
+
+@pytest.mark.parametrize("mode", [inputs.MODE_LO, inputs.MODE_WENO])
+def test_kpp_100_steps(mode):
+    """The KPP flux of Sec. 5.5 (non-convex, sin/cos), 40 x 40 cells, P2,
+    lambda_e = 2 as in the paper, 100 steps from the disc data (shocks and
+    rarefactions from the first step)."""
+    _note(f"[run parity] kpp2d 40x40 P2 mode={mode}, 100 steps")
+    w = inputs.kpp2d(40, 2, mode=mode, steps=100)
+    O = oracle_for(w)
+    _run_parity(w, oracle_initial(w, O), 100, O=O)
+
+
+def test_kpp_has_no_adjoint():
+    dgweno = _dg()
+    w = inputs.kpp2d(16, 2, steps=1)
+    g = dgweno.DG.from_workload(w)
+    U = g.initial_state(w)
+    with pytest.raises(dgweno.DGError):
+        g.rhs_vjp(U, U.clone())
 
 
 def test_zhao_sensor_has_no_adjoint():
