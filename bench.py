@@ -43,6 +43,8 @@ def workload(name):
         "rot2d_2048_p2": lambda: inputs.rot2d(2048, 2, seed=0, steps=50),
         # the sensor of Zhao et al. (Sec. 5.6) in place of eq. (sensor)
         "rot2d_256_p2_zhao": lambda: inputs.rot2d(256, 2, seed=0, steps=200, mode=inputs.MODE_ZHAO),
+        # the KPP problem of Sec. 5.5 at the paper's size (128^2, P2, lambda_e = 2, t = 1)
+        "kpp2d_128_p2": lambda: inputs.kpp2d(128, 2),
         # DRAM-resident (302 MB per state array, beyond the 256 MB last-level
         # cache); its initial data take ~25 s to evaluate on the host, so it
         # is not among the default extras
@@ -357,7 +359,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="rot2d_256_p2")
-    ap.add_argument("--extra", default="rot2d_256_p3,burgers2d_1024_p2,rot2d_256_p2_zhao",
+    ap.add_argument("--extra", default="rot2d_256_p3,burgers2d_1024_p2,rot2d_256_p2_zhao,kpp2d_128_p2",
                     help="comma-separated workloads reported alongside (no cpu baseline)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
