@@ -372,7 +372,7 @@ def main():
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU domain decomposition is a design note, not a code path.", file=sys.stderr)
         sys.exit(2)
     import torch
