@@ -33,7 +33,9 @@ vectorised over cells only; no blocking, fusion or reordering):
       ||v||_e^2 = sum_{1<=|k|<=p} h^{2|k|-d} int_K |D^k v|^2 dx,
   with the Hermite-WENO reconstruction U* = sum_l omega_l U_l and the linear
   weights of Sec. 5 (omega~_0 = 1 - m_e w, omega~_l = w).
-* Sec. 2, eq. (ssp): the three-stage SSP Runge-Kutta step.
+* Sec. 2, eq. (ssp): the three-stage SSP Runge-Kutta step; also the
+  second-order and the five-stage fourth-order SSP methods (Sec. 5.1 uses SSP
+  methods of order p + 1 for its convergence study).
 
 Readings where the paper is silent (they are listed again, with reasons, in the
 project's design notes):
@@ -56,8 +58,10 @@ project's design notes):
 Pins (tests/test_oracle_*.py): Gauss rules, Legendre polynomials, mass and
 stiffness matrices and the semi-norm against closed forms; the operator, sensor
 and wave speed against a brute-force evaluation of the integrals in physical
-coordinates; conservation, zero sensor on reproduced data, symmetries and the
-RK3 amplification polynomial; Table 1 and Table 2 of Sec. 5 (DG and LO
+coordinates; conservation, zero sensor on reproduced data, symmetries; the
+amplification polynomials of the three SSP methods (the Taylor coefficients of
+exp up to their order), their orders in time against the exact propagator, and
+the five-stage table's consistency and SSP coefficient 1.508; Table 1 and Table 2 of Sec. 5 (DG and LO
 columns); the reverse mode against finite differences; the Zhao et al. sensor
 is 0 on reproduced data, reaches 1 when one neighbour candidate takes all the
 weight, lies in [0, 1] and is shift- and mirror-invariant; the KPP flux's
@@ -123,6 +127,7 @@ class Problem:
     eps: float = 1e-6
     r: float = 2.0
     theta: float = 1.0   # exponent of the Zhao et al. sensor (mode MODE_ZHAO)
+    rk_order: int = 3    # SSP Runge-Kutta order: 2, 3 (eq. ssp) or 4 (five stages)
     lambda_override: float = 0.0
     quad_vol: int = 0
     quad_face: int = 0
@@ -556,8 +561,39 @@ class Oracle:
         L = (self.galerkin_residual(U) - self.dissipation(U, gam)) @ self.Minv.T
         return (L, gam) if with_gamma else L
 
+    # Shu-Osher coefficients of the five-stage fourth-order SSP Runge-Kutta
+    # method of Spiteri and Ruuth (as tabulated by Gottlieb, Ketcheson and Shu):
+    # U_k = sum_j (alpha_kj U_j + beta_kj dt L(U_j)), rows k = 1..5 over j = 0..4
+    SSP54_ALPHA = ((1.0,),
+                   (0.444370493651235, 0.555629506348765),
+                   (0.620101851488403, 0.0, 0.379898148511597),
+                   (0.178079954393132, 0.0, 0.0, 0.821920045606868),
+                   (0.0, 0.0, 0.517231671970585, 0.096059710526147, 0.386708617503269))
+    SSP54_BETA = ((0.391752226571890,),
+                  (0.0, 0.368410593050371),
+                  (0.0, 0.0, 0.251891774271694),
+                  (0.0, 0.0, 0.0, 0.544974750228521),
+                  (0.0, 0.0, 0.0, 0.063692468666290, 0.226007483236906))
+
     def step(self, U: torch.Tensor, dt: float) -> torch.Tensor:
-        """Eq. (ssp): the optimal third-order SSP Runge-Kutta step."""
+        """One SSP Runge-Kutta step of the problem's order: eq. (ssp), the
+        optimal third-order method (the default); the second-order one; or the
+        five-stage fourth-order one (Sec. 5.1 runs SSP methods of order p + 1
+        for its convergence study)."""
+        k = self.P.rk_order
+        if k == 2:
+            U1 = U + dt * self.rhs(U)
+            return 0.5 * U + 0.5 * U1 + 0.5 * dt * self.rhs(U1)
+        if k == 4:
+            stages = [U]
+            Ls = [self.rhs(U)]
+            for row_a, row_b in zip(self.SSP54_ALPHA, self.SSP54_BETA):
+                Uk = sum(a * Uj for a, Uj in zip(row_a, stages) if a != 0.0)
+                Uk = Uk + sum(b * dt * Lj for b, Lj in zip(row_b, Ls) if b != 0.0)
+                stages.append(Uk)
+                if len(stages) <= 5:
+                    Ls.append(self.rhs(Uk))
+            return stages[-1]
         U1 = U + dt * self.rhs(U)
         U2 = 0.75 * U + 0.25 * U1 + 0.25 * dt * self.rhs(U1)
         return U / 3.0 + (2.0 / 3.0) * U2 + (2.0 / 3.0) * dt * self.rhs(U2)

@@ -52,6 +52,7 @@ class Workload:
     eps: float = 1e-6
     r: float = 2.0
     theta: float = 1.0                 # exponent of the Zhao et al. sensor (MODE_ZHAO)
+    rk_order: int = 3                  # SSP Runge-Kutta order: 2, 3 or 4
     lambda_override: float = 0.0
     cfl: float = 0.1
     steps: int = 100

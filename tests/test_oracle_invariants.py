@@ -151,6 +151,87 @@ def test_ssp_rk3_third_order_in_time():
     assert 7.0 < errs[0] / errs[1] < 9.0
 
 
+def _with_order(w, k):
+    P = oracle_problem(w)
+    P.rk_order = k
+    return type(oracle_for(w))(P)
+
+
+def _amplification_coefficients(O, k):
+    """Coefficients c_j of the step's amplification polynomial R(z) = sum c_j z^j:
+    for the linear DG operator the step maps an eigenvector v (eigenvalue lam)
+    to R(dt lam) v, so R is fitted to its values at several dt."""
+    A = linear_operator(O)
+    lam, V = np.linalg.eig(A)
+    j = int(np.argmax(np.abs(lam)))
+    # R(dt lam_j) for several dt, from the step applied to the eigenvector
+    zs, Rs = [], []
+    v = V[:, j]
+    for s in np.linspace(0.2, 1.0, 2 * k + 2):
+        dt = s / abs(lam[j])
+        out = (O.step(torch.from_numpy(v.real.copy()).reshape(O.P.ncells, O.P.nloc), dt).reshape(-1).numpy()
+               + 1j * O.step(torch.from_numpy(v.imag.copy()).reshape(O.P.ncells, O.P.nloc), dt).reshape(-1).numpy())
+        zs.append(dt * lam[j])
+        Rs.append(np.vdot(v, out) / np.vdot(v, v))
+    deg = {2: 2, 3: 3, 4: 5}[k]
+    Vm = np.vander(np.array(zs), deg + 1, increasing=True)
+    return np.linalg.lstsq(Vm, np.array(Rs), rcond=None)[0]
+
+
+@pytest.mark.parametrize("k", [2, 3, 4])
+def test_ssp_step_amplification_polynomial(k):
+    """An SSP method of order k applied to a linear operator has the
+    amplification polynomial of the Taylor series of exp(z) up to z^k: 1, 1,
+    1/2, 1/6, 1/24 (order conditions).  The two-stage method is exactly
+    1 + z + z^2/2; the five-stage fourth-order method has degree five."""
+    w = inputs.adv1d(6, 1, mode=inputs.MODE_DG)
+    c = _amplification_coefficients(_with_order(w, k), k)
+    taylor = [1.0, 1.0, 0.5, 1.0 / 6.0, 1.0 / 24.0][: k + 1]
+    assert np.allclose(c[: k + 1], taylor, rtol=0, atol=1e-9)
+    if k == 2:
+        assert abs(c[2] - 0.5) < 1e-9
+    if k == 4:
+        # five stages: the z^5 term is present and smaller than the Taylor 1/120
+        assert 0.0 < c[5].real < 1.0 / 120.0
+
+
+@pytest.mark.parametrize("k,lo,hi", [(2, 3.5, 4.5), (4, 14.0, 18.0)])
+def test_ssp_orders_in_time(k, lo, hi):
+    """Against the exact propagator exp(T A) of the linear DG operator, halving
+    dt divides the error by 2^k."""
+    w = inputs.adv1d(8, 1, mode=inputs.MODE_DG)
+    O = _with_order(w, k)
+    A = linear_operator(O)
+    U0 = oracle_initial(w, O)
+    T = 0.25
+    ref = scipy.linalg.expm(T * A) @ U0.reshape(-1).numpy()
+    errs = [np.abs(O.run(U0, T / n, n).reshape(-1).numpy() - ref).max() for n in (20, 40)]
+    assert lo < errs[0] / errs[1] < hi
+
+
+def test_ssp54_shu_osher_table_is_consistent_and_ssp():
+    """The five-stage table: each row of alpha sums to one (consistency), all
+    entries are non-negative (a convex combination of forward Euler steps),
+    and the SSP coefficient min alpha/beta is the published 1.508."""
+    O = _with_order(inputs.adv1d(4, 1), 4)
+    ratios = []
+    for ra, rb in zip(O.SSP54_ALPHA, O.SSP54_BETA):
+        assert abs(sum(ra) - 1.0) < 1e-14
+        assert min(ra) >= 0.0 and min(rb) >= 0.0
+        ratios += [a / b for a, b in zip(ra, rb) if b > 0.0]
+    assert abs(min(ratios) - 1.508) < 1e-3
+
+
+def test_ssp_methods_conserve_mass():
+    w = inputs.burgers1d(40, 2, mode=inputs.MODE_WENO)
+    for k in (2, 4):
+        O = _with_order(w, k)
+        U = oracle_initial(w, O)
+        m0 = float(U[:, 0].sum())
+        U = O.run(U, w.dt(), 10)
+        assert abs(float(U[:, 0].sum()) - m0) < 1e-12
+
+
 @pytest.mark.parametrize("p,limit", [(1, 0.409), (2, 0.209), (3, 0.130), (4, 0.089)])
 def test_dg_stability_limits(p, limit):
     """The upwind DG operator with SSP-RK3 is linearly stable up to the known
