@@ -33,6 +33,11 @@ METRIC = "FP64 DOF-updates/s per RK stage + %HBM roofline; batched & adjoint vs 
 HBM_PEAK_GBS = 8000.0
 
 
+def _order(w, k):
+    w.rk_order = k
+    return w
+
+
 def workload(name):
     from paper_2309_12019_amd import inputs
     table = {
@@ -49,6 +54,9 @@ def workload(name):
         # cache); its initial data take ~25 s to evaluate on the host, so it
         # is not among the default extras
         "burgers2d_2048_p2": lambda: inputs.burgers2d(2048, 2, seed=0),
+        # the five-stage fourth-order SSP method that Sec. 5.1 pairs with p = 3
+        "rot2d_256_p3_rk4": lambda: _order(inputs.rot2d(256, 3, seed=0, steps=200), 4),
+        "burgers2d_1024_p2_rk4": lambda: _order(inputs.burgers2d(1024, 2, seed=0), 4),
     }
     return table[name]()
 
@@ -61,15 +69,25 @@ FLOPS_PER_CELL_STAGE = {(2, 2, 0, 2): 1160.0, (2, 3, 0, 2): 2376.0, (2, 2, 1, 2)
 FP64_PEAK_TFLOPS = 78.6
 
 
-def stage_bytes_per_dof():
-    """Algorithmic HBM bytes per DOF per stage: stage 1 reads U^n and writes
-    U^(1) (16 B); stages 2 and 3 also read U^n (24 B); mean 64/3 B."""
-    return (16.0 + 24.0 + 24.0) / 3.0
+def stage_bytes_per_dof(rk_order=3):
+    """Algorithmic HBM bytes per DOF per stage launch: the first stage reads
+    U^n and writes U^(1) (16 B); every later launch also reads the state it
+    combines with (24 B).  Three-stage method: mean 64/3 B; two-stage: 20 B;
+    five-stage fourth-order (six launches): 136/6 B."""
+    launches = LAUNCHES_PER_STEP[rk_order]
+    return (16.0 + 24.0 * (launches - 1)) / launches
+
+
+# RK stages and stage-kernel launches per step of each SSP method (the
+# five-stage method evaluates the operator at U^(3) twice)
+STAGES_PER_STEP = {2: 2, 3: 3, 4: 5}
+LAUNCHES_PER_STEP = {2: 2, 3: 3, 4: 6}
 
 
 def time_gpu(w, steps, warmup, fused=None):
-    """Time `steps` SSP-RK3 steps of dg_run; fused: None keeps the library's
-    automatic choice of the fused step kernel, 0 / 1 forces it off / on."""
+    """Time `steps` SSP steps (the workload's order) of dg_run; fused: None
+    keeps the library's automatic choice of the fused step kernel, 0 / 1
+    forces it off / on."""
     import torch
     from paper_2309_12019_amd import dgweno
     g = dgweno.DG.from_workload(w)
@@ -359,7 +377,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="rot2d_256_p2")
-    ap.add_argument("--extra", default="rot2d_256_p3,burgers2d_1024_p2,rot2d_256_p2_zhao,kpp2d_128_p2",
+    ap.add_argument("--extra", default="rot2d_256_p3,burgers2d_1024_p2,rot2d_256_p2_zhao,kpp2d_128_p2,"
+                    "rot2d_256_p3_rk4,burgers2d_1024_p2_rk4",
                     help="comma-separated workloads reported alongside (no cpu baseline)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
@@ -453,12 +472,15 @@ def main():
         k = min(we.steps, 100)
         re_ = time_gpu(we, k, 5)
         s_ = re_["event_ms"] / 1e3
-        launches = k if re_["fused"] else 3 * k
-        extra[name] = {"value": 3.0 * we.ndof * k / s_, "steps": k, "dofs": we.ndof, "fused_step": re_["fused"],
+        ko = we.rk_order
+        launches = k if re_["fused"] else LAUNCHES_PER_STEP[ko] * k
+        extra[name] = {"value": STAGES_PER_STEP[ko] * we.ndof * k / s_, "steps": k, "dofs": we.ndof,
+                       "rk_order": ko, "fused_step": re_["fused"],
                        "us_per_step": s_ / k * 1e6, "avg_launch_us": s_ / launches * 1e6}
         if not re_["fused"]:
-            extra[name]["hbm_frac"] = bpd * we.ndof / (s_ / launches) / 1e9 / HBM_PEAK_GBS
-            extra[name]["hbm_frac_of_measured_copy"] = bpd * we.ndof / (s_ / launches) / 1e9 / cgbs
+            bpo = stage_bytes_per_dof(ko)
+            extra[name]["hbm_frac"] = bpo * we.ndof / (s_ / launches) / 1e9 / HBM_PEAK_GBS
+            extra[name]["hbm_frac_of_measured_copy"] = bpo * we.ndof / (s_ / launches) / 1e9 / cgbs
     if extra:
         line["extra"] = extra
     if not args.no_batch:

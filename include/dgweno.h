@@ -83,18 +83,22 @@ typedef struct dg_mesh_desc {
   double lambda_override;    /* > 0: lambda_e := this value in every cell */
   void* stream;              /* hipStream_t the context queues work on (0 = default) */
   double zhao_theta;         /* exponent theta of the ZHAO sensor, > 0 (Sec. 5.6: 1) */
+  int32_t rk_order;          /* SSP Runge-Kutta order of dg_step/dg_run: 3 (eq. ssp,
+                                default), 2 or 4 (Sec. 5.1 runs order p + 1) */
 } dg_mesh_desc;
 
 typedef struct dg_ctx dg_ctx;   /* opaque, owned by the library */
 
 /* Fill a descriptor with the defaults: 1D, 64 cells on [0,1] periodic, p = 2,
  * LINADV with vel_x = 1, mode WENO, q = 1, b = 0, w_nb = 0.01, eps = 1e-6,
- * pow = 2, no lambda override, default stream, zhao_theta = 1.  Never fails. */
+ * pow = 2, no lambda override, default stream, zhao_theta = 1, rk_order = 3.
+ * Never fails. */
 void dg_default_desc(dg_mesh_desc* desc);
 
 /* Validate `desc` and create a context on the current HIP device: mesh,
  * compile-time tables for degree p, and two stage buffers of
- * n_cells * n_loc doubles (the only allocations the context makes).
+ * n_cells * n_loc doubles (three for rk_order 4; the only allocations the
+ * context makes besides the adjoint's, on first use).
  * Errors: DG_EINVAL (bad field, null pointer, non-square 2D cells),
  * DG_ENOMEM, DG_EDEVICE.  On failure *out is set to NULL. */
 int dg_init_mesh(const dg_mesh_desc* desc, dg_ctx** out);
@@ -122,14 +126,19 @@ int dg_project_ic(dg_ctx* ctx, const double* u_at_nodes, double* U);
  * overlap. */
 int dg_rhs(dg_ctx* ctx, const double* U, double* dUdt, double* gamma);
 
-/* One SSP-RK3 step of size dt (eq. ssp), in place on U (device).
- * gamma_e and lambda_e are re-evaluated in every stage (Sec. 3, the
- * stabilisation is part of the semi-discrete operator).  dt must be finite
- * and > 0. */
+/* One SSP Runge-Kutta step of size dt, in place on U (device): by default
+ * the three-stage third-order method of eq. ssp; with rk_order 2 the two-stage
+ * second-order method, with rk_order 4 the five-stage fourth-order method of
+ * Spiteri and Ruuth (Sec. 5.1 uses order p + 1 for its convergence study; the
+ * paper does not name the fourth-order scheme).  gamma_e and lambda_e are
+ * re-evaluated in every stage (Sec. 3, the stabilisation is part of the
+ * semi-discrete operator).  The five-stage method evaluates the operator six
+ * times per step (its last stage needs L(U^(3)) a second time).  dt must be
+ * finite and > 0. */
 int dg_step(dg_ctx* ctx, double* U, double dt);
 
-/* nsteps SSP-RK3 steps of size dt, in place on U.  The 3 * nsteps stage
- * launches are recorded once into a HIP graph (cached for the same U, dt and
+/* nsteps SSP steps of size dt, in place on U.  The stage launches (3, 2 or
+ * 6 per step) are recorded once into a HIP graph (cached for the same U, dt and
  * chunk length) and replayed on the context stream.  nsteps >= 0. */
 int dg_run(dg_ctx* ctx, double* U, double dt, int32_t nsteps);
 
@@ -167,7 +176,8 @@ int dg_get_tile(const dg_ctx* ctx, int32_t* tx, int32_t* ty);
  * in 1D, and in 2D for meshes of at most one 16x16 tile per compute unit,
  * where per-stage launches are latency bound), 0 off, 1 on.  Errors:
  * DG_EINVAL for another mode, DG_EUNSUPPORTED for mode 1 when the three
- * tiles exceed LDS (2D degree 4).  dg_get_fused writes 1 if steps use it.
+ * tiles exceed LDS (2D degree 4) or rk_order is not 3; with rk_order 2 or 4
+ * the automatic mode never uses it.  dg_get_fused writes 1 if steps use it.
  * Mode 0 also makes the adjoint (below) launch its two passes of every stage
  * separately instead of sharing launches between consecutive stages; the
  * result is bitwise the same either way. */
@@ -189,7 +199,8 @@ const char* dg_last_error(void);
  * used (ties: split evenly).  The first adjoint call on a context allocates
  * two state-sized buffers and two sensor-record buffers (DG_EUNSUPPORTED if
  * the adjoint kernels' tile exceeds LDS).  Every adjoint call returns
- * DG_EUNSUPPORTED for mode ZHAO and for the KPP flux.
+ * DG_EUNSUPPORTED for mode ZHAO and for the KPP flux; the step and run
+ * adjoints also for rk_order other than 3.
  * ------------------------------------------------------------------------ */
 
 /* out = J(U)^T v: the transpose Jacobian of dU/dt = L(U) (dg_rhs) applied to
@@ -241,7 +252,8 @@ int dg_validate_desc(const dg_mesh_desc* desc);
 typedef struct dg_batch dg_batch;
 
 /* Create a batch from `count` descriptors (each validated as for
- * dg_init_mesh; all work runs on descs[0].stream).  Allocates the problem
+ * dg_init_mesh; DG_EUNSUPPORTED for rk_order other than 3; all work runs on
+ * descs[0].stream).  Allocates the problem
  * table, tile lists and two stage arenas of the batch's total size. */
 int dg_batch_create(const dg_mesh_desc* descs, int32_t count, dg_batch** out);
 void dg_batch_destroy(dg_batch* batch);

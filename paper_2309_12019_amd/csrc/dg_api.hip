@@ -65,6 +65,7 @@ struct dg_ctx {
   hipStream_t capture = nullptr;  // private stream used only to record graphs
   double* U1 = nullptr;
   double* U2 = nullptr;
+  double* U3 = nullptr;           // third stage buffer (five-stage method only)
   double* red = nullptr;          // per-block partial results of reductions
   size_t red_len = 0;
   LaunchFn launch = nullptr;
@@ -166,13 +167,53 @@ int step_fused(dg_ctx* c, hipStream_t st, const double* Un, double* Uout, double
   return DG_OK;
 }
 
-// len SSP-RK3 steps on U in place.  With the fused kernel the steps
-// alternate between U and the scratch buffer U1 (the kernel cannot write the
-// array it reads), and an odd count ends with one copy back into U.
-int rk3_steps(dg_ctx* c, hipStream_t st, double* U, double dt, int len) {
+// The second-order SSP step in place: U1 = U + dt L(U); U = 1/2 U + 1/2 (U1 + dt L(U1)).
+int rk2_step(dg_ctx* c, hipStream_t st, double* U, double dt) {
+  int rc;
+  if ((rc = stage(c, st, U, U, c->U1, nullptr, 0.0, 1.0, dt, 0))) return rc;
+  return stage(c, st, c->U1, U, U, nullptr, 0.5, 0.5, dt, 0);
+}
+
+// Shu-Osher coefficients of the five-stage fourth-order SSP method (Spiteri
+// and Ruuth): U_k = sum_j alpha_kj U_j + beta_kj dt L(U_j).
+constexpr double kA10 = 1.0, kB10 = 0.391752226571890;
+constexpr double kA20 = 0.444370493651235, kA21 = 0.555629506348765, kB21 = 0.368410593050371;
+constexpr double kA30 = 0.620101851488403, kA32 = 0.379898148511597, kB32 = 0.251891774271694;
+constexpr double kA40 = 0.178079954393132, kA43 = 0.821920045606868, kB43 = 0.544974750228521;
+constexpr double kA52 = 0.517231671970585, kA53 = 0.096059710526147, kB53 = 0.063692468666290;
+constexpr double kA54 = 0.386708617503269, kB54 = 0.226007483236906;
+
+// The five-stage step in place, as stage launches of the form
+// out = a un + b (uin + dt' L(uin)) with dt' = dt beta / alpha.  The last
+// stage needs L(U3) and L(U4); L(U3) is evaluated twice (for U4 and for the
+// partial sum W = a52 U2 + a53 U3 + b53 dt L(U3)) so that every launch
+// remains one stage kernel.  Buffers: U1 <- U1, U3; U2 <- U2, W; U3 <- U4.
+int rk54_step(dg_ctx* c, hipStream_t st, double* U, double dt) {
+  int rc;
+  double *A = c->U1, *B = c->U2, *C = c->U3;
+  if ((rc = stage(c, st, U, U, A, nullptr, 0.0, kA10, dt * kB10 / kA10, 0))) return rc;  // U1
+  if ((rc = stage(c, st, A, U, B, nullptr, kA20, kA21, dt * kB21 / kA21, 0))) return rc;  // U2
+  if ((rc = stage(c, st, B, U, A, nullptr, kA30, kA32, dt * kB32 / kA32, 0))) return rc;  // U3
+  if ((rc = stage(c, st, A, U, C, nullptr, kA40, kA43, dt * kB43 / kA43, 0))) return rc;  // U4
+  if ((rc = stage(c, st, A, B, B, nullptr, kA52, kA53, dt * kB53 / kA53, 0))) return rc;  // W
+  return stage(c, st, C, B, U, nullptr, 1.0, kA54, dt * kB54 / kA54, 0);                 // U^{n+1}
+}
+
+// One SSP step of the descriptor's order on U in place (stage kernels).
+int ssp_step(dg_ctx* c, hipStream_t st, double* U, double dt) {
+  if (c->d.rk_order == 2) return rk2_step(c, st, U, dt);
+  if (c->d.rk_order == 4) return rk54_step(c, st, U, dt);
+  return rk3_step_to(c, st, U, U, dt);
+}
+
+// len SSP steps on U in place.  With the fused kernel (three-stage method
+// only) the steps alternate between U and the scratch buffer U1 (the kernel
+// cannot write the array it reads), and an odd count ends with one copy back
+// into U.
+int rk_steps(dg_ctx* c, hipStream_t st, double* U, double dt, int len) {
   if (!c->fused) {
     for (int s = 0; s < len; ++s) {
-      int rc = rk3_step_to(c, st, U, U, dt);
+      int rc = ssp_step(c, st, U, dt);
       if (rc) return rc;
     }
     return DG_OK;
@@ -192,7 +233,7 @@ int rk3_steps(dg_ctx* c, hipStream_t st, double* U, double dt, int len) {
 }
 
 int rk3_step(dg_ctx* c, hipStream_t st, double* U, double dt, double* U1 = nullptr, double* U2 = nullptr) {
-  if (!U1 && !U2) return rk3_steps(c, st, U, dt, 1);
+  if (!U1 && !U2) return rk_steps(c, st, U, dt, 1);
   return rk3_step_to(c, st, U, U, dt, U1, U2);
 }
 
@@ -218,6 +259,7 @@ int validate(const dg_mesh_desc* d) {
   if (d->mode != DG_MODE_DG && d->mode != DG_MODE_LO && d->mode != DG_MODE_WENO && d->mode != DG_MODE_ZHAO)
     return fail(DG_EINVAL, "unknown mode %d", d->mode);
   if (!(d->zhao_theta > 0.0) || !std::isfinite(d->zhao_theta)) return fail(DG_EINVAL, "zhao_theta must be > 0");
+  if (d->rk_order < 2 || d->rk_order > 4) return fail(DG_EINVAL, "rk_order must be 2, 3 or 4 (got %d)", d->rk_order);
   if (!(d->q >= 1.0) || !std::isfinite(d->q)) return fail(DG_EINVAL, "q must be >= 1");
   if (!(d->b >= 0.0 && d->b <= 1.0)) return fail(DG_EINVAL, "b must be in [0,1]");
   const int m = 2 * d->dim;
@@ -487,6 +529,7 @@ void dg_default_desc(dg_mesh_desc* d) {
   d->weno_eps = 1e-6;
   d->weno_pow = 2.0;
   d->zhao_theta = 1.0;
+  d->rk_order = 3;
 }
 
 const char* dg_last_error(void) { return g_err; }
@@ -505,6 +548,7 @@ int dg_validate_desc(const dg_mesh_desc* desc) {
 // rings and the one-workgroup-per-CU occupancy of the fused kernel cost more
 // than the launches and HBM passes it saves (0.7-0.86x from 384^2 up).
 bool fused_fits(const dg_ctx* c) {
+  if (c->d.rk_order != 3) return false;            // the fused kernel is the three-stage method
   if (c->d.dim == 2 && c->d.p == 4) return false;  // not built (its tiles exceed LDS)
   const int tx = c->d.dim == 1 ? dgk::kStepTile1D : dgk::kStepTile2D;
   const int ty = c->d.dim == 1 ? 1 : dgk::kStepTile2D;
@@ -562,7 +606,8 @@ int dg_init_mesh(const dg_mesh_desc* desc, dg_ctx** out) {
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0) c->cus = cus;
   resolve_fused(c);
   const size_t bytes = sizeof(double) * (size_t)c->ncells * c->nl;
-  if ((e = hipMalloc(&c->U1, bytes)) != hipSuccess || (e = hipMalloc(&c->U2, bytes)) != hipSuccess) {
+  if ((e = hipMalloc(&c->U1, bytes)) != hipSuccess || (e = hipMalloc(&c->U2, bytes)) != hipSuccess ||
+      (c->d.rk_order == 4 && (e = hipMalloc(&c->U3, bytes)) != hipSuccess)) {
     dg_destroy(c);
     return fail(DG_ENOMEM, "stage buffers (%zu bytes each): %s", bytes, hipGetErrorString(e));
   }
@@ -585,6 +630,7 @@ void dg_destroy(dg_ctx* c) {
   drop_graphs(c);
   if (c->U1) (void)hipFree(c->U1);
   if (c->U2) (void)hipFree(c->U2);
+  if (c->U3) (void)hipFree(c->U3);
   if (c->red) (void)hipFree(c->red);
   if (c->A1) (void)hipFree(c->A1);
   if (c->A2) (void)hipFree(c->A2);
@@ -654,7 +700,7 @@ int dg_rhs(dg_ctx* c, const double* U, double* dUdt, double* gamma) {
 int dg_step(dg_ctx* c, double* U, double dt) {
   if (!c || !U) return fail(DG_EINVAL, "NULL argument");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite and > 0");
-  return rk3_step(c, c->stream, U, dt);
+  return rk_steps(c, c->stream, U, dt, 1);
 }
 
 // The executable graph of `len` SSP-RK3 steps on U with step dt: from the
@@ -670,7 +716,7 @@ static int run_graph(dg_ctx* c, double* U, double dt, int len, hipGraphExec_t* o
   hipError_t e = hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
   int rc = DG_OK;
-  rc = rk3_steps(c, c->capture, U, dt, len);
+  rc = rk_steps(c, c->capture, U, dt, len);
   e = hipStreamEndCapture(c->capture, &g);
   if (rc) {
     if (g) (void)hipGraphDestroy(g);
@@ -780,6 +826,8 @@ int dg_set_tile(dg_ctx* c, int32_t tx, int32_t ty) {
 int dg_set_fused(dg_ctx* c, int32_t mode) {
   if (!c) return fail(DG_EINVAL, "ctx is NULL");
   if (mode < -1 || mode > 1) return fail(DG_EINVAL, "mode must be -1 (automatic), 0 (off) or 1 (on)");
+  if (mode == 1 && c->d.rk_order != 3)
+    return fail(DG_EUNSUPPORTED, "the fused step kernel implements the three-stage SSP method only");
   if (mode == 1 && !fused_fits(c))
     return fail(DG_EUNSUPPORTED, "the fused step kernel's LDS tiles exceed the device limit for this degree");
   c->fused_mode = mode;
@@ -813,6 +861,7 @@ int dg_step_adjoint(dg_ctx* c, const double* Un, double dt, const double* lam_ou
   if (!c || !Un || !lam_out || !lam_in) return fail(DG_EINVAL, "NULL argument");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite and > 0");
   if (lam_in == Un) return fail(DG_EINVAL, "lam_in must not overlap Un");
+  if (c->d.rk_order != 3) return fail(DG_EUNSUPPORTED, "the step adjoint covers the three-stage SSP method only");
   int rc = ensure_adjoint(c);
   if (rc) return rc;
   return rk3_adjoint(c, c->stream, Un, dt, lam_out, lam_in);
@@ -849,6 +898,7 @@ int dg_revolve_stats(int32_t nsteps, int32_t nsnaps, int64_t* stats) {
 int dg_adjoint_forward(dg_ctx* c, const double* U0, double* UT, double dt, int32_t nsteps, int32_t nsnaps,
                        double* ckpt, double* stages) {
   if (!c || !U0 || !UT || !ckpt) return fail(DG_EINVAL, "NULL argument");
+  if (c->d.rk_order != 3) return fail(DG_EUNSUPPORTED, "the step adjoint covers the three-stage SSP method only");
   if (c->d.mode == DG_MODE_ZHAO) return fail(DG_EUNSUPPORTED, "the adjoint does not cover the ZHAO sensor");
   if (c->d.flux == DG_FLUX_KPP) return fail(DG_EUNSUPPORTED, "the adjoint does not cover the KPP flux");
   if (nsteps < 1 || nsnaps < 0) return fail(DG_EINVAL, "need nsteps >= 1 and nsnaps >= 0");
@@ -905,6 +955,7 @@ int dg_adjoint_forward(dg_ctx* c, const double* U0, double* UT, double dt, int32
 int dg_adjoint_backward(dg_ctx* c, double dt, int32_t nsteps, int32_t nsnaps, double* ckpt, const double* stages,
                         double* lam) {
   if (!c || !ckpt || !lam) return fail(DG_EINVAL, "NULL argument");
+  if (c->d.rk_order != 3) return fail(DG_EUNSUPPORTED, "the step adjoint covers the three-stage SSP method only");
   if (nsteps < 1 || nsnaps < 0) return fail(DG_EINVAL, "need nsteps >= 1 and nsnaps >= 0");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite and > 0");
   int rc = ensure_adjoint(c);

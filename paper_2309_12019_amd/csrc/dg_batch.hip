@@ -241,6 +241,7 @@ int dg_batch_create(const dg_mesh_desc* descs, int32_t count, dg_batch** out) {
     dg_mesh_desc d = descs[i];
     int rc = dg_validate_desc(&d);
     if (rc) return rc;
+    if (d.rk_order != 3) return bfail(DG_EUNSUPPORTED, "problem %d: batched runs use the three-stage SSP method only", i);
   }
   dg_batch* b = new (std::nothrow) dg_batch();
   if (!b) return bfail(DG_ENOMEM, "host allocation failed");

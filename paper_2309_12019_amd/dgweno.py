@@ -44,6 +44,7 @@ class MeshDesc(ctypes.Structure):
         ("lambda_override", ctypes.c_double),
         ("stream", ctypes.c_void_p),
         ("zhao_theta", ctypes.c_double),
+        ("rk_order", ctypes.c_int32),
     ]
 
 
@@ -143,6 +144,7 @@ def desc_from_fields(f: dict) -> MeshDesc:
     d.weno_eps, d.weno_pow = f["eps"], f["r"]
     d.lambda_override = f["lambda_override"]
     d.zhao_theta = f.get("theta", 1.0)
+    d.rk_order = f.get("rk_order", 3)
     return d
 
 

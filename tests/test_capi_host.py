@@ -49,8 +49,8 @@ def _desc(**kw):
 
 def test_default_desc(lib):
     d = _desc()
-    assert (d.dim, d.nx, d.p, d.mode, d.q, d.b, d.w_nb, d.weno_eps, d.weno_pow) == \
-        (1, 64, 2, 2, 1.0, 0.0, 0.01, 1e-6, 2.0)
+    assert (d.dim, d.nx, d.p, d.mode, d.q, d.b, d.w_nb, d.weno_eps, d.weno_pow, d.rk_order) == \
+        (1, 64, 2, 2, 1.0, 0.0, 0.01, 1e-6, 2.0, 3)
 
 
 @pytest.mark.parametrize("bad", [
@@ -58,7 +58,7 @@ def test_default_desc(lib):
     dict(dim=2, nx=4, ny=8),                  # non-square cells on the unit square
     dict(x1=0.0), dict(flux=7), dict(mode=9), dict(q=0.5), dict(b=1.5),
     dict(w_nb=0.6), dict(weno_eps=0.0), dict(weno_pow=-1.0), dict(lambda_override=-1.0),
-    dict(vel_x=float("nan")),
+    dict(vel_x=float("nan")), dict(rk_order=1), dict(rk_order=5), dict(zhao_theta=0.0),
 ])
 def test_invalid_descriptors_rejected_on_host(lib, bad):
     d = _desc(**bad)
@@ -67,6 +67,18 @@ def test_invalid_descriptors_rejected_on_host(lib, bad):
     assert rc == -1
     assert h.value is None
     assert len(lib.dg_last_error()) > 0
+
+
+def test_batch_refuses_other_runge_kutta_orders_on_host(lib):
+    """Batched runs implement the three-stage method only; the refusal comes
+    from the host checks, before any device call."""
+    from paper_2309_12019_amd import dgweno
+    arr = (dgweno.MeshDesc * 2)(_desc(), _desc(rk_order=4))
+    h = ctypes.c_void_p(123)
+    rc = lib.dg_batch_create(arr, 2, ctypes.byref(h))
+    assert rc == dgweno.DG_EUNSUPPORTED
+    assert h.value is None
+    assert "three-stage" in lib.dg_last_error().decode()
 
 
 def test_null_arguments_rejected(lib):
