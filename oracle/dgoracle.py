@@ -49,7 +49,13 @@ project's design notes):
   an override is given (the paper fixes lambda_e by hand for one test).
 * Basis: tensor Legendre polynomials on the reference cell [-1,1]^d; the
   method is basis-independent (Sec. 2).
-* Non-periodic faces see a fixed exterior state through the same LLF flux.
+* Non-periodic faces see a fixed exterior state through the same LLF flux;
+  for the four-quadrant Burgers problem of Sec. 5.4 the exterior state is the
+  exact solution in R^2 at the face Gauss points and at the time of the
+  stage's input state (the paper sets its inflow data from the exact
+  solution; here every boundary face uses it, inflow or not).  The exact
+  solution comes from the Lax-Oleinik formula along the diagonal lines on
+  which the problem is one-dimensional.
 * Mode ZHAO: gamma_e = gamma_e^Z as printed (neither q nor the threshold b
   applies); min_l omega~_l runs over the candidates that exist; a cell with no
   face neighbour (m_e = 0) has gamma_e^Z = 0 (its only weight is its linear
@@ -67,7 +73,11 @@ is 0 on reproduced data, reaches 1 when one neighbour candidate takes all the
 weight, lies in [0, 1] and is shift- and mirror-invariant; the KPP flux's
 operator against the brute-force integrals (its LLF wave speed against a
 search along the segment), and the three schemes on the KPP problem against
-the solution ranges Sec. 5.5 prints.  The Hermite candidates
+the solution ranges Sec. 5.5 prints; the exact solution of the
+four-quadrant problem against its initial data, the integral conservation law
+on boxes, the entropy condition, the invariant set [-1, 0.8] and a hand
+derivation of its waves, and the operator with that exterior state against the
+brute-force integrals.  The Hermite candidates
 and nonlinear weights are a reading (the paper defers them to another
 reference): against the paper's WENO columns they are parity unpinned, and only
 the stated behaviour (optimal rates; WENO equal to DG with a threshold) is
@@ -81,6 +91,7 @@ import math
 from fractions import Fraction
 from typing import List, Optional, Sequence, Tuple
 
+import numpy as np
 import torch
 
 DTYPE = torch.float64
@@ -91,6 +102,61 @@ KPP = 2      # F(u) = (sin u, cos u), the non-convex flux of Sec. 5.5 (2D)
 
 MODE_DG, MODE_LO, MODE_WENO = 0, 1, 2   # labels of Sec. 5
 MODE_ZHAO = 3   # the sensor of Zhao et al. that Sec. 5.6 compares with
+
+BC_CONSTANT = 0   # non-periodic faces see the constant exterior state bc_value
+BC_RIEMANN = 1    # ... see the exact solution of Sec. 5.4's four-quadrant problem
+
+# Sec. 5.4: the initial states of the two-dimensional Burgers problem on the
+# quadrants of the unit square (discontinuities on x = 1/2 and y = 1/2)
+RIEMANN_NW, RIEMANN_NE, RIEMANN_SW, RIEMANN_SE = -0.2, -1.0, 0.5, 0.8
+
+
+def burgers2d_riemann_exact(x, y, t: float) -> np.ndarray:
+    """Entropy solution in R^2 of u_t + div(v u^2 / 2) = 0, v = (1, 1), from the
+    four-quadrant data of Sec. 5.4, at points (x, y) and time t >= 0.
+
+    With xi = x + y and c = x - y the equation reads u_t + (u^2)_xi = 0 on
+    every line c = const, so each line carries a one-dimensional problem with
+    the convex flux g(u) = u^2 and piecewise-constant data: south-west state
+    for xi < 1 - |c|, then the south-east (c > 0) or north-west (c < 0)
+    state, then the north-east state for xi > 1 + |c|.  Its entropy solution
+    is the Lax-Oleinik formula (Evans, Partial Differential Equations,
+    Sec. 3.4): u = (xi - y*) / (2t) where y* minimises
+    U0(y) + (xi - y)^2 / (4t), U0 the integral of the data along the line
+    (g* (q) = q^2 / 4 is the Legendre transform of g).  U0 is piecewise
+    linear, so the minimiser is a break point or the stationary point
+    y = xi - 2t u_k of one piece."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    x, y = np.broadcast_arrays(x, y)
+    if t <= 0.0:
+        north = y > 0.5
+        east = x > 0.5
+        return np.where(north, np.where(east, RIEMANN_NE, RIEMANN_NW),
+                        np.where(east, RIEMANN_SE, RIEMANN_SW))
+    xi, c = x + y, x - y
+    a, b = 1.0 - np.abs(c), 1.0 + np.abs(c)
+    uA = np.full_like(xi, RIEMANN_SW)
+    uB = np.where(c > 0.0, RIEMANN_SE, RIEMANN_NW)
+    uC = np.full_like(xi, RIEMANN_NE)
+
+    def U0(yy):
+        return np.where(yy < a, uA * (yy - a),
+                        np.where(yy <= b, uB * (yy - a), uB * (b - a) + uC * (yy - b)))
+
+    inf = np.full_like(xi, np.inf)
+    ys, vals = [], []
+    for yy, ok in ((a, np.ones_like(xi, dtype=bool)), (b, np.ones_like(xi, dtype=bool)),
+                   (xi - 2.0 * t * uA, xi - 2.0 * t * uA <= a),
+                   (xi - 2.0 * t * uB, (xi - 2.0 * t * uB >= a) & (xi - 2.0 * t * uB <= b)),
+                   (xi - 2.0 * t * uC, xi - 2.0 * t * uC >= b)):
+        ys.append(yy)
+        vals.append(np.where(ok, U0(yy) + (xi - yy) ** 2 / (4.0 * t), inf))
+    best = np.argmin(np.stack(vals), axis=0)
+    ystar = np.take_along_axis(np.stack(ys), best[None], axis=0)[0]
+    # a stationary minimiser y* = xi - 2t u_k gives u = u_k: return the state
+    # itself rather than (xi - y*)/(2t), which loses digits for small t
+    return np.select([best == 2, best == 3, best == 4], [uA, uB, uC], (xi - ystar) / (2.0 * t))
 
 
 # --------------------------------------------------------------------------
@@ -120,6 +186,7 @@ class Problem:
     cx: float = 0.5
     cy: float = 0.5
     bc_value: float = 0.0
+    bc_kind: int = BC_CONSTANT   # BC_RIEMANN: exterior state from the exact solution
     mode: int = MODE_WENO
     q: float = 1.0
     b: float = 0.0
@@ -163,6 +230,8 @@ class Problem:
                 raise ValueError("2D cells must be square")
         if self.flux == KPP and self.dim != 2:
             raise ValueError("the KPP flux is two-dimensional")
+        if self.bc_kind == BC_RIEMANN and not (self.dim == 2 and self.flux == BURGERS):
+            raise ValueError("the four-quadrant exterior state belongs to 2D Burgers")
 
     def qv(self) -> int:
         """Volume Gauss points per axis (exact for the polynomial part)."""
@@ -440,8 +509,18 @@ class Oracle:
         return 0.5 * (Fm + Fp) - 0.5 * s_plus * (up - um)
 
     # ------------------------------------------------------------------
-    def galerkin_residual(self, U: torch.Tensor) -> torch.Tensor:
-        """R(U) of eq. (weak2): volume term minus face-flux term."""
+    def exterior(self, xf: torch.Tensor, yf: torch.Tensor, t: float) -> torch.Tensor:
+        """The state outside a non-periodic boundary at the face points: the
+        constant bc_value, or the exact solution at time t (Sec. 5.4 sets its
+        inflow data from the exact solution; here every boundary face takes
+        its values at the face Gauss points)."""
+        if self.P.bc_kind == BC_RIEMANN:
+            return torch.from_numpy(burgers2d_riemann_exact(xf.numpy(), yf.numpy(), t))
+        return torch.full(xf.shape, self.P.bc_value, dtype=DTYPE)
+
+    def galerkin_residual(self, U: torch.Tensor, t: float = 0.0) -> torch.Tensor:
+        """R(U) of eq. (weak2) at time t (the time enters through the exterior
+        state only): volume term minus face-flux term."""
         P, d = self.P, self.P.dim
         x, y = self.phys(self.vpts)
         uq = U @ self.V.T
@@ -456,7 +535,7 @@ class Oracle:
             has = nb >= 0
             Unb = U[nb.clamp(min=0)]
             up_in = Unb @ self.FVopp[f].T
-            up = torch.where(has[:, None], up_in, torch.full_like(up_in, P.bc_value))
+            up = torch.where(has[:, None], up_in, self.exterior(xf, yf, t).expand_as(up_in))
             H = self.llf(um, up, ax, s, xf, yf)
             R = R - self.Jf * (H * self.fw[f]) @ self.FV[f]
         return R
@@ -555,10 +634,10 @@ class Oracle:
         nu = self.max_speed(U) * self.h / (2.0 * self.P.p)
         return (gam * nu)[:, None] * (U @ self.K.T)
 
-    def rhs(self, U: torch.Tensor, with_gamma: bool = False):
-        """dU/dt = M^{-1} (R(U) - s(U))."""
+    def rhs(self, U: torch.Tensor, with_gamma: bool = False, t: float = 0.0):
+        """dU/dt = M^{-1} (R(U) - s(U)) at time t."""
         gam = self.gamma(U)
-        L = (self.galerkin_residual(U) - self.dissipation(U, gam)) @ self.Minv.T
+        L = (self.galerkin_residual(U, t) - self.dissipation(U, gam)) @ self.Minv.T
         return (L, gam) if with_gamma else L
 
     # Shu-Osher coefficients of the five-stage fourth-order SSP Runge-Kutta
@@ -575,32 +654,37 @@ class Oracle:
                   (0.0, 0.0, 0.0, 0.544974750228521),
                   (0.0, 0.0, 0.0, 0.063692468666290, 0.226007483236906))
 
-    def step(self, U: torch.Tensor, dt: float) -> torch.Tensor:
-        """One SSP Runge-Kutta step of the problem's order: eq. (ssp), the
-        optimal third-order method (the default); the second-order one; or the
-        five-stage fourth-order one (Sec. 5.1 runs SSP methods of order p + 1
-        for its convergence study)."""
+    def step(self, U: torch.Tensor, dt: float, t: float = 0.0) -> torch.Tensor:
+        """One SSP Runge-Kutta step of the problem's order from time t: eq.
+        (ssp), the optimal third-order method (the default); the second-order
+        one; or the five-stage fourth-order one (Sec. 5.1 runs SSP methods of
+        order p + 1 for its convergence study).  Each stage's operator is
+        taken at the time of its input state, the same combination applied to
+        t' = 1 (third order: t, t + dt, t + dt/2)."""
         k = self.P.rk_order
         if k == 2:
-            U1 = U + dt * self.rhs(U)
-            return 0.5 * U + 0.5 * U1 + 0.5 * dt * self.rhs(U1)
+            U1 = U + dt * self.rhs(U, t=t)
+            return 0.5 * U + 0.5 * U1 + 0.5 * dt * self.rhs(U1, t=t + dt)
         if k == 4:
-            stages = [U]
-            Ls = [self.rhs(U)]
+            stages, times = [U], [t]
+            Ls = [self.rhs(U, t=t)]
             for row_a, row_b in zip(self.SSP54_ALPHA, self.SSP54_BETA):
                 Uk = sum(a * Uj for a, Uj in zip(row_a, stages) if a != 0.0)
                 Uk = Uk + sum(b * dt * Lj for b, Lj in zip(row_b, Ls) if b != 0.0)
+                tk = sum(a * tj for a, tj in zip(row_a, times)) + sum(row_b) * dt
                 stages.append(Uk)
+                times.append(tk)
                 if len(stages) <= 5:
-                    Ls.append(self.rhs(Uk))
+                    Ls.append(self.rhs(Uk, t=tk))
             return stages[-1]
-        U1 = U + dt * self.rhs(U)
-        U2 = 0.75 * U + 0.25 * U1 + 0.25 * dt * self.rhs(U1)
-        return U / 3.0 + (2.0 / 3.0) * U2 + (2.0 / 3.0) * dt * self.rhs(U2)
+        U1 = U + dt * self.rhs(U, t=t)
+        U2 = 0.75 * U + 0.25 * U1 + 0.25 * dt * self.rhs(U1, t=t + dt)
+        return U / 3.0 + (2.0 / 3.0) * U2 + (2.0 / 3.0) * dt * self.rhs(U2, t=t + 0.5 * dt)
 
-    def run(self, U: torch.Tensor, dt: float, nsteps: int) -> torch.Tensor:
-        for _ in range(nsteps):
-            U = self.step(U, dt)
+    def run(self, U: torch.Tensor, dt: float, nsteps: int, t0: float = 0.0) -> torch.Tensor:
+        """nsteps steps from time t0; step n starts at t0 + n dt."""
+        for n in range(nsteps):
+            U = self.step(U, dt, t0 + n * dt)
         return U
 
     # ------------------------------------------------------------------

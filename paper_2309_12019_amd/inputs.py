@@ -23,6 +23,7 @@ import numpy as np
 LINADV, BURGERS, KPP = 0, 1, 2
 MODE_DG, MODE_LO, MODE_WENO = 0, 1, 2
 MODE_ZHAO = 3   # the sensor of Zhao et al. compared in Sec. 5.6
+BC_CONSTANT, BC_RIEMANN = 0, 1   # exterior state: bc_value, or Sec. 5.4's exact solution
 
 
 @dataclasses.dataclass
@@ -45,6 +46,7 @@ class Workload:
     cx: float = 0.5
     cy: float = 0.5
     bc_value: float = 0.0
+    bc_kind: int = BC_CONSTANT
     mode: int = MODE_WENO
     q: float = 1.0
     b: float = 0.0
@@ -303,6 +305,27 @@ def batch_mix(seed: int = 0, count: int = 512, steps: int = 100) -> List[Workloa
         w.name = f"b{i}_{w.name}"
         out.append(w)
     return out
+
+
+def riemann_quadrants(x, y):
+    """The four-quadrant data of Sec. 5.4 on the unit square: -0.2 (north-west),
+    -1 (north-east), 0.5 (south-west), 0.8 (south-east)."""
+    o = _Ops(x)
+    north, east = y > 0.5, x > 0.5
+    return o.where(north, o.where(east, -1.0, -0.2), o.where(east, 0.8, 0.5))
+
+
+def burgers2d_riemann(n: int = 128, p: int = 2, mode: int = MODE_WENO, steps: Optional[int] = None,
+                      cfl: float = 0.1, t_end: float = 0.5) -> Workload:
+    """The 2D Burgers problem of Sec. 5.4: u_t + div(v u^2/2) = 0, v = (1, 1),
+    on the unit square with n x n cells, four-quadrant data, the exterior
+    state on every boundary face from the exact solution in R^2, run to
+    t_end (the paper: 128^2, P2, t = 0.5)."""
+    w = Workload(name=f"burgers2d_riemann_{n}_p{p}", dim=2, nx=n, ny=n, periodic_x=False,
+                 periodic_y=False, p=p, flux=BURGERS, vx=1.0, vy=1.0, bc_kind=BC_RIEMANN,
+                 mode=mode, cfl=cfl, ic=riemann_quadrants, umax=1.0)
+    w.steps = steps if steps is not None else int(math.ceil(t_end / w.dt()))
+    return w
 
 
 def kpp2d(n: int = 128, p: int = 2, mode: int = MODE_WENO, steps: Optional[int] = None,

@@ -31,9 +31,12 @@ def _gauss(n):
 
 
 class Brute:
-    def __init__(self, w):
-        """w: an inputs.Workload-like object (fields only)."""
+    def __init__(self, w, exterior=None):
+        """w: an inputs.Workload-like object (fields only); exterior(x, y):
+        the state outside non-periodic faces (default: the constant
+        bc_value)."""
         self.w = w
+        self.exterior = exterior
         self.d = w.dim
         self.p = w.p
         self.n1 = w.p + 1
@@ -168,7 +171,8 @@ class Brute:
                 um = self.value(U[e], c, xf, yf)
                 nb = self.neighbour(e, ax, side)
                 if nb is None:
-                    up = np.full_like(um, w.bc_value)
+                    up = (np.full_like(um, w.bc_value) if self.exterior is None
+                          else np.asarray(self.exterior(xf, yf), dtype=np.float64))
                 else:
                     up = self.value(U[nb[0]], nb[1], xf, yf)
                 Fm = self.F(um, xf, yf)[ax] * side
