@@ -57,6 +57,9 @@ def workload(name):
         # the five-stage fourth-order SSP method that Sec. 5.1 pairs with p = 3
         "rot2d_256_p3_rk4": lambda: _order(inputs.rot2d(256, 3, seed=0, steps=200), 4),
         "burgers2d_1024_p2_rk4": lambda: _order(inputs.burgers2d(1024, 2, seed=0), 4),
+        # the four-quadrant problem of Sec. 5.4 at the paper's size (exact
+        # exterior state at every stage time; steps launched without a graph)
+        "burgers2d_riemann_128_p2": lambda: inputs.burgers2d_riemann(128, 2),
     }
     return table[name]()
 
@@ -378,7 +381,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="rot2d_256_p2")
     ap.add_argument("--extra", default="rot2d_256_p3,burgers2d_1024_p2,rot2d_256_p2_zhao,kpp2d_128_p2,"
-                    "rot2d_256_p3_rk4,burgers2d_1024_p2_rk4",
+                    "rot2d_256_p3_rk4,burgers2d_1024_p2_rk4,burgers2d_riemann_128_p2",
                     help="comma-separated workloads reported alongside (no cpu baseline)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")

@@ -65,6 +65,15 @@ enum dg_flux { DG_FLUX_LINADV = 0, DG_FLUX_BURGERS = 1, DG_FLUX_KPP = 2 };
  * neighbours); q and b do not apply.  The adjoint covers DG, LO and WENO. */
 enum dg_mode { DG_MODE_DG = 0, DG_MODE_LO = 1, DG_MODE_WENO = 2, DG_MODE_ZHAO = 3 };
 
+/* State outside non-periodic boundary faces.  CONSTANT: bc_value.  RIEMANN
+ * (2D Burgers, both axes non-periodic): the exact solution in R^2 of the
+ * four-quadrant problem of Sec. 5.4 (u_t + div((1,1) u^2/2) = 0 with -0.2 | -1
+ * above 0.5 | 0.8, split at x = y = 1/2), evaluated at the boundary face's
+ * Gauss points at the time of each stage's input state (the paper takes its
+ * inflow data from that solution; here every boundary face does).  The time
+ * comes from the context's clock (dg_set_time). */
+enum dg_bc { DG_BC_CONSTANT = 0, DG_BC_RIEMANN = 1 };
+
 typedef struct dg_mesh_desc {
   int32_t dim;               /* 1 or 2 */
   int32_t nx, ny;            /* cells along x and y (ny ignored for dim 1) */
@@ -85,14 +94,15 @@ typedef struct dg_mesh_desc {
   double zhao_theta;         /* exponent theta of the ZHAO sensor, > 0 (Sec. 5.6: 1) */
   int32_t rk_order;          /* SSP Runge-Kutta order of dg_step/dg_run: 3 (eq. ssp,
                                 default), 2 or 4 (Sec. 5.1 runs order p + 1) */
+  int32_t bc_kind;           /* enum dg_bc */
 } dg_mesh_desc;
 
 typedef struct dg_ctx dg_ctx;   /* opaque, owned by the library */
 
 /* Fill a descriptor with the defaults: 1D, 64 cells on [0,1] periodic, p = 2,
  * LINADV with vel_x = 1, mode WENO, q = 1, b = 0, w_nb = 0.01, eps = 1e-6,
- * pow = 2, no lambda override, default stream, zhao_theta = 1, rk_order = 3.
- * Never fails. */
+ * pow = 2, no lambda override, default stream, zhao_theta = 1, rk_order = 3,
+ * bc_kind CONSTANT.  Never fails. */
 void dg_default_desc(dg_mesh_desc* desc);
 
 /* Validate `desc` and create a context on the current HIP device: mesh,
@@ -120,6 +130,13 @@ int dg_proj_nodes(const dg_ctx* ctx, double* xy_host);
  * from dg_proj_nodes; U (device) receives the coefficients. */
 int dg_project_ic(dg_ctx* ctx, const double* u_at_nodes, double* U);
 
+/* The context's clock: the time of the state that dg_step and dg_run
+ * advance.  It starts at 0; dg_step adds dt, dg_run nsteps * dt (step k of a
+ * run starts at t + k dt), and dg_rhs evaluates at it.  It matters only for
+ * bc_kind RIEMANN.  dg_set_time: t finite. */
+int dg_set_time(dg_ctx* ctx, double t);
+int dg_get_time(const dg_ctx* ctx, double* t);
+
 /* Semi-discrete operator (eq. weak2 plus eq. astab): dUdt = M^{-1}(R(U) - s(U)).
  * U, dUdt: device [n_cells * n_loc]; gamma: device [n_cells] receiving
  * gamma_e of every cell (0 for DG, 1 for LO), or NULL.  U and dUdt must not
@@ -137,8 +154,9 @@ int dg_rhs(dg_ctx* ctx, const double* U, double* dUdt, double* gamma);
  * finite and > 0. */
 int dg_step(dg_ctx* ctx, double* U, double dt);
 
-/* nsteps SSP steps of size dt, in place on U.  The stage launches (3, 2 or
- * 6 per step) are recorded once into a HIP graph (cached for the same U, dt and
+/* nsteps SSP steps of size dt, in place on U.  With bc_kind RIEMANN the
+ * stage launches go to the stream directly (their exterior state changes with
+ * time); otherwise the stage launches (3, 2 or 6 per step) are recorded once into a HIP graph (cached for the same U, dt and
  * chunk length) and replayed on the context stream.  nsteps >= 0. */
 int dg_run(dg_ctx* ctx, double* U, double dt, int32_t nsteps);
 
@@ -176,8 +194,8 @@ int dg_get_tile(const dg_ctx* ctx, int32_t* tx, int32_t* ty);
  * in 1D, and in 2D for meshes of at most one 16x16 tile per compute unit,
  * where per-stage launches are latency bound), 0 off, 1 on.  Errors:
  * DG_EINVAL for another mode, DG_EUNSUPPORTED for mode 1 when the three
- * tiles exceed LDS (2D degree 4) or rk_order is not 3; with rk_order 2 or 4
- * the automatic mode never uses it.  dg_get_fused writes 1 if steps use it.
+ * tiles exceed LDS (2D degree 4), rk_order is not 3 or bc_kind is not
+ * CONSTANT; in those cases the automatic mode never uses it.  dg_get_fused writes 1 if steps use it.
  * Mode 0 also makes the adjoint (below) launch its two passes of every stage
  * separately instead of sharing launches between consecutive stages; the
  * result is bitwise the same either way. */
@@ -199,8 +217,8 @@ const char* dg_last_error(void);
  * used (ties: split evenly).  The first adjoint call on a context allocates
  * two state-sized buffers and two sensor-record buffers (DG_EUNSUPPORTED if
  * the adjoint kernels' tile exceeds LDS).  Every adjoint call returns
- * DG_EUNSUPPORTED for mode ZHAO and for the KPP flux; the step and run
- * adjoints also for rk_order other than 3.
+ * DG_EUNSUPPORTED for mode ZHAO, for the KPP flux and for bc_kind RIEMANN;
+ * the step and run adjoints also for rk_order other than 3.
  * ------------------------------------------------------------------------ */
 
 /* out = J(U)^T v: the transpose Jacobian of dU/dt = L(U) (dg_rhs) applied to
@@ -252,7 +270,8 @@ int dg_validate_desc(const dg_mesh_desc* desc);
 typedef struct dg_batch dg_batch;
 
 /* Create a batch from `count` descriptors (each validated as for
- * dg_init_mesh; DG_EUNSUPPORTED for rk_order other than 3; all work runs on
+ * dg_init_mesh; DG_EUNSUPPORTED for rk_order other than 3 or bc_kind
+ * RIEMANN; all work runs on
  * descs[0].stream).  Allocates the problem
  * table, tile lists and two stage arenas of the batch's total size. */
 int dg_batch_create(const dg_mesh_desc* descs, int32_t count, dg_batch** out);

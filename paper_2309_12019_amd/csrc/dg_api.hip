@@ -66,6 +66,7 @@ struct dg_ctx {
   double* U1 = nullptr;
   double* U2 = nullptr;
   double* U3 = nullptr;           // third stage buffer (five-stage method only)
+  double t = 0.0;                 // the context's clock: time of the state dg_step/dg_run advance
   double* red = nullptr;          // per-block partial results of reductions
   size_t red_len = 0;
   LaunchFn launch = nullptr;
@@ -104,6 +105,7 @@ StageArgs base_args(const dg_ctx* c) {
   A.wpow = d.weno_pow;
   A.lam_over = d.lambda_override;
   A.theta = d.zhao_theta;
+  A.bc_kind = d.bc_kind;
   A.tx = c->tx;
   A.ty = d.dim == 2 ? c->ty : 1;
   return A;
@@ -113,9 +115,10 @@ size_t stage_lds_bytes(int dim, int nl, int tx, int ty) {
   return sizeof(double) * (size_t)dgk::tile_lds_doubles(dim, nl, tx, dim == 2 ? ty : 1);
 }
 
-// one stage: out = a*un + b*(uin + dt*L(uin)), or out = L(uin) when rhs_only
+// one stage: out = a*un + b*(uin + dt*L(uin)), or out = L(uin) when rhs_only;
+// t is the time of uin (it enters through the BC_RIEMANN exterior state only)
 int stage(dg_ctx* c, hipStream_t st, const double* uin, const double* un, double* out, double* gamma,
-          double a, double b, double dt, int rhs_only) {
+          double a, double b, double dt, int rhs_only, double t = 0.0) {
   LaunchReq r{};
   r.kind = dgk::LAUNCH_STAGE;
   r.flux = c->d.flux;
@@ -129,6 +132,7 @@ int stage(dg_ctx* c, hipStream_t st, const double* uin, const double* un, double
   r.args.b = b;
   r.args.dt = dt;
   r.args.rhs_only = rhs_only;
+  r.args.t = t;
   r.stream = st;
   hipError_t e = c->launch(&r);
   if (e != hipSuccess) return hip_fail(e, "stage kernel launch");
@@ -139,15 +143,16 @@ int stage(dg_ctx* c, hipStream_t st, const double* uin, const double* un, double
 // The stage states go to U1, U2 (default: the context's buffers).
 // One SSP-RK3 step from Un into Uout (Uout may be Un: the last stage reads
 // U^n and writes the same element from one thread); the stage states go to
-// U1, U2 (the handle's scratch unless given).
+// U1, U2 (the handle's scratch unless given).  The step starts at time t; the
+// stages' operators are taken at t, t + dt and t + dt/2.
 int rk3_step_to(dg_ctx* c, hipStream_t st, const double* Un, double* Uout, double dt, double* U1 = nullptr,
-                double* U2 = nullptr) {
+                double* U2 = nullptr, double t = 0.0) {
   int rc;
   U1 = U1 ? U1 : c->U1;
   U2 = U2 ? U2 : c->U2;
-  if ((rc = stage(c, st, Un, Un, U1, nullptr, 0.0, 1.0, dt, 0))) return rc;
-  if ((rc = stage(c, st, U1, Un, U2, nullptr, 0.75, 0.25, dt, 0))) return rc;
-  return stage(c, st, U2, Un, Uout, nullptr, 1.0 / 3.0, 2.0 / 3.0, dt, 0);
+  if ((rc = stage(c, st, Un, Un, U1, nullptr, 0.0, 1.0, dt, 0, t))) return rc;
+  if ((rc = stage(c, st, U1, Un, U2, nullptr, 0.75, 0.25, dt, 0, t + dt))) return rc;
+  return stage(c, st, U2, Un, Uout, nullptr, 1.0 / 3.0, 2.0 / 3.0, dt, 0, t + 0.5 * dt);
 }
 
 // One fused SSP-RK3 step (one launch) from Un into Uout != Un.
@@ -167,11 +172,12 @@ int step_fused(dg_ctx* c, hipStream_t st, const double* Un, double* Uout, double
   return DG_OK;
 }
 
-// The second-order SSP step in place: U1 = U + dt L(U); U = 1/2 U + 1/2 (U1 + dt L(U1)).
-int rk2_step(dg_ctx* c, hipStream_t st, double* U, double dt) {
+// The second-order SSP step in place from time t: U1 = U + dt L(U, t);
+// U = 1/2 U + 1/2 (U1 + dt L(U1, t + dt)).
+int rk2_step(dg_ctx* c, hipStream_t st, double* U, double dt, double t) {
   int rc;
-  if ((rc = stage(c, st, U, U, c->U1, nullptr, 0.0, 1.0, dt, 0))) return rc;
-  return stage(c, st, c->U1, U, U, nullptr, 0.5, 0.5, dt, 0);
+  if ((rc = stage(c, st, U, U, c->U1, nullptr, 0.0, 1.0, dt, 0, t))) return rc;
+  return stage(c, st, c->U1, U, U, nullptr, 0.5, 0.5, dt, 0, t + dt);
 }
 
 // Shu-Osher coefficients of the five-stage fourth-order SSP method (Spiteri
@@ -188,32 +194,37 @@ constexpr double kA54 = 0.386708617503269, kB54 = 0.226007483236906;
 // stage needs L(U3) and L(U4); L(U3) is evaluated twice (for U4 and for the
 // partial sum W = a52 U2 + a53 U3 + b53 dt L(U3)) so that every launch
 // remains one stage kernel.  Buffers: U1 <- U1, U3; U2 <- U2, W; U3 <- U4.
-int rk54_step(dg_ctx* c, hipStream_t st, double* U, double dt) {
+// The stage states' times follow from the same combination applied to t' = 1.
+int rk54_step(dg_ctx* c, hipStream_t st, double* U, double dt, double t0) {
   int rc;
   double *A = c->U1, *B = c->U2, *C = c->U3;
-  if ((rc = stage(c, st, U, U, A, nullptr, 0.0, kA10, dt * kB10 / kA10, 0))) return rc;  // U1
-  if ((rc = stage(c, st, A, U, B, nullptr, kA20, kA21, dt * kB21 / kA21, 0))) return rc;  // U2
-  if ((rc = stage(c, st, B, U, A, nullptr, kA30, kA32, dt * kB32 / kA32, 0))) return rc;  // U3
-  if ((rc = stage(c, st, A, U, C, nullptr, kA40, kA43, dt * kB43 / kA43, 0))) return rc;  // U4
-  if ((rc = stage(c, st, A, B, B, nullptr, kA52, kA53, dt * kB53 / kA53, 0))) return rc;  // W
-  return stage(c, st, C, B, U, nullptr, 1.0, kA54, dt * kB54 / kA54, 0);                 // U^{n+1}
+  const double t1 = kA10 * t0 + kB10 * dt;
+  const double t2 = (kA20 * t0 + kA21 * t1) + kB21 * dt;
+  const double t3 = (kA30 * t0 + kA32 * t2) + kB32 * dt;
+  const double t4 = (kA40 * t0 + kA43 * t3) + kB43 * dt;
+  if ((rc = stage(c, st, U, U, A, nullptr, 0.0, kA10, dt * kB10 / kA10, 0, t0))) return rc;  // U1
+  if ((rc = stage(c, st, A, U, B, nullptr, kA20, kA21, dt * kB21 / kA21, 0, t1))) return rc;  // U2
+  if ((rc = stage(c, st, B, U, A, nullptr, kA30, kA32, dt * kB32 / kA32, 0, t2))) return rc;  // U3
+  if ((rc = stage(c, st, A, U, C, nullptr, kA40, kA43, dt * kB43 / kA43, 0, t3))) return rc;  // U4
+  if ((rc = stage(c, st, A, B, B, nullptr, kA52, kA53, dt * kB53 / kA53, 0, t3))) return rc;  // W
+  return stage(c, st, C, B, U, nullptr, 1.0, kA54, dt * kB54 / kA54, 0, t4);                 // U^{n+1}
 }
 
-// One SSP step of the descriptor's order on U in place (stage kernels).
-int ssp_step(dg_ctx* c, hipStream_t st, double* U, double dt) {
-  if (c->d.rk_order == 2) return rk2_step(c, st, U, dt);
-  if (c->d.rk_order == 4) return rk54_step(c, st, U, dt);
-  return rk3_step_to(c, st, U, U, dt);
+// One SSP step of the descriptor's order on U in place from time t (stage kernels).
+int ssp_step(dg_ctx* c, hipStream_t st, double* U, double dt, double t) {
+  if (c->d.rk_order == 2) return rk2_step(c, st, U, dt, t);
+  if (c->d.rk_order == 4) return rk54_step(c, st, U, dt, t);
+  return rk3_step_to(c, st, U, U, dt, nullptr, nullptr, t);
 }
 
 // len SSP steps on U in place.  With the fused kernel (three-stage method
 // only) the steps alternate between U and the scratch buffer U1 (the kernel
 // cannot write the array it reads), and an odd count ends with one copy back
-// into U.
-int rk_steps(dg_ctx* c, hipStream_t st, double* U, double dt, int len) {
+// into U.  Step s starts at time t0 + s dt.
+int rk_steps(dg_ctx* c, hipStream_t st, double* U, double dt, int len, double t0 = 0.0) {
   if (!c->fused) {
     for (int s = 0; s < len; ++s) {
-      int rc = ssp_step(c, st, U, dt);
+      int rc = ssp_step(c, st, U, dt, t0 + s * dt);
       if (rc) return rc;
     }
     return DG_OK;
@@ -260,6 +271,11 @@ int validate(const dg_mesh_desc* d) {
     return fail(DG_EINVAL, "unknown mode %d", d->mode);
   if (!(d->zhao_theta > 0.0) || !std::isfinite(d->zhao_theta)) return fail(DG_EINVAL, "zhao_theta must be > 0");
   if (d->rk_order < 2 || d->rk_order > 4) return fail(DG_EINVAL, "rk_order must be 2, 3 or 4 (got %d)", d->rk_order);
+  if (d->bc_kind != DG_BC_CONSTANT && d->bc_kind != DG_BC_RIEMANN)
+    return fail(DG_EINVAL, "unknown bc_kind %d", d->bc_kind);
+  if (d->bc_kind == DG_BC_RIEMANN &&
+      (d->dim != 2 || d->flux != DG_FLUX_BURGERS || d->periodic_x || d->periodic_y))
+    return fail(DG_EINVAL, "bc_kind RIEMANN needs 2D Burgers with non-periodic boundaries");
   if (!(d->q >= 1.0) || !std::isfinite(d->q)) return fail(DG_EINVAL, "q must be >= 1");
   if (!(d->b >= 0.0 && d->b <= 1.0)) return fail(DG_EINVAL, "b must be in [0,1]");
   const int m = 2 * d->dim;
@@ -295,6 +311,8 @@ int check_tile(const dg_ctx* c, int tx, int ty) {
 int zrec_size(int dim, int nl) { return dgk::zrec_doubles(dim, nl); }
 
 int ensure_adjoint(dg_ctx* c) {
+  if (c->d.bc_kind != DG_BC_CONSTANT)
+    return fail(DG_EUNSUPPORTED, "the adjoint does not cover the exact-solution exterior state");
   if (c->d.mode == DG_MODE_ZHAO) return fail(DG_EUNSUPPORTED, "the adjoint does not cover the ZHAO sensor");
   if (c->d.flux == DG_FLUX_KPP) return fail(DG_EUNSUPPORTED, "the adjoint does not cover the KPP flux");
   if (c->A1) return DG_OK;
@@ -530,6 +548,7 @@ void dg_default_desc(dg_mesh_desc* d) {
   d->weno_pow = 2.0;
   d->zhao_theta = 1.0;
   d->rk_order = 3;
+  d->bc_kind = DG_BC_CONSTANT;
 }
 
 const char* dg_last_error(void) { return g_err; }
@@ -549,6 +568,7 @@ int dg_validate_desc(const dg_mesh_desc* desc) {
 // than the launches and HBM passes it saves (0.7-0.86x from 384^2 up).
 bool fused_fits(const dg_ctx* c) {
   if (c->d.rk_order != 3) return false;            // the fused kernel is the three-stage method
+  if (c->d.bc_kind != DG_BC_CONSTANT) return false;  // its rings take the constant exterior state
   if (c->d.dim == 2 && c->d.p == 4) return false;  // not built (its tiles exceed LDS)
   const int tx = c->d.dim == 1 ? dgk::kStepTile1D : dgk::kStepTile2D;
   const int ty = c->d.dim == 1 ? 1 : dgk::kStepTile2D;
@@ -694,13 +714,28 @@ int dg_project_ic(dg_ctx* c, const double* u_at_nodes, double* U) {
 int dg_rhs(dg_ctx* c, const double* U, double* dUdt, double* gamma) {
   if (!c || !U || !dUdt) return fail(DG_EINVAL, "NULL argument");
   if (U == dUdt) return fail(DG_EINVAL, "U and dUdt must not overlap");
-  return stage(c, c->stream, U, nullptr, dUdt, gamma, 0.0, 1.0, 0.0, 1);
+  return stage(c, c->stream, U, nullptr, dUdt, gamma, 0.0, 1.0, 0.0, 1, c->t);
 }
 
 int dg_step(dg_ctx* c, double* U, double dt) {
   if (!c || !U) return fail(DG_EINVAL, "NULL argument");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite and > 0");
-  return rk_steps(c, c->stream, U, dt, 1);
+  const int rc = rk_steps(c, c->stream, U, dt, 1, c->t);
+  if (rc == DG_OK) c->t += dt;
+  return rc;
+}
+
+int dg_set_time(dg_ctx* c, double t) {
+  if (!c) return fail(DG_EINVAL, "ctx is NULL");
+  if (!std::isfinite(t)) return fail(DG_EINVAL, "t must be finite");
+  c->t = t;
+  return DG_OK;
+}
+
+int dg_get_time(const dg_ctx* c, double* t) {
+  if (!c || !t) return fail(DG_EINVAL, "NULL argument");
+  *t = c->t;
+  return DG_OK;
 }
 
 // The executable graph of `len` SSP-RK3 steps on U with step dt: from the
@@ -737,6 +772,13 @@ int dg_run(dg_ctx* c, double* U, double dt, int32_t nsteps) {
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite and > 0");
   if (nsteps < 0) return fail(DG_EINVAL, "nsteps must be >= 0");
   if (nsteps == 0) return DG_OK;
+  if (c->d.bc_kind != DG_BC_CONSTANT) {
+    // the exterior state depends on the stage times, which a replayed graph
+    // would repeat: launch the steps directly
+    const int rc = rk_steps(c, c->stream, U, dt, nsteps, c->t);
+    if (rc == DG_OK) c->t += nsteps * dt;
+    return rc;
+  }
   // whole chunks of up to 64 steps replay one captured graph; a remainder
   // replays a second graph of its own length (both cached per (U, dt, length))
   const int chunk = nsteps < 64 ? nsteps : 64;
@@ -754,6 +796,7 @@ int dg_run(dg_ctx* c, double* U, double dt, int32_t nsteps) {
     hipError_t e = hipGraphLaunch(tail, c->stream);
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
   }
+  c->t += nsteps * dt;
   return DG_OK;
 }
 
@@ -828,6 +871,8 @@ int dg_set_fused(dg_ctx* c, int32_t mode) {
   if (mode < -1 || mode > 1) return fail(DG_EINVAL, "mode must be -1 (automatic), 0 (off) or 1 (on)");
   if (mode == 1 && c->d.rk_order != 3)
     return fail(DG_EUNSUPPORTED, "the fused step kernel implements the three-stage SSP method only");
+  if (mode == 1 && c->d.bc_kind != DG_BC_CONSTANT)
+    return fail(DG_EUNSUPPORTED, "the fused step kernel takes the constant exterior state only");
   if (mode == 1 && !fused_fits(c))
     return fail(DG_EUNSUPPORTED, "the fused step kernel's LDS tiles exceed the device limit for this degree");
   c->fused_mode = mode;
@@ -899,6 +944,8 @@ int dg_adjoint_forward(dg_ctx* c, const double* U0, double* UT, double dt, int32
                        double* ckpt, double* stages) {
   if (!c || !U0 || !UT || !ckpt) return fail(DG_EINVAL, "NULL argument");
   if (c->d.rk_order != 3) return fail(DG_EUNSUPPORTED, "the step adjoint covers the three-stage SSP method only");
+  if (c->d.bc_kind != DG_BC_CONSTANT)
+    return fail(DG_EUNSUPPORTED, "the adjoint does not cover the exact-solution exterior state");
   if (c->d.mode == DG_MODE_ZHAO) return fail(DG_EUNSUPPORTED, "the adjoint does not cover the ZHAO sensor");
   if (c->d.flux == DG_FLUX_KPP) return fail(DG_EUNSUPPORTED, "the adjoint does not cover the KPP flux");
   if (nsteps < 1 || nsnaps < 0) return fail(DG_EINVAL, "need nsteps >= 1 and nsnaps >= 0");

@@ -29,6 +29,9 @@ namespace dgk {
 
 enum { FLUX_LINADV = 0, FLUX_BURGERS = 1, FLUX_KPP = 2 };  // KPP: 2D only
 enum { MODE_DG = 0, MODE_LO = 1, MODE_WENO = 2, MODE_ZHAO = 3 };
+// exterior state at non-periodic faces: the constant bc, or (2D Burgers only)
+// the exact solution of the four-quadrant problem of Sec. 5.4 at time t
+enum { BC_CONSTANT = 0, BC_RIEMANN = 1 };
 
 struct StageArgs {
   const double* uin;  // operator input U^(k-1), [cells][NL]
@@ -42,7 +45,9 @@ struct StageArgs {
   double h, x0, y0;
   double vx, vy, omega, cx, cy;  // LINADV velocity; BURGERS direction (vx, vy)
   double anorm;                  // ||(vx, vy)||_2 (BURGERS wave speed factor)
-  double bc;                     // exterior state at non-periodic faces
+  double bc;                     // exterior state at non-periodic faces (BC_CONSTANT)
+  double t;                      // time of uin (the exterior state of BC_RIEMANN)
+  int bc_kind;                   // BC_CONSTANT or BC_RIEMANN
   double q, bthr, wnb, eps, wpow, lam_over;
   double theta;                  // exponent of the Zhao et al. sensor (MODE_ZHAO)
   int tx, ty;                    // tile (one of the compiled shapes; ty = 1 in 1D)
@@ -116,6 +121,41 @@ __device__ inline double sqrt_pos(double x) {
 // b[j*S + off(f)] with off = -1, +1, -W, +W (faces -x, +x, -y, +y).
 // Non-periodic boundary slots hold the constant exterior state, so the
 // face traces need no special case.
+// Exact solution in R^2 of the four-quadrant Burgers problem of Sec. 5.4,
+// u_t + div((1, 1) u^2 / 2) = 0 with -0.2 | -1 above 0.5 | 0.8 (split at
+// x = y = 1/2), at (x, y) and time t > 0.  Along each line c = x - y the
+// problem is one-dimensional (flux u^2 in x + y); its waves, located by
+// z = 2x - 1 for c >= 0 and by w = 2y - 1 for c < 0:
+//   c >= 0: a fan 0.5 -> 0.8 over t <= z <= 1.6t and a shock 0.8 | -1 at
+//     z = 2c - 0.2t; the shock reaches the fan's head at t = 10c/9, crosses
+//     the fan along z = 3.6 sqrt(10c/9) sqrt(t) - 2t, leaves it at t = 1.6c
+//     and goes on as 0.5 | -1 at z = 2.4c - 0.5t;
+//   c < 0 (d = -c): shocks 0.5 | -0.2 at w = 0.3t and -0.2 | -1 at
+//     w = 2d - 1.2t, which merge at t = 4d/3 into 0.5 | -1 at
+//     w = 16d/15 - 0.5t.
+__device__ inline double riemann_exact(double x, double y, double t) {
+  const double c = x - y;
+  if (c >= 0.0) {
+    const double z = 2.0 * x - 1.0, t1 = c * (10.0 / 9.0), t2 = 1.6 * c;
+    if (t <= t1) {
+      if (z <= t) return 0.5;
+      if (z < 1.6 * t) return z / (2.0 * t);
+      return z < 2.0 * c - 0.2 * t ? 0.8 : -1.0;
+    }
+    if (t <= t2) {
+      if (z <= t) return 0.5;
+      return z < 3.6 * sqrt(t1) * sqrt(t) - 2.0 * t ? z / (2.0 * t) : -1.0;
+    }
+    return z < 2.4 * c - 0.5 * t ? 0.5 : -1.0;
+  }
+  const double d = -c, w = 2.0 * y - 1.0;
+  if (t <= d * (4.0 / 3.0)) {
+    if (w < 0.3 * t) return 0.5;
+    return w < 2.0 * d - 1.2 * t ? -0.2 : -1.0;
+  }
+  return w < d * (16.0 / 15.0) - 0.5 * t ? 0.5 : -1.0;
+}
+
 template <int DIM, int P, int FLUX, int MODE, int S, int W>
 struct Cell {
   using TB = Tables<DIM, P, FLUX>;
@@ -125,6 +165,31 @@ struct Cell {
   static constexpr int NF = 2 * DIM;
 
   __device__ static constexpr int off(int f) { return f == 0 ? -1 : f == 1 ? 1 : f == 2 ? -W : W; }
+
+  // BC_RIEMANN exterior slots: a slot outside one boundary holds, in planes
+  // 0..Q-1, the exact solution at the Q Gauss points of the one face that
+  // reads it (node order of the face loop) at time A.t; a slot outside two
+  // boundaries (used by no face) holds zeros; slots inside are left alone.
+  __device__ static inline void riemann_slot(const StageArgs& A, int gx, int gy, double (&v)[NL]) {
+    const bool ox = (unsigned)gx >= (unsigned)A.nx, oy = (unsigned)gy >= (unsigned)A.ny;
+    if (!ox && !oy) return;
+#pragma unroll
+    for (int j = 0; j < NL; ++j) v[j] = 0.0;
+    if (ox && oy) return;
+    const double hh = 0.5 * A.h;
+#pragma unroll
+    for (int r = 0; r < Q; ++r) {
+      double x, y;
+      if (ox) {
+        x = gx < 0 ? A.x0 : A.x0 + A.nx * A.h;
+        y = fma(hh, TB::nd.x[r], A.y0 + (gy + 0.5) * A.h);
+      } else {
+        y = gy < 0 ? A.y0 : A.y0 + A.ny * A.h;
+        x = fma(hh, TB::nd.x[r], A.x0 + (gx + 0.5) * A.h);
+      }
+      v[r] = riemann_exact(x, y, A.t);
+    }
+  }
 
   // c^T B c with the sensor's quadratic form (zero entries skipped at compile time)
   __device__ static inline double qform(const double (&v)[NL]) {
@@ -339,18 +404,20 @@ struct Cell {
   // same values as its LDS slot b), the neighbours are read from LDS.  SB as
   // for sensor(); the arithmetic is the same either way.  The three parts
   // (gamma_of, residual, finish) may also run on different threads.
-  template <bool SB = true>
+  // XBC: compile the BC_RIEMANN exterior state in (the per-stage kernel only).
+  template <bool SB = true, bool XBC = false>
   __device__ static inline void rhs(const StageArgs& A, const double* b, const double (&c)[NL], int ix, int iy,
                                     double (&L)[NL], double& gam_out) {
     const double gam = gamma_of<SB>(A, b, c, ix, iy);
     gam_out = gam;
     double R[NL], lam;
-    residual(A, b, c, ix, iy, R, lam);
+    residual<XBC>(A, b, c, ix, iy, R, lam);
     finish(A, c, gam, lam, R, L);
   }
 
   // Volume minus face terms of the weak form (R) and the cell's wave speed
   // lambda_e (before the override)
+  template <bool XBC = false>
   __device__ static inline void residual(const StageArgs& A, const double* b, const double (&c)[NL], int ix, int iy,
                                          double (&R)[NL], double& lam) {
     const double hh = 0.5 * A.h;
@@ -482,6 +549,12 @@ struct Cell {
         const int axis = f >> 1;
         const bool plus = f & 1;
         const double s = plus ? 1.0 : -1.0;
+        // a boundary face under BC_RIEMANN reads u^+ at its nodes from the slot
+        bool xb = false;
+        if constexpr (XBC && FLUX == FLUX_BURGERS) {
+          if (A.bc_kind == BC_RIEMANN)
+            xb = f == 0 ? ix == 0 : f == 1 ? ix == A.nx - 1 : f == 2 ? iy == 0 : iy == A.ny - 1;
+        }
         double tm[N], tp[N];
 #pragma unroll
         for (int k = 0; k < N; ++k) {
@@ -505,6 +578,9 @@ struct Cell {
           for (int k = 1; k < N; ++k) {
             um = fma(tm[k], TB::nd.L[k][r], um);
             up = fma(tp[k], TB::nd.L[k][r], up);
+          }
+          if constexpr (XBC && FLUX == FLUX_BURGERS) {
+            if (xb) up = b[r * S + off(f)];
           }
           const double vax = axis == 0 ? vxl[r] : vyl[r];
           double H;
@@ -664,7 +740,8 @@ __device__ inline void load_slot(const StageArgs& A, double* lds, int slot, int 
 // threads also load the halo ring.  After one barrier each thread evaluates
 // its cell from registers (own) and LDS (face neighbours), reads U^n of its
 // cell and writes the RK combination straight to HBM.
-template <int DIM, int P, int FLUX, int MODE, int TX, int TY>
+// XBC: compile the BC_RIEMANN exterior state in (2D Burgers per-stage kernel).
+template <int DIM, int P, int FLUX, int MODE, int TX, int TY, bool XBC = false>
 __device__ inline void stage_tile(const StageArgs& A, double* lds, int ix0, int iy0) {
   using G = TileGeom<DIM, TX, TY>;
   using C = Cell<DIM, P, FLUX, MODE, G::S, G::W>;
@@ -681,13 +758,26 @@ __device__ inline void stage_tile(const StageArgs& A, double* lds, int ix0, int 
   // own slot (cells past a ragged edge hold the wrapped or exterior state)
   double c[NL];
   load_cell<DIM, NL>(A, gx, gy, c);
-  if (halo) load_slot<DIM, NL, S>(A, lds, hs, hgx, hgy);
+  bool xbc = false;  // exterior slots from the exact solution (BC_RIEMANN)
+  if constexpr (XBC) xbc = A.bc_kind == BC_RIEMANN;
+  if (xbc) {
+    C::riemann_slot(A, gx, gy, c);
+    if (halo) {
+      double v[NL];
+      load_cell<DIM, NL>(A, hgx, hgy, v);
+      C::riemann_slot(A, hgx, hgy, v);
+#pragma unroll
+      for (int j = 0; j < NL; ++j) lds[j * S + hs] = v[j];
+    }
+  } else if (halo) {
+    load_slot<DIM, NL, S>(A, lds, hs, hgx, hgy);
+  }
 #pragma unroll
   for (int j = 0; j < NL; ++j) lds[j * S + sc] = c[j];
   tile_barrier();
   if (active) {
     double L[NL], gam;
-    C::rhs(A, lds + sc, c, gx, gy, L, gam);
+    C::template rhs<true, XBC>(A, lds + sc, c, gx, gy, L, gam);
     if (A.gamma) A.gamma[cell] = gam;
     double* dst = A.out + cell * NL;
     if (A.rhs_only) {
@@ -713,7 +803,8 @@ __device__ inline void stage_tile(const StageArgs& A, double* lds, int ix0, int 
 template <int DIM, int P, int FLUX, int MODE, int TX, int TY>
 __global__ void __launch_bounds__(DIM == 2 ? TX * TY : TX) stage_kernel(const StageArgs A) {
   extern __shared__ double lds[];
-  stage_tile<DIM, P, FLUX, MODE, TX, TY>(A, lds, blockIdx.x * TX, DIM == 2 ? blockIdx.y * TY : 0);
+  stage_tile<DIM, P, FLUX, MODE, TX, TY, DIM == 2 && FLUX == FLUX_BURGERS>(A, lds, blockIdx.x * TX,
+                                                                         DIM == 2 ? blockIdx.y * TY : 0);
 }
 
 // ---------------------------------------------------------------------------

@@ -45,6 +45,7 @@ class MeshDesc(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("zhao_theta", ctypes.c_double),
         ("rk_order", ctypes.c_int32),
+        ("bc_kind", ctypes.c_int32),
     ]
 
 
@@ -69,6 +70,8 @@ EXPORTS = {
     "dg_get_tile": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_int32)]),
     "dg_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "dg_set_time": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double]),
+    "dg_get_time": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
     "dg_stream_copy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     "dg_last_error": (ctypes.c_char_p, []),
     "dg_validate_desc": (ctypes.c_int, [ctypes.POINTER(MeshDesc)]),
@@ -145,6 +148,7 @@ def desc_from_fields(f: dict) -> MeshDesc:
     d.lambda_override = f["lambda_override"]
     d.zhao_theta = f.get("theta", 1.0)
     d.rk_order = f.get("rk_order", 3)
+    d.bc_kind = f.get("bc_kind", 0)
     return d
 
 
@@ -213,6 +217,16 @@ class DG:
     def run(self, U: torch.Tensor, dt: float, nsteps: int) -> torch.Tensor:
         _check(self.lib.dg_run(self.h, _ptr(U, self.ncells * self.nloc, "U"), float(dt), int(nsteps)))
         return U
+
+    def set_time(self, t: float) -> None:
+        """Set the context's clock (dg_set_time): the time of the state the
+        next dg_step / dg_run / dg_rhs sees."""
+        _check(self.lib.dg_set_time(self.h, float(t)))
+
+    def time(self) -> float:
+        t = ctypes.c_double()
+        _check(self.lib.dg_get_time(self.h, ctypes.byref(t)))
+        return t.value
 
     def stable_dt(self, U: torch.Tensor, cfl: float) -> float:
         out = ctypes.c_double()

@@ -49,8 +49,8 @@ def _desc(**kw):
 
 def test_default_desc(lib):
     d = _desc()
-    assert (d.dim, d.nx, d.p, d.mode, d.q, d.b, d.w_nb, d.weno_eps, d.weno_pow, d.rk_order) == \
-        (1, 64, 2, 2, 1.0, 0.0, 0.01, 1e-6, 2.0, 3)
+    assert (d.dim, d.nx, d.p, d.mode, d.q, d.b, d.w_nb, d.weno_eps, d.weno_pow, d.rk_order, d.bc_kind) == \
+        (1, 64, 2, 2, 1.0, 0.0, 0.01, 1e-6, 2.0, 3, 0)
 
 
 @pytest.mark.parametrize("bad", [
@@ -59,6 +59,9 @@ def test_default_desc(lib):
     dict(x1=0.0), dict(flux=7), dict(mode=9), dict(q=0.5), dict(b=1.5),
     dict(w_nb=0.6), dict(weno_eps=0.0), dict(weno_pow=-1.0), dict(lambda_override=-1.0),
     dict(vel_x=float("nan")), dict(rk_order=1), dict(rk_order=5), dict(zhao_theta=0.0),
+    dict(bc_kind=2), dict(bc_kind=1, flux=1),                         # the exact exterior state is 2D
+    dict(dim=2, nx=8, ny=8, flux=1, bc_kind=1),                       # ... on non-periodic boundaries
+    dict(dim=2, nx=8, ny=8, flux=0, bc_kind=1, periodic_x=0, periodic_y=0),   # ... for Burgers
 ])
 def test_invalid_descriptors_rejected_on_host(lib, bad):
     d = _desc(**bad)
