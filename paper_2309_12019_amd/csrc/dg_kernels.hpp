@@ -171,6 +171,7 @@ struct Cell {
   // reads it (node order of the face loop) at time A.t; a slot outside two
   // boundaries (used by no face) holds zeros; slots inside are left alone.
   __device__ static inline void riemann_slot(const StageArgs& A, int gx, int gy, double (&v)[NL]) {
+    static_assert(Q <= NL, "the face nodes must fit the slot's planes");
     const bool ox = (unsigned)gx >= (unsigned)A.nx, oy = (unsigned)gy >= (unsigned)A.ny;
     if (!ox && !oy) return;
 #pragma unroll
@@ -759,19 +760,20 @@ __device__ inline void stage_tile(const StageArgs& A, double* lds, int ix0, int 
   double c[NL];
   load_cell<DIM, NL>(A, gx, gy, c);
   bool xbc = false;  // exterior slots from the exact solution (BC_RIEMANN)
-  if constexpr (XBC) xbc = A.bc_kind == BC_RIEMANN;
-  if (xbc) {
-    C::riemann_slot(A, gx, gy, c);
-    if (halo) {
-      double v[NL];
-      load_cell<DIM, NL>(A, hgx, hgy, v);
-      C::riemann_slot(A, hgx, hgy, v);
+  if constexpr (XBC) {
+    xbc = A.bc_kind == BC_RIEMANN;
+    if (xbc) {
+      C::riemann_slot(A, gx, gy, c);
+      if (halo) {
+        double v[NL];
+        load_cell<DIM, NL>(A, hgx, hgy, v);
+        C::riemann_slot(A, hgx, hgy, v);
 #pragma unroll
-      for (int j = 0; j < NL; ++j) lds[j * S + hs] = v[j];
+        for (int j = 0; j < NL; ++j) lds[j * S + hs] = v[j];
+      }
     }
-  } else if (halo) {
-    load_slot<DIM, NL, S>(A, lds, hs, hgx, hgy);
   }
+  if (!xbc && halo) load_slot<DIM, NL, S>(A, lds, hs, hgx, hgy);
 #pragma unroll
   for (int j = 0; j < NL; ++j) lds[j * S + sc] = c[j];
   tile_barrier();
