@@ -21,6 +21,7 @@ from typing import Callable, List, Optional
 import numpy as np
 
 LINADV, BURGERS, KPP = 0, 1, 2
+EULER = 3   # the 1D Euler equations of Sec. 5.6 (three conserved variables per point)
 MODE_DG, MODE_LO, MODE_WENO = 0, 1, 2
 MODE_ZHAO = 3   # the sensor of Zhao et al. compared in Sec. 5.6
 BC_CONSTANT, BC_RIEMANN = 0, 1   # exterior state: bc_value, or Sec. 5.4's exact solution
@@ -88,6 +89,8 @@ class Workload:
         if self.flux == KPP:
             # ||F'(u)||_2 = 1; a larger lambda override also bounds the step
             return max(1.0, self.lambda_override)
+        if self.flux == EULER:
+            return self.umax     # a stated bound on |v| + c over the run
         a = abs(self.vx) if self.dim == 1 else math.hypot(self.vx, self.vy)
         return a * self.umax
 
@@ -313,6 +316,31 @@ def riemann_quadrants(x, y):
     o = _Ops(x)
     north, east = y > 0.5, x > 0.5
     return o.where(north, o.where(east, -1.0, -0.2), o.where(east, 0.8, 0.5))
+
+
+def sod_tube(x):
+    """Sod's shock tube (Sec. 5.6) in conserved variables (rho, rho v, rho E),
+    stacked on the axis before the last: (1, 0, 2.5) left of x = 1/2 (rho = 1,
+    v = 0, p = 1), (0.125, 0, 0.25) right of it (rho = 0.125, v = 0, p = 0.1),
+    gamma = 1.4."""
+    o = _Ops(x)
+    left = x < 0.5
+    rho = o.where(left, 1.0, 0.125)
+    m = o.where(left, 0.0, 0.0)
+    E = o.where(left, 2.5, 0.25)
+    return o.m.stack([rho, m, E], -2) if o.t else np.stack([rho, m, E], axis=-2)
+
+
+def sod1d(n: int = 128, p: int = 2, mode: int = MODE_WENO, steps: Optional[int] = None,
+          cfl: float = 0.1, t_end: float = 0.231) -> Workload:
+    """Sod's shock tube of Sec. 5.6: the 1D Euler equations on (0, 1) between
+    reflecting walls, n cells, run to t_end (the paper: 128 cells, P2,
+    t = 0.231).  The step uses 2 as a bound on |v| + c over the run (the
+    star region between the waves has |v| + c of about 1.93)."""
+    w = Workload(name=f"sod1d_{n}_p{p}", dim=1, nx=n, periodic_x=False, p=p, flux=EULER,
+                 vx=0.0, mode=mode, cfl=cfl, ic=sod_tube, umax=2.0)
+    w.steps = steps if steps is not None else int(math.ceil(t_end / w.dt()))
+    return w
 
 
 def burgers2d_riemann(n: int = 128, p: int = 2, mode: int = MODE_WENO, steps: Optional[int] = None,
