@@ -60,6 +60,10 @@ def workload(name):
         # the four-quadrant problem of Sec. 5.4 at the paper's size (exact
         # exterior state at every stage time; steps launched without a graph)
         "burgers2d_riemann_128_p2": lambda: inputs.burgers2d_riemann(128, 2),
+        # the 1D Euler equations of Sec. 5.6: Sod's tube at the paper's size,
+        # and on 2^20 cells (28 MB per state) for the per-stage kernel's bandwidth
+        "sod1d_128_p2": lambda: inputs.sod1d(128, 2),
+        "sod1d_1m_p2": lambda: inputs.sod1d(1 << 20, 2, steps=100),
     }
     return table[name]()
 
@@ -381,7 +385,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="rot2d_256_p2")
     ap.add_argument("--extra", default="rot2d_256_p3,burgers2d_1024_p2,rot2d_256_p2_zhao,kpp2d_128_p2,"
-                    "rot2d_256_p3_rk4,burgers2d_1024_p2_rk4,burgers2d_riemann_128_p2",
+                    "rot2d_256_p3_rk4,burgers2d_1024_p2_rk4,burgers2d_riemann_128_p2,sod1d_128_p2,sod1d_1m_p2",
                     help="comma-separated workloads reported alongside (no cpu baseline)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")

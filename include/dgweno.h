@@ -12,6 +12,15 @@
  *   DG_FLUX_KPP    : F(u) = (sin u, cos u), the non-convex flux of Sec. 5.5
  *                    (2D only; LLF wave speed max |F'(w) . n| over w between
  *                    the two states, exactly; p + 2 quadrature points)
+ *   DG_FLUX_EULER  : the 1D Euler equations of Sec. 5.6, a system for
+ *                    U = (rho, rho v, rho E) with F = (rho v, rho v^2 + p,
+ *                    (rho E + p) v), p = 0.4 (rho E - rho v^2 / 2); LLF wave
+ *                    speed max(|v| + c) of the two states, lambda_e the
+ *                    largest |v| + c at the p + 2 volume Gauss points,
+ *                    gamma_e from the density coefficients alone (the same
+ *                    for all three components); a non-periodic end is a
+ *                    reflecting wall (mirror state (rho, -rho v, rho E);
+ *                    bc_value unused).  Per-stage kernel only.
  * discretised in the broken space V_p (Sec. 2): tensor Legendre polynomials
  * of degree p per axis on every cell.  The library evaluates
  *   dU/dt = M^{-1} (R(U) - s(U))
@@ -25,6 +34,8 @@
  *   U[cell * n_loc + j], cell = ix + nx * iy (x fastest), n_loc = (p+1)^dim,
  *   j = a + (p+1) * b where a is the x-degree and b the y-degree of the
  *   Legendre product P_a(xi) P_b(eta) on the reference cell [-1,1]^dim.
+ *   DG_FLUX_EULER: n_loc = 3 (p+1), j = k (p+1) + a for component k
+ *   (rho, rho v, rho E) and degree a.
  *
  * Conventions for every entry point:
  *   - Return 0 on success, a negative DG_E* code on failure; the message of
@@ -54,7 +65,7 @@ enum dg_status {
   DG_EUNSUPPORTED = -5  /* valid but not built (e.g. an unsupported size) */
 };
 
-enum dg_flux { DG_FLUX_LINADV = 0, DG_FLUX_BURGERS = 1, DG_FLUX_KPP = 2 };
+enum dg_flux { DG_FLUX_LINADV = 0, DG_FLUX_BURGERS = 1, DG_FLUX_KPP = 2, DG_FLUX_EULER = 3 };
 
 /* Scheme labels of Sec. 5: DG (no stabilisation), LO (gamma_e = 1 in
  * eq. astab, i.e. the low-order operator of eq. lostab), WENO (gamma_e from
@@ -127,7 +138,8 @@ int dg_proj_nodes(const dg_ctx* ctx, double* xy_host);
 /* L2 projection of initial data onto V_p (Sec. 2, eq. fesol):
  * U_j = (int phi_j u0 dx) / (int phi_j^2 dx), the integral taken with the
  * projection rule.  u_at_nodes (device, [cell][node]) holds u0 at the nodes
- * from dg_proj_nodes; U (device) receives the coefficients. */
+ * from dg_proj_nodes ([cell][component][node] for DG_FLUX_EULER, the
+ * conserved variables); U (device) receives the coefficients. */
 int dg_project_ic(dg_ctx* ctx, const double* u_at_nodes, double* U);
 
 /* The context's clock: the time of the state that dg_step and dg_run
@@ -194,8 +206,8 @@ int dg_get_tile(const dg_ctx* ctx, int32_t* tx, int32_t* ty);
  * in 1D, and in 2D for meshes of at most one 16x16 tile per compute unit,
  * where per-stage launches are latency bound), 0 off, 1 on.  Errors:
  * DG_EINVAL for another mode, DG_EUNSUPPORTED for mode 1 when the three
- * tiles exceed LDS (2D degree 4), rk_order is not 3 or bc_kind is not
- * CONSTANT; in those cases the automatic mode never uses it.  dg_get_fused writes 1 if steps use it.
+ * tiles exceed LDS (2D degree 4), rk_order is not 3, bc_kind is not
+ * CONSTANT or the flux is Euler; in those cases the automatic mode never uses it.  dg_get_fused writes 1 if steps use it.
  * Mode 0 also makes the adjoint (below) launch its two passes of every stage
  * separately instead of sharing launches between consecutive stages; the
  * result is bitwise the same either way. */
@@ -217,7 +229,8 @@ const char* dg_last_error(void);
  * used (ties: split evenly).  The first adjoint call on a context allocates
  * two state-sized buffers and two sensor-record buffers (DG_EUNSUPPORTED if
  * the adjoint kernels' tile exceeds LDS).  Every adjoint call returns
- * DG_EUNSUPPORTED for mode ZHAO, for the KPP flux and for bc_kind RIEMANN;
+ * DG_EUNSUPPORTED for mode ZHAO, for the KPP and Euler fluxes and for bc_kind
+ * RIEMANN;
  * the step and run adjoints also for rk_order other than 3.
  * ------------------------------------------------------------------------ */
 
@@ -270,8 +283,8 @@ int dg_validate_desc(const dg_mesh_desc* desc);
 typedef struct dg_batch dg_batch;
 
 /* Create a batch from `count` descriptors (each validated as for
- * dg_init_mesh; DG_EUNSUPPORTED for rk_order other than 3 or bc_kind
- * RIEMANN; all work runs on
+ * dg_init_mesh; DG_EUNSUPPORTED for rk_order other than 3, bc_kind RIEMANN
+ * or the Euler flux; all work runs on
  * descs[0].stream).  Allocates the problem
  * table, tile lists and two stage arenas of the batch's total size. */
 int dg_batch_create(const dg_mesh_desc* descs, int32_t count, dg_batch** out);

@@ -264,8 +264,10 @@ int validate(const dg_mesh_desc* d) {
     const double hx = (d->x1 - d->x0) / d->nx, hy = (d->y1 - d->y0) / d->ny;
     if (std::fabs(hx - hy) > 1e-12 * hx) return fail(DG_EINVAL, "2D cells must be square (hx=%g hy=%g)", hx, hy);
   }
-  if (d->flux != DG_FLUX_LINADV && d->flux != DG_FLUX_BURGERS && d->flux != DG_FLUX_KPP)
+  if (d->flux != DG_FLUX_LINADV && d->flux != DG_FLUX_BURGERS && d->flux != DG_FLUX_KPP &&
+      d->flux != DG_FLUX_EULER)
     return fail(DG_EINVAL, "unknown flux %d", d->flux);
+  if (d->flux == DG_FLUX_EULER && d->dim != 1) return fail(DG_EINVAL, "the Euler system is one-dimensional here");
   if (d->flux == DG_FLUX_KPP && d->dim != 2) return fail(DG_EINVAL, "the KPP flux is two-dimensional");
   if (d->mode != DG_MODE_DG && d->mode != DG_MODE_LO && d->mode != DG_MODE_WENO && d->mode != DG_MODE_ZHAO)
     return fail(DG_EINVAL, "unknown mode %d", d->mode);
@@ -311,6 +313,7 @@ int check_tile(const dg_ctx* c, int tx, int ty) {
 int zrec_size(int dim, int nl) { return dgk::zrec_doubles(dim, nl); }
 
 int ensure_adjoint(dg_ctx* c) {
+  if (c->d.flux == DG_FLUX_EULER) return fail(DG_EUNSUPPORTED, "the adjoint does not cover the Euler system");
   if (c->d.bc_kind != DG_BC_CONSTANT)
     return fail(DG_EUNSUPPORTED, "the adjoint does not cover the exact-solution exterior state");
   if (c->d.mode == DG_MODE_ZHAO) return fail(DG_EUNSUPPORTED, "the adjoint does not cover the ZHAO sensor");
@@ -569,6 +572,7 @@ int dg_validate_desc(const dg_mesh_desc* desc) {
 bool fused_fits(const dg_ctx* c) {
   if (c->d.rk_order != 3) return false;            // the fused kernel is the three-stage method
   if (c->d.bc_kind != DG_BC_CONSTANT) return false;  // its rings take the constant exterior state
+  if (c->d.flux == DG_FLUX_EULER) return false;      // scalar states only
   if (c->d.dim == 2 && c->d.p == 4) return false;  // not built (its tiles exceed LDS)
   const int tx = c->d.dim == 1 ? dgk::kStepTile1D : dgk::kStepTile2D;
   const int ty = c->d.dim == 1 ? 1 : dgk::kStepTile2D;
@@ -600,6 +604,7 @@ int dg_init_mesh(const dg_mesh_desc* desc, dg_ctx** out) {
   c->d = *desc;
   if (c->d.dim == 1) c->d.ny = 1;
   c->nl = c->d.dim == 1 ? c->d.p + 1 : (c->d.p + 1) * (c->d.p + 1);
+  if (c->d.flux == DG_FLUX_EULER) c->nl *= 3;   // (rho, rho v, rho E) per coefficient
   c->ncells = (long long)c->d.nx * c->d.ny;
   c->h = (c->d.x1 - c->d.x0) / c->d.nx;
   c->stream = static_cast<hipStream_t>(desc->stream);
@@ -705,7 +710,8 @@ int dg_project_ic(dg_ctx* c, const double* u_at_nodes, double* U) {
   r.kind = dgk::LAUNCH_PROJECT;
   r.src = u_at_nodes;
   r.dst = U;
-  r.ncells = c->ncells;
+  // the Euler state projects component by component ([cell][component][...])
+  r.ncells = c->ncells * (c->d.flux == DG_FLUX_EULER ? 3 : 1);
   r.stream = c->stream;
   hipError_t e = c->launch(&r);
   return e == hipSuccess ? DG_OK : hip_fail(e, "projection launch");
@@ -873,6 +879,8 @@ int dg_set_fused(dg_ctx* c, int32_t mode) {
     return fail(DG_EUNSUPPORTED, "the fused step kernel implements the three-stage SSP method only");
   if (mode == 1 && c->d.bc_kind != DG_BC_CONSTANT)
     return fail(DG_EUNSUPPORTED, "the fused step kernel takes the constant exterior state only");
+  if (mode == 1 && c->d.flux == DG_FLUX_EULER)
+    return fail(DG_EUNSUPPORTED, "the fused step kernel takes scalar states only");
   if (mode == 1 && !fused_fits(c))
     return fail(DG_EUNSUPPORTED, "the fused step kernel's LDS tiles exceed the device limit for this degree");
   c->fused_mode = mode;
@@ -946,6 +954,7 @@ int dg_adjoint_forward(dg_ctx* c, const double* U0, double* UT, double dt, int32
   if (c->d.rk_order != 3) return fail(DG_EUNSUPPORTED, "the step adjoint covers the three-stage SSP method only");
   if (c->d.bc_kind != DG_BC_CONSTANT)
     return fail(DG_EUNSUPPORTED, "the adjoint does not cover the exact-solution exterior state");
+  if (c->d.flux == DG_FLUX_EULER) return fail(DG_EUNSUPPORTED, "the adjoint does not cover the Euler system");
   if (c->d.mode == DG_MODE_ZHAO) return fail(DG_EUNSUPPORTED, "the adjoint does not cover the ZHAO sensor");
   if (c->d.flux == DG_FLUX_KPP) return fail(DG_EUNSUPPORTED, "the adjoint does not cover the KPP flux");
   if (nsteps < 1 || nsnaps < 0) return fail(DG_EINVAL, "need nsteps >= 1 and nsnaps >= 0");

@@ -244,6 +244,7 @@ int dg_batch_create(const dg_mesh_desc* descs, int32_t count, dg_batch** out) {
     if (d.rk_order != 3) return bfail(DG_EUNSUPPORTED, "problem %d: batched runs use the three-stage SSP method only", i);
     if (d.bc_kind != DG_BC_CONSTANT)
       return bfail(DG_EUNSUPPORTED, "problem %d: batched runs take the constant exterior state only", i);
+    if (d.flux == DG_FLUX_EULER) return bfail(DG_EUNSUPPORTED, "problem %d: batched runs take scalar states only", i);
   }
   dg_batch* b = new (std::nothrow) dg_batch();
   if (!b) return bfail(DG_ENOMEM, "host allocation failed");

@@ -1,0 +1,206 @@
+// Device code of the one-dimensional Euler equations of Sec. 5.6:
+// U = (rho, rho v, rho E), F(U) = (rho v, rho v^2 + p, (rho E + p) v),
+// p = (gamma - 1)(rho E - rho v^2 / 2), gamma = 1.4, with the same DG
+// operator, dissipation and sensor as the scalar path:
+//   L_k = (2/h) Mhat^-1 [ vol_k - face_k - (gamma_e lambda_e / p) Khat c_k ]
+// for the three components k, gamma_e from the density coefficients alone.
+// The LLF wave speed is the larger |v| + c of the two states, lambda_e the
+// largest |v| + c over the volume Gauss nodes (p + 2 of them: the flux is
+// rational), and a reflecting wall sees the mirror state (rho, -rho v, rho E).
+//
+// State layout: cell-major, [cell][component][coefficient] (3 (p+1) doubles
+// per cell).  A tile of TX cells holds the 3 (p+1) coefficient planes of its
+// cells and a one-cell halo in LDS (density planes first, so the scalar
+// sensor reads them unchanged).
+#pragma once
+
+#include "dg_kernels.hpp"
+
+namespace dgk {
+
+constexpr double kEulerGamma = 1.4;
+
+// F(u) and |v| + c of one state
+__device__ inline void euler_flux(const double (&u)[3], double (&F)[3], double& speed) {
+  const double v = u[1] / u[0];
+  const double p = (kEulerGamma - 1.0) * (u[2] - 0.5 * u[1] * v);
+  F[0] = u[1];
+  F[1] = fma(u[1], v, p);
+  F[2] = (u[2] + p) * v;
+  speed = fabs(v) + sqrt(kEulerGamma * p / u[0]);
+}
+
+// H . n of the LLF flux for the outward normal n = side
+__device__ inline void llf_euler(double side, const double (&um)[3], const double (&up)[3], double (&H)[3]) {
+  double Fm[3], Fp[3], sm, sp;
+  euler_flux(um, Fm, sm);
+  euler_flux(up, Fp, sp);
+  const double s = fmax(sm, sp);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) H[k] = 0.5 * side * (Fm[k] + Fp[k]) - 0.5 * s * (up[k] - um[k]);
+}
+
+template <int P, int MODE, int TX>
+struct EulerCell {
+  using G = TileGeom<1, TX, 1>;
+  using C = Cell<1, P, FLUX_EULER, MODE, G::S, G::W>;  // sensor, dissipation, tables
+  using TB = typename C::TB;
+  static constexpr int N = P + 1;
+  static constexpr int Q = TB::Q;
+  static constexpr int S = G::S;
+
+  // Volume minus face terms for the three components, and lambda_e.
+  // b: the cell's slot in the LDS tile (plane j = k N + a); c[k][a]: own state.
+  __device__ static inline void residual(const StageArgs& A, const double* b, const double (&c)[3][N], int ix,
+                                         double (&R)[3][N], double& lam) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int a = 0; a < N; ++a) R[k][a] = 0.0;
+    lam = 0.0;
+    // ---- volume  int phi_a' F(u_h)
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      double u[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        double t = c[k][0];
+#pragma unroll
+        for (int a = 1; a < N; ++a) t = fma(c[k][a], TB::nd.L[a][q], t);
+        u[k] = t;
+      }
+      double F[3], sp;
+      euler_flux(u, F, sp);
+      lam = fmax(lam, sp);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double wF = TB::nd.w[q] * F[k];
+#pragma unroll
+        for (int a = 1; a < N; ++a) R[k][a] = fma(TB::nd.D[a][q], wF, R[k][a]);
+      }
+    }
+    // ---- faces  - phi_a H . n at x_{e -/+ 1/2}
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+      const bool wall = !A.per_x && (f ? ix == A.nx - 1 : ix == 0);
+      double um[3], up[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        double tm = 0.0, tp = 0.0;
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+          const double so = f ? 1.0 : TB::dg.sgn[a];  // P_a at this cell's face
+          const double sn = f ? TB::dg.sgn[a] : 1.0;  // P_a at the neighbour's face
+          tm = fma(so, c[k][a], tm);
+          tp = fma(sn, b[(k * N + a) * S + C::off(f)], tp);
+        }
+        um[k] = tm;
+        up[k] = tp;
+      }
+      if (wall) {
+        up[0] = um[0];
+        up[1] = -um[1];
+        up[2] = um[2];
+      }
+      double H[3];
+      llf_euler(f ? 1.0 : -1.0, um, up, H);
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int a = 0; a < N; ++a) R[k][a] = fma(f ? -1.0 : -TB::dg.sgn[a], H[k], R[k][a]);
+    }
+  }
+};
+
+// One tile of the Euler stage: TX threads, one per cell; the layout and the
+// barrier discipline of the scalar stage tile.  out = a U^n + b (U + dt L),
+// or out = L when rhs_only; gamma (optional) receives gamma_e.
+template <int P, int MODE, int TX>
+__device__ inline void euler_stage_tile(const StageArgs& A, double* lds, int ix0) {
+  using E = EulerCell<P, MODE, TX>;
+  using C = typename E::C;
+  constexpr int N = E::N, NLE = 3 * N, S = E::S;
+  const bool comb = !A.rhs_only && A.a != 0.0;
+  const int t = threadIdx.x;
+  int sc, gx, gy, hs, hgx, hgy;
+  const bool halo = tile_slots<1, TX, 1>(t, ix0, 0, sc, gx, gy, hs, hgx, hgy);
+  const bool active = gx < A.nx;
+  double cf[NLE];
+  load_cell<1, NLE>(A, gx, 0, cf);
+  if (halo) load_slot<1, NLE, S>(A, lds, hs, hgx, 0);
+#pragma unroll
+  for (int j = 0; j < NLE; ++j) lds[j * S + sc] = cf[j];
+  tile_barrier();
+  if (active) {
+    double c[3][N], rho[N];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int a = 0; a < N; ++a) c[k][a] = cf[k * N + a];
+#pragma unroll
+    for (int a = 0; a < N; ++a) rho[a] = c[0][a];
+    const double gam = C::template gamma_of<true>(A, lds + sc, rho, gx, 0);
+    double R[3][N], lam;
+    E::residual(A, lds + sc, c, gx, R, lam);
+    if (A.gamma) A.gamma[gx] = gam;
+    double* dst = A.out + (size_t)gx * NLE;
+    const double* un = comb ? A.un + (size_t)gx * NLE : nullptr;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      double L[N];
+      C::finish(A, c[k], gam, lam, R[k], L);
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        double v = L[a];
+        if (!A.rhs_only) {
+          v = A.b * fma(A.dt, L[a], c[k][a]);
+          if (comb) v = fma(A.a, un[k * N + a], v);
+        }
+        dst[k * N + a] = v;
+      }
+    }
+  }
+}
+
+template <int P, int MODE, int TX>
+__global__ void __launch_bounds__(TX) euler_stage_kernel(const StageArgs A) {
+  extern __shared__ double lds[];
+  euler_stage_tile<P, MODE, TX>(A, lds, blockIdx.x * TX);
+}
+
+// Per-block maximum of lambda_e = max over the volume nodes of |v| + c.
+template <int P>
+__global__ void __launch_bounds__(256) euler_lambda_kernel(const StageArgs A, const double* __restrict__ U,
+                                                           double* __restrict__ block_max) {
+  using TB = Tables<1, P, FLUX_EULER>;
+  constexpr int N = P + 1, Q = TB::Q;
+  __shared__ double red[256];
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  double lam = 0.0;
+  if (e < A.nx) {
+    if (A.lam_over > 0.0) {
+      lam = A.lam_over;
+    } else {
+      const double* c = U + e * 3 * N;
+      for (int q = 0; q < Q; ++q) {
+        double u[3], F[3], sp;
+        for (int k = 0; k < 3; ++k) {
+          double s = 0.0;
+          for (int a = 0; a < N; ++a) s = fma(c[k * N + a], TB::nd.L[a][q], s);
+          u[k] = s;
+        }
+        euler_flux(u, F, sp);
+        lam = fmax(lam, sp);
+      }
+    }
+  }
+  red[threadIdx.x] = lam;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) block_max[blockIdx.x] = red[0];
+}
+
+}  // namespace dgk

@@ -27,7 +27,7 @@
 
 namespace dgk {
 
-enum { FLUX_LINADV = 0, FLUX_BURGERS = 1, FLUX_KPP = 2 };  // KPP: 2D only
+enum { FLUX_LINADV = 0, FLUX_BURGERS = 1, FLUX_KPP = 2, FLUX_EULER = 3 };  // KPP: 2D; EULER: 1D system
 enum { MODE_DG = 0, MODE_LO = 1, MODE_WENO = 2, MODE_ZHAO = 3 };
 // exterior state at non-periodic faces: the constant bc, or (2D Burgers only)
 // the exact solution of the four-quadrant problem of Sec. 5.4 at time t

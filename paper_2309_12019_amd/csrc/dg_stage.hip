@@ -1,6 +1,7 @@
 // Kernel instantiations for one (dimension, degree) pair.  The build compiles
 // this file once per pair with -DDGK_DIM=<d> -DDGK_P=<p>, so the 8 pairs build
 // in parallel; each object exports dgk_launch_<d>_<p>.
+#include "dg_euler.hpp"
 #include "dg_launch.hpp"
 
 #ifndef DGK_DIM
@@ -167,6 +168,30 @@ hipError_t launch_adj_f(const LaunchReq* r) {
   }
 }
 
+template <int MODE, int TX>
+hipError_t launch_euler_tile(const StageArgs& A, hipStream_t st) {
+  constexpr int NLE = 3 * (DGK_P + 1);
+  const size_t lds = sizeof(double) * (size_t)tile_lds_doubles(1, NLE, TX, 1);
+  dim3 grid((A.nx + TX - 1) / TX), block(TX);
+  hipLaunchKernelGGL((euler_stage_kernel<DGK_P, MODE, TX>), grid, block, lds, st, A);
+  return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t launch_euler_m(const StageArgs& A, hipStream_t st) {
+  if (A.tx == 64) return launch_euler_tile<MODE, 64>(A, st);
+  return launch_euler_tile<MODE, 256>(A, st);
+}
+
+hipError_t launch_euler(int mode, const StageArgs& A, hipStream_t s) {
+  switch (mode) {
+    case MODE_DG: return launch_euler_m<MODE_DG>(A, s);
+    case MODE_LO: return launch_euler_m<MODE_LO>(A, s);
+    case MODE_ZHAO: return launch_euler_m<MODE_ZHAO>(A, s);
+    default: return launch_euler_m<MODE_WENO>(A, s);
+  }
+}
+
 template <int FLUX>
 hipError_t launch_stage_f(int mode, const StageArgs& A, hipStream_t s) {
   switch (mode) {
@@ -189,6 +214,10 @@ extern "C" hipError_t DGK_CAT(dgk_launch, DGK_DIM, DGK_P)(const LaunchReq* r) {
   const StageArgs& A = r->args;
   switch (r->kind) {
     case LAUNCH_STAGE: {
+      if (r->flux == FLUX_EULER) {
+        if constexpr (DGK_DIM == 1) return launch_euler(r->mode, A, r->stream);
+        return hipErrorInvalidValue;
+      }
       if (r->flux == FLUX_LINADV) return launch_stage_f<FLUX_LINADV>(r->mode, A, r->stream);
       if (r->flux == FLUX_BURGERS) return launch_stage_f<FLUX_BURGERS>(r->mode, A, r->stream);
       if constexpr (DGK_DIM == 2) return launch_stage_f<FLUX_KPP>(r->mode, A, r->stream);
@@ -223,6 +252,13 @@ extern "C" hipError_t DGK_CAT(dgk_launch, DGK_DIM, DGK_P)(const LaunchReq* r) {
     case LAUNCH_LAMBDA: {
       const long long n = r->ncells;
       dim3 grid((unsigned)((n + 255) / 256)), block(256);
+      if (r->flux == FLUX_EULER) {
+        if constexpr (DGK_DIM == 1) {
+          hipLaunchKernelGGL((euler_lambda_kernel<DGK_P>), grid, block, 0, r->stream, A, r->src, r->dst);
+          return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+      }
       if (r->flux == FLUX_LINADV)
         hipLaunchKernelGGL((lambda_kernel<DGK_DIM, DGK_P, FLUX_LINADV>), grid, block, 0, r->stream, A, r->src,
                            r->dst);

@@ -284,7 +284,7 @@ constexpr SenTab<DIM, P> make_sen() {
 // KPP (sin and cos of u_h: no exact rule): p+2.
 constexpr int quad_points(int dim, int p, int flux) {
   if (flux == 0) return p + 1;
-  if (flux == 2) return p + 2;
+  if (flux == 2 || flux == 3) return p + 2;  // KPP, Euler: rational or transcendental fluxes
   return dim == 1 ? (3 * p + 1) / 2 : (3 * p + 2) / 2;
 }
 

@@ -18,6 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdgweno.so")
 
 DG_OK, DG_EINVAL, DG_ENOMEM, DG_EDEVICE, DG_ENONFINITE, DG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+DG_FLUX_EULER = 3
 FLUX_LINADV, FLUX_BURGERS = 0, 1
 MODE_DG, MODE_LO, MODE_WENO = 0, 1, 2
 
@@ -167,6 +168,7 @@ class DG:
         nc, nl, nq = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
         _check(lib.dg_sizes(h, ctypes.byref(nc), ctypes.byref(nl), ctypes.byref(nq)))
         self.ncells, self.nloc, self.nproj = nc.value, nl.value, nq.value
+        self.ncomp = 3 if desc.flux == DG_FLUX_EULER else 1   # values per projection node
         self.device = torch.device("cuda", torch.cuda.current_device())
 
     @classmethod
@@ -199,7 +201,8 @@ class DG:
 
     def project_ic(self, u_at_nodes: torch.Tensor, U: Optional[torch.Tensor] = None) -> torch.Tensor:
         U = self.empty() if U is None else U
-        _check(self.lib.dg_project_ic(self.h, _ptr(u_at_nodes, self.ncells * self.nproj, "u_at_nodes"),
+        nvals = self.ncells * self.nproj * self.ncomp
+        _check(self.lib.dg_project_ic(self.h, _ptr(u_at_nodes, nvals, "u_at_nodes"),
                                       _ptr(U, self.ncells * self.nloc, "U")))
         return U
 

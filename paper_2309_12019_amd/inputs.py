@@ -72,7 +72,8 @@ class Workload:
 
     @property
     def nloc(self) -> int:
-        return (self.p + 1) ** self.dim
+        """Coefficients per cell: (p+1)^dim, times 3 for the Euler system."""
+        return (self.p + 1) ** self.dim * (3 if self.flux == EULER else 1)
 
     @property
     def ndof(self) -> int:

@@ -8,6 +8,7 @@ import torch
 
 from oracle.dgoracle import MODE_DG, MODE_LO, MODE_WENO, MODE_ZHAO, gauss_legendre
 from oracle.euler1d import EulerOracle, EulerProblem, conserved, flux, stable_dt, wave_speed
+from exact_sod import _star, sod_density
 from paper_2309_12019_amd import inputs
 
 GAMMA = 1.4   # the heat capacity ratio of Sec. 5.6 (stated here, not taken from the oracle)
@@ -141,39 +142,6 @@ def test_operator_against_bruteforce(p, mode):
 
 
 # --- Sod's problem against its exact solution -----------------------------
-def _star(g=GAMMA):
-    rl, pl, rr, pr = 1.0, 1.0, 0.125, 0.1
-    cl, cr = math.sqrt(g * pl / rl), math.sqrt(g * pr / rr)
-
-    def fk(p, rk, pk, ck):
-        if p > pk:
-            A, B = 2 / ((g + 1) * rk), (g - 1) / (g + 1) * pk
-            return (p - pk) * math.sqrt(A / (p + B))
-        return 2 * ck / (g - 1) * ((p / pk) ** ((g - 1) / (2 * g)) - 1)
-
-    lo, hi = 1e-8, 10.0
-    for _ in range(200):
-        mid = 0.5 * (lo + hi)
-        lo, hi = (mid, hi) if fk(mid, rl, pl, cl) + fk(mid, rr, pr, cr) < 0 else (lo, mid)
-    ps = 0.5 * (lo + hi)
-    us = 0.5 * (fk(ps, rr, pr, cr) - fk(ps, rl, pl, cl))
-    rls = rl * (ps / pl) ** (1 / g)
-    q = ps / pr
-    rrs = rr * (q + (g - 1) / (g + 1)) / ((g - 1) / (g + 1) * q + 1)
-    S = cr * math.sqrt((g + 1) / (2 * g) * q + (g - 1) / (2 * g))
-    return dict(ps=ps, us=us, rls=rls, rrs=rrs, S=S, cl=cl, cls=cl * (ps / pl) ** ((g - 1) / (2 * g)))
-
-
-def sod_density(x, t, g=GAMMA):
-    s = _star(g)
-    xi = (np.asarray(x) - 0.5) / t
-    cl = s["cl"]
-    fan_c = 2 / (g + 1) * (cl - (g - 1) / 2 * xi)
-    fan = 1.0 * (np.maximum(fan_c, 1e-300) / cl) ** (2 / (g - 1))
-    return np.select([xi < -cl, xi < s["us"] - s["cls"], xi < s["us"], xi < s["S"]],
-                     [1.0, fan, s["rls"], s["rrs"]], 0.125)
-
-
 def test_exact_sod_solution_satisfies_the_jump_conditions():
     """The star state: Rankine-Hugoniot across the right shock (mass, momentum,
     energy), the Riemann invariants across the left fan, p and v continuous at
