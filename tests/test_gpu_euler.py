@@ -157,3 +157,30 @@ def test_sod_at_the_papers_size():
     for name in ("LO", "WENO"):
         assert res[name][0] >= 0.125 - 1e-3 and res[name][1] <= 1.0 + 1e-3
     assert res["WENO"][2] < res["LO"][2]
+
+
+def test_sensor_comparison_on_sod():
+    """Sec. 5.6 compares four sensors on Sod's tube (128 cells, P2, t = 0.231):
+    the WENO sensor gamma_e is less diffusive than Zhao et al.'s gamma^Z, and
+    the thresholded gamma^b (b = 0.1, 0.2) is more accurate still.  Measured
+    as the L1 density error against the exact solution."""
+    dgweno = _dg()
+    xg, wg = (a.numpy() for a in gauss_legendre(4))
+    P = np.stack([np.ones_like(xg), xg, 1.5 * xg ** 2 - 0.5])
+    x = ((np.arange(128) + 0.5) / 128)[:, None] + 0.5 / 128 * xg[None, :]
+    exact = sod_density(x, 0.231)
+    err = {}
+    for name, mode, b in (("Z", inputs.MODE_ZHAO, 0.0), ("gamma", inputs.MODE_WENO, 0.0),
+                          ("b0.1", inputs.MODE_WENO, 0.1), ("b0.2", inputs.MODE_WENO, 0.2)):
+        w = inputs.sod1d(128, 2, mode=mode)
+        w.b = b
+        g = dgweno.DG.from_workload(w)
+        U = g.initial_state(w)
+        n = int(math.ceil(0.231 / w.dt()))
+        g.run(U, 0.231 / n, n)
+        torch.cuda.synchronize()
+        rho = U.cpu().reshape(128, 3, 3).numpy()[:, 0, :] @ P
+        err[name] = float((np.abs(rho - exact) * wg * 0.5 / 128).sum())
+        _note(f"[sod sensors] {name}: L1 density error {err[name]:.4e}, rho in [{rho.min():.4f}, {rho.max():.4f}]")
+    assert err["gamma"] < err["Z"]
+    assert err["b0.1"] < err["gamma"] and err["b0.2"] < err["gamma"]
