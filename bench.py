@@ -46,6 +46,8 @@ def workload(name):
         "burgers2d_1024_p2": lambda: inputs.burgers2d(1024, 2, seed=0),
         "adv1d_64_p2": lambda: inputs.adv1d(64, 2, steps=100),
         "rot2d_2048_p2": lambda: inputs.rot2d(2048, 2, seed=0, steps=50),
+        # the rotation at a bandwidth-bound size (per-stage kernel, 9.4 M DOFs)
+        "rot2d_1024_p2": lambda: inputs.rot2d(1024, 2, seed=0, steps=100),
         # the sensor of Zhao et al. (Sec. 5.6) in place of eq. (sensor)
         "rot2d_256_p2_zhao": lambda: inputs.rot2d(256, 2, seed=0, steps=200, mode=inputs.MODE_ZHAO),
         # the KPP problem of Sec. 5.5 at the paper's size (128^2, P2, lambda_e = 2, t = 1)
@@ -384,8 +386,9 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="rot2d_256_p2")
-    ap.add_argument("--extra", default="rot2d_256_p3,burgers2d_1024_p2,rot2d_256_p2_zhao,kpp2d_128_p2,"
-                    "rot2d_256_p3_rk4,burgers2d_1024_p2_rk4,burgers2d_riemann_128_p2,sod1d_128_p2,sod1d_1m_p2",
+    ap.add_argument("--extra", default="rot2d_256_p3,burgers2d_1024_p2,rot2d_1024_p2,rot2d_256_p2_zhao,"
+                    "kpp2d_128_p2,rot2d_256_p3_rk4,burgers2d_1024_p2_rk4,burgers2d_riemann_128_p2,"
+                    "sod1d_128_p2,sod1d_1m_p2",
                     help="comma-separated workloads reported alongside (no cpu baseline)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
