@@ -134,3 +134,20 @@ def test_papers_size_ranges_of_the_three_schemes():
     assert got["DG"][0] < lo0 - 0.2 and got["DG"][1] > hi0 + 0.2
     assert got["LO"][0] >= lo0 - 1e-3 and got["LO"][1] <= hi0 + 1e-3
     assert got["WENO"][0] >= lo0 - 1e-3 and got["WENO"][1] <= hi0 + 1e-3
+
+
+@pytest.mark.parametrize("n,p", [(2, 1), (4, 3), (18, 2)])
+def test_small_and_ragged_meshes(n, p):
+    """2 x 2 cells (every cell on two boundaries), 4 x 4 P3 and 18 x 18 (one
+    cell row past a 16 x 16 tile): 20 steps from t = 0.05 against the oracle."""
+    _note(f"[riemann edge] {n}^2 P{p}")
+    w = inputs.burgers2d_riemann(n, p, mode=inputs.MODE_WENO, steps=20)
+    O = oracle_for(w)
+    U0 = oracle_initial(w, O)
+    ref = O.run(U0, w.dt(), 20, 0.05)
+    g = _dg().DG.from_workload(w)
+    g.set_time(0.05)
+    U = U0.cuda().contiguous()
+    g.run(U, w.dt(), 20)
+    torch.cuda.synchronize()
+    assert relinf(U.cpu(), ref) <= 1e-11

@@ -172,3 +172,21 @@ def test_table1_weno_error_tends_to_the_dg_error():
         _note(f"    WENO / DG = {ratios[-1]:.4f}")
     assert ratios[0] > ratios[1] > ratios[2]
     assert ratios[2] < 1.1
+
+
+@pytest.mark.parametrize("k", [2, 4])
+def test_small_meshes_and_zero_steps(k):
+    """A 1-cell periodic mesh, a 3x3 rotation mesh, and zero steps (a no-op)."""
+    _note(f"[rk edge] order {k}")
+    for w in (inputs.adv1d(1, 2, mode=inputs.MODE_WENO), inputs.rot2d(3, 2, seed=1)):
+        w.rk_order = k
+        O = oracle_for(w)
+        U0 = _state(w, O, 9)
+        g = _dg().DG.from_workload(w)
+        U = U0.cuda().contiguous()
+        g.run(U, w.dt(), 0)
+        torch.cuda.synchronize()
+        assert torch.equal(U.cpu(), U0)
+        g.run(U, w.dt(), 7)
+        torch.cuda.synchronize()
+        assert relinf(U.cpu(), O.run(U0, w.dt(), 7)) <= 1e-11
