@@ -22,6 +22,7 @@ import numpy as np
 import pytest
 import torch
 
+from exact_burgers import burgers_exact
 from helpers import oracle_for, oracle_initial
 from paper_2309_12019_amd import inputs
 
@@ -190,3 +191,49 @@ def test_small_meshes_and_zero_steps(k):
         g.run(U, w.dt(), 7)
         torch.cuda.synchronize()
         assert relinf(U.cpu(), O.run(U0, w.dt(), 7)) <= 1e-11
+
+
+def _table2_error(p, N, mode, k=3, lam=0.0):
+    """L1 error at t = 0.1 of the GPU run of Sec. 5.2 (sin data, periodic unit
+    interval, CFL 0.1) with the SSP method of order k."""
+    w = inputs.burgers1d(N, p, mode=mode)
+    w.rk_order = k
+    w.lambda_override = lam
+    g = _dg().DG.from_workload(w)
+    U = g.initial_state(w)
+    n = int(math.ceil(0.1 / w.dt()))
+    g.run(U, 0.1 / n, n)
+    torch.cuda.synchronize()
+    O = oracle_for(w)          # the error functional only
+    Q = p + 3
+    xe = O.nodes(Q)[..., 0].numpy()
+    return O.l1_error(U.cpu(), torch.from_numpy(burgers_exact(xe, 0.1)), Q)
+
+
+TABLE2 = json.load(open(os.path.join(HERE, "golden", "paper_tables.json")))["table2_burgers"]["rows"]
+
+
+@pytest.mark.parametrize("p,tol", [(1, 0.25), (2, 0.08), (3, 0.08)])
+def test_table2_on_the_gpu(p, tol):
+    """Every row of Table 2 (Sec. 5.2, E_h = 16..2048; 512 for p = 3): the DG
+    errors within the oracle's tolerances of the printed ones and rates
+    within 0.3 of p + 1; the LO errors (global lambda = 1, as the oracle's
+    pins found) within 5 % and first order.  The p = 2 row at E_h = 16 is
+    left out, as in the oracle's pins: the paper's own rate from 16 to 32
+    cells there is 1.91, pre-asymptotic (the run here is 24 % above it)."""
+    sizes = [r["E_h"] for r in TABLE2 if r["p"] == p and not (p == 2 and r["E_h"] == 16)]
+    dg, lo = [], []
+    for N in sizes:
+        row = [r for r in TABLE2 if r["p"] == p and r["E_h"] == N][0]
+        e_dg = _table2_error(p, N, inputs.MODE_DG)
+        e_lo = _table2_error(p, N, inputs.MODE_LO, lam=1.0)
+        _note(f"[table 2] P{p} E_h={N}: DG {e_dg:.4e} (paper {row['DG']:.3e}, ratio {e_dg / row['DG']:.4f}), "
+              f"LO {e_lo:.4e} (paper {row['LO']:.3e}, ratio {e_lo / row['LO']:.4f})")
+        dg.append(e_dg)
+        lo.append(e_lo)
+        assert abs(e_dg / row["DG"] - 1) < tol
+        assert abs(e_lo / row["LO"] - 1) < 0.05
+    for a, b in zip(dg, dg[1:]):
+        assert abs(math.log2(a / b) - (p + 1)) < 0.3
+    for a, b in zip(lo, lo[1:]):
+        assert abs(math.log2(a / b) - 1) < 0.15

@@ -17,6 +17,7 @@ import pytest
 import scipy.linalg
 import torch
 
+from exact_burgers import burgers_exact
 from helpers import oracle_for, oracle_initial, oracle_problem
 from paper_2309_12019_amd import inputs
 
@@ -49,13 +50,6 @@ def _advection_error(p, N, mode, t=1.0):
     return O.l1_error(torch.from_numpy(UT.reshape(U0.shape)), exact, Q)
 
 
-def burgers_exact(x, t):
-    """u = u0(x - u t) for u0 = sin(2 pi x), solved by Newton's method."""
-    u = np.sin(2 * np.pi * x)
-    for _ in range(60):
-        a = 2 * np.pi * (x - u * t)
-        u = u - (u - np.sin(a)) / (1 + 2 * np.pi * t * np.cos(a))
-    return u
 
 
 def _burgers_error(p, N, mode, lam=0.0, t=0.1, cfl=0.1):
