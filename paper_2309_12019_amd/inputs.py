@@ -275,6 +275,34 @@ def rot2d(n: int = 256, p: int = 2, seed: int = 0, mode: int = MODE_WENO,
                     steps=steps, cfl=cfl, ic=HumpAndCylinder(seed), umax=1.0)
 
 
+def leveque_rotation(x, y):
+    """The three bodies of Sec. 5.3 (LeVeque's solid-body rotation): a smooth
+    hump 1/4 + 1/4 cos(pi r / 0.15) about (0.25, 0.5), a cone 1 - r / 0.15
+    about (0.5, 0.25), and a cylinder of height 1 about (0.5, 0.75) with a slot
+    |x - 0.5| < 0.025 below y = 0.85; radius 0.15 each, 0 elsewhere."""
+    o = _Ops(x)
+    r_h = o.m.sqrt((x - 0.25) ** 2 + (y - 0.5) ** 2)
+    r_c = o.m.sqrt((x - 0.5) ** 2 + (y - 0.25) ** 2)
+    r_s = o.m.sqrt((x - 0.5) ** 2 + (y - 0.75) ** 2)
+    hump = 0.25 + 0.25 * o.m.cos(np.pi * r_h / 0.15)
+    cone = 1.0 - r_c / 0.15
+    slot = (r_s <= 0.15) & ((o.m.abs(x - 0.5) >= 0.025) | (y >= 0.85))
+    return o.where(r_h <= 0.15, hump, o.where(r_c <= 0.15, cone, o.fl(slot)))
+
+
+def leveque2d(n: int = 128, p: int = 2, mode: int = MODE_WENO, steps: Optional[int] = None,
+              cfl: float = 0.1, t_end: float = 1.0) -> Workload:
+    """Sec. 5.3 as printed: v = 2 pi (0.5 - y, x - 0.5) on the unit square
+    (one revolution per unit time), the three bodies of leveque_rotation,
+    zero exterior state, n x n cells, run to t_end (the paper: 128^2, P2,
+    t = 1)."""
+    w = Workload(name=f"leveque2d_{n}_p{p}", dim=2, nx=n, ny=n, periodic_x=False, periodic_y=False,
+                 p=p, flux=LINADV, vx=0.0, vy=0.0, omega=2.0 * np.pi, cx=0.5, cy=0.5, bc_value=0.0,
+                 mode=mode, cfl=cfl, ic=leveque_rotation, umax=1.0)
+    w.steps = steps if steps is not None else int(math.ceil(t_end / w.dt()))
+    return w
+
+
 def burgers2d(n: int = 1024, p: int = 2, seed: int = 0, mode: int = MODE_WENO,
               steps: Optional[int] = None, cfl: float = 0.1,
               t_end_factor: float = 1.5, ny: Optional[int] = None) -> Workload:
