@@ -4,8 +4,9 @@
  *   J. Vedral, "Dissipative WENO stabilization of high-order discontinuous
  *   Galerkin methods for hyperbolic problems", arXiv 2309.12019.
  *
- * Problem (Sec. 2, eq. ivp): u_t + div F(u) = 0 for a scalar u on a uniform
- * Cartesian mesh of square cells (1D or 2D), with
+ * Problem (Sec. 2, eq. ivp): u_t + div F(u) = 0 for a scalar u (or, with
+ * DG_FLUX_EULER, the 1D Euler system) on a uniform Cartesian mesh of square
+ * cells (1D or 2D), with
  *   DG_FLUX_LINADV : F(u) = v(x) u,  v = (vel_x - omega (y - rot_cy),
  *                                         vel_y + omega (x - rot_cx))
  *   DG_FLUX_BURGERS: F(u) = a u^2 / 2, a = (vel_x, vel_y)
@@ -28,7 +29,7 @@
  * flux (Sec. 2), s the dissipative term of eq. (astab) with
  * nu_e = lambda_e h / (2p) (eq. visc), and gamma_e the WENO smoothness sensor
  * of eqs. (sensor)/(gensensor) (Sec. 4); it advances U with the SSP-RK3 step
- * of eq. (ssp).
+ * of eq. (ssp), or the second- or fourth-order SSP step (rk_order).
  *
  * Data layout of a state U (caller-owned device memory, FP64, contiguous):
  *   U[cell * n_loc + j], cell = ix + nx * iy (x fastest), n_loc = (p+1)^dim,
