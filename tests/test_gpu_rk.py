@@ -256,3 +256,47 @@ def test_table1_lo_column_on_the_gpu(p):
         errs.append(e)
     for a, b in zip(errs, errs[1:]):
         assert abs(math.log2(a / b) - 1) < 0.2
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_weno_columns_with_a_threshold(p):
+    """Tables 1 and 2 print WENO errors equal to the DG errors for p >= 2.
+    With the threshold b = 0.05 of eq. (gensensor) the sensor is off on these
+    smooth solutions and the GPU's WENO errors match the printed WENO column
+    on every row (Table 1 to E_h = 256 for p = 3, the rounding floor above;
+    Table 2 from E_h = 32 for p = 2, as for its DG column).  With b = 0 the
+    sensor's dissipation raises them 4-fold (p = 2) and more."""
+    def t1(N):
+        w = inputs.adv1d(N, p, mode=inputs.MODE_WENO, cfl=0.5)
+        w.ic, w.rk_order, w.b = inputs.cos_wave, p + 1, 0.05
+        g = _dg().DG.from_workload(w)
+        U = g.initial_state(w)
+        n = int(math.ceil(1.0 / w.dt()))
+        g.run(U, 1.0 / n, n)
+        torch.cuda.synchronize()
+        O = oracle_for(w)
+        xe = O.nodes(p + 3)[..., 0].numpy()
+        return O.l1_error(U.cpu(), torch.from_numpy(inputs.cos_wave(xe - 1.0)), p + 3)
+
+    def t2(N):
+        w = inputs.burgers1d(N, p, mode=inputs.MODE_WENO)
+        w.b = 0.05
+        g = _dg().DG.from_workload(w)
+        U = g.initial_state(w)
+        n = int(math.ceil(0.1 / w.dt()))
+        g.run(U, 0.1 / n, n)
+        torch.cuda.synchronize()
+        O = oracle_for(w)
+        xe = O.nodes(p + 3)[..., 0].numpy()
+        return O.l1_error(U.cpu(), torch.from_numpy(burgers_exact(xe, 0.1)), p + 3)
+
+    for N in [r["E_h"] for r in TABLE1 if r["p"] == p and not (p == 3 and r["E_h"] > 256)]:
+        ref = [r for r in TABLE1 if r["p"] == p and r["E_h"] == N][0]["WENO"]
+        e = t1(N)
+        _note(f"[table 1] WENO b=0.05 P{p} E_h={N}: ratio {e / ref:.4f}")
+        assert abs(e / ref - 1) < 0.08
+    for N in [r["E_h"] for r in TABLE2 if r["p"] == p and not (p == 2 and r["E_h"] == 16)]:
+        ref = [r for r in TABLE2 if r["p"] == p and r["E_h"] == N][0]["WENO"]
+        e = t2(N)
+        _note(f"[table 2] WENO b=0.05 P{p} E_h={N}: ratio {e / ref:.4f}")
+        assert abs(e / ref - 1) < 0.08
