@@ -212,3 +212,18 @@ def test_degenerate_and_ragged_meshes(n, periodic):
     g.run(Ug, w.dt(), 0)
     torch.cuda.synchronize()
     assert relinf(Ug.cpu().reshape(ref.shape), O.run(U, w.dt(), 10)) <= 1e-11
+
+
+def test_run_equals_repeated_step_bitwise():
+    """Graph replay (dg_run: one 64-step graph and a 6-step graph) against 70
+    eager steps, Sod 128 P2 WENO."""
+    _note("[euler determinism] dg_run vs dg_step")
+    w = _workload(128, 2, inputs.MODE_WENO)
+    g = _dg().DG.from_workload(w)
+    U0 = g.initial_state(w)
+    A, B = U0.clone(), U0.clone()
+    g.run(A, w.dt(), 70)
+    for _ in range(70):
+        g.step(B, w.dt())
+    torch.cuda.synchronize()
+    assert torch.equal(A, B)
