@@ -227,3 +227,20 @@ def test_run_equals_repeated_step_bitwise():
         g.step(B, w.dt())
     torch.cuda.synchronize()
     assert torch.equal(A, B)
+
+
+@pytest.mark.parametrize("p", [1, 3])
+def test_tile_shape_independence(p):
+    """The 64- and 256-cell tiles give bitwise the same 20 steps (600 cells:
+    ragged for both)."""
+    _note(f"[euler tiles] P{p}")
+    w = _workload(600, p, inputs.MODE_WENO)
+    out = []
+    for tx in (256, 64):
+        g = _dg().DG.from_workload(w)
+        g.set_tile(tx)
+        U = g.initial_state(w)
+        g.run(U, w.dt(), 20)
+        torch.cuda.synchronize()
+        out.append(U.cpu())
+    assert torch.equal(out[0], out[1])
