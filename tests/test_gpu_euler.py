@@ -244,3 +244,30 @@ def test_tile_shape_independence(p):
         torch.cuda.synchronize()
         out.append(U.cpu())
     assert torch.equal(out[0], out[1])
+
+
+def test_full_size_parity():
+    """The benchmark's Euler workload itself (Sod on 2^20 cells, P2, WENO,
+    the default 256-cell tiles the benchmark times): the whole-mesh
+    operator and 10 steps against the oracle, which runs this size in
+    seconds (vectorised over cells)."""
+    _note("[euler full size] Sod 2^20 cells P2 WENO")
+    w = inputs.sod1d(1 << 20, 2, steps=10)
+    O = _oracle(w)
+    U0 = O.project(w.ic)
+    g = _dg().DG.from_workload(w)
+    assert g.tile() == (256, 1)
+    Ug = g.initial_state(w)
+    torch.cuda.synchronize()
+    assert relinf(Ug.cpu().reshape(U0.shape), U0) <= 1e-13
+    ref, gref = O.rhs(U0, with_gamma=True)
+    got, gam = g.rhs(U0.reshape(w.nx, -1).cuda().contiguous(), with_gamma=True)
+    torch.cuda.synchronize()
+    assert relinf(got.cpu().reshape(ref.shape), ref) <= 1e-12
+    assert (gam.cpu() - gref).abs().max() <= 1e-12
+    U = U0.reshape(w.nx, -1).cuda().contiguous()
+    g.run(U, w.dt(), 10)
+    torch.cuda.synchronize()
+    err = relinf(U.cpu().reshape(U0.shape), O.run(U0, w.dt(), 10))
+    _note(f"    10 steps: rel Linf = {err:.3e}")
+    assert err <= 1e-11
