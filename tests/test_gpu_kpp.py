@@ -50,3 +50,23 @@ def test_kpp_128_ranges_of_the_three_schemes():
     assert got["LO"][0] >= lo0 - 1e-3 and got["LO"][1] <= hi0 + 1e-3
     pw = g["printed_range"]["WENO"]
     assert got["WENO"][0] >= pw[0] - 1e-2 and got["WENO"][1] <= pw[1] + 1e-2
+
+
+def test_papers_size_parity_20_steps():
+    """The benchmark's KPP workload (128^2, P2, WENO, lambda_e = 2): 20 steps
+    of the whole mesh (fused step kernel) against the oracle."""
+    from helpers import oracle_for, oracle_initial
+    from paper_2309_12019_amd import dgweno
+    _note("[kpp full size] 128^2 P2 WENO, 20 steps")
+    w = inputs.kpp2d(128, 2, steps=20)
+    O = oracle_for(w)
+    U0 = oracle_initial(w, O)
+    ref = O.run(U0, w.dt(), 20)
+    g = dgweno.DG.from_workload(w)
+    assert g.fused()
+    U = U0.cuda().contiguous()
+    g.run(U, w.dt(), 20)
+    torch.cuda.synchronize()
+    err = float((U.cpu() - ref).abs().max() / ref.abs().max())
+    _note(f"    rel Linf = {err:.3e}")
+    assert err <= 1e-11

@@ -151,3 +151,20 @@ def test_small_and_ragged_meshes(n, p):
     g.run(U, w.dt(), 20)
     torch.cuda.synchronize()
     assert relinf(U.cpu(), ref) <= 1e-11
+
+
+def test_papers_size_parity_20_steps():
+    """The benchmark's four-quadrant workload (128^2, P2, WENO) from t = 0:
+    20 steps of the whole mesh against the oracle."""
+    _note("[riemann full size] 128^2 P2 WENO, 20 steps")
+    w = inputs.burgers2d_riemann(128, 2, steps=20)
+    O = oracle_for(w)
+    U0 = oracle_initial(w, O)
+    ref = O.run(U0, w.dt(), 20)
+    g = _dg().DG.from_workload(w)
+    U = U0.cuda().contiguous()
+    g.run(U, w.dt(), 20)
+    torch.cuda.synchronize()
+    err = relinf(U.cpu(), ref)
+    _note(f"    rel Linf = {err:.3e}")
+    assert err <= 1e-11
