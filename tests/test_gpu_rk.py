@@ -300,3 +300,21 @@ def test_weno_columns_with_a_threshold(p):
         e = t2(N)
         _note(f"[table 2] WENO b=0.05 P{p} E_h={N}: ratio {e / ref:.4f}")
         assert abs(e / ref - 1) < 0.08
+
+
+def test_benchmark_size_parity_fourth_order():
+    """The benchmark's fourth-order workload (256^2 rotation, P3, WENO, the
+    default tiles): 10 whole-mesh steps against the oracle."""
+    _note("[rk full size] rot2d 256^2 P3 order 4, 10 steps")
+    w = inputs.rot2d(256, 3, seed=0, steps=10)
+    w.rk_order = 4
+    O = oracle_for(w)
+    U0 = oracle_initial(w, O)
+    ref = O.run(U0, w.dt(), 10)
+    g = _dg().DG.from_workload(w)
+    U = U0.cuda().contiguous()
+    g.run(U, w.dt(), 10)
+    torch.cuda.synchronize()
+    err = relinf(U.cpu(), ref)
+    _note(f"    rel Linf = {err:.3e}")
+    assert err <= 1e-11
