@@ -10,7 +10,8 @@ evaluates the same on a window of the input around the cell (radius 1 for the
 operator, 3 for the step; the window oracle is pinned against the whole-mesh
 oracle on small meshes).  Long GPU runs at full size are checked through
 properties that hold at any size: finite values, gamma in [0, 1], and cell-mean
-conservation on the periodic mesh."""
+conservation on the periodic mesh.  The headline run (256^2 P2 rotation, 200
+fused steps) is small enough for the oracle to follow whole."""
 import sys
 
 import numpy as np
@@ -144,3 +145,26 @@ def test_full_size_adjoint_at_sampled_cells():
             worst_S = max(worst_S, float((lin[e] - ref[c]).abs().max()) / sS)
     _note(f"    J^T v {worst_J:.2e}, step adjoint {worst_S:.2e}")
     assert worst_J <= 1e-11 and worst_S <= 1e-11
+
+
+def test_headline_run_against_the_oracle_whole_mesh():
+    """The headline benchmark run itself: 256^2 P2 rotation, 200 steps, the
+    library's automatic path (the fused step kernel, graph replay), compared
+    on the whole mesh with 200 oracle steps (about 40 s of host time)."""
+    _note("[full size] rot2d_256_p2: 200 fused steps vs 200 oracle steps, whole mesh")
+    w = FULL["rot2d_256_p2"]()
+    O = oracle_for(w)
+    U0 = oracle_initial(w, O)
+    g = _dg().DG.from_workload(w)
+    assert g.fused() and g.tile() == (16, 16)
+    U = U0.cuda().contiguous()
+    g.run(U, w.dt(), w.steps)
+    torch.cuda.synchronize()
+    ref = U0
+    for k in range(w.steps):
+        ref = O.step(ref, w.dt())
+        if (k + 1) % 50 == 0:
+            _note(f"    oracle step {k + 1}")
+    err = float((U.cpu() - ref).abs().max() / ref.abs().max())
+    _note(f"    rel Linf = {err:.3e}")
+    assert err <= 1e-11
