@@ -302,7 +302,7 @@ def bench_adjoint(n=512, steps=400, ndir=32, nsnaps=None, seed=0):
     return res
 
 
-STAGE_SOURCES = ("dg_kernels.hpp", "dg_tables.hpp", "dg_stage.hip")
+STAGE_SOURCES = ("dg_kernels.hpp", "dg_tables.hpp", "dg_stage.hip", "dg_euler.hpp")
 
 
 def stage_source_digest():
@@ -427,7 +427,8 @@ def main():
         ach = bpd * w.ndof / avg / 1e9
         return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": ach / HBM_PEAK_GBS, "traffic": traffic_for(args.workload),
-                "kernel": f"stage_kernel<{w.dim},{w.p},{w.flux},{w.mode}>",
+                "kernel": (f"euler_stage_kernel<{w.p},{w.mode}>" if w.flux == 3 else
+                           f"stage_kernel<{w.dim},{w.p},{w.flux},{w.mode}>"),
                 "bytes_per_dof": bpd, "avg_launch_us": avg * 1e6}
 
     if r["fused"]:
@@ -491,6 +492,7 @@ def main():
             bpo = stage_bytes_per_dof(ko)
             extra[name]["hbm_frac"] = bpo * we.ndof / (s_ / launches) / 1e9 / HBM_PEAK_GBS
             extra[name]["hbm_frac_of_measured_copy"] = bpo * we.ndof / (s_ / launches) / 1e9 / cgbs
+            extra[name]["traffic"] = traffic_for(name)
     if extra:
         line["extra"] = extra
     if not args.no_batch:

@@ -143,22 +143,26 @@ __device__ inline void euler_stage_tile(const StageArgs& A, double* lds, int ix0
     double R[3][N], lam;
     E::residual(A, lds + sc, c, gx, R, lam);
     if (A.gamma) A.gamma[gx] = gam;
-    double* dst = A.out + (size_t)gx * NLE;
-    const double* un = comb ? A.un + (size_t)gx * NLE : nullptr;
+    // all three components first, then the cell's 3 (p+1) doubles in one
+    // burst: stores spread between the components' arithmetic leave lines
+    // partly written in L2 and multiply the HBM write traffic
+    double out[NLE];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       double L[N];
       C::finish(A, c[k], gam, lam, R[k], L);
 #pragma unroll
-      for (int a = 0; a < N; ++a) {
-        double v = L[a];
-        if (!A.rhs_only) {
-          v = A.b * fma(A.dt, L[a], c[k][a]);
-          if (comb) v = fma(A.a, un[k * N + a], v);
-        }
-        dst[k * N + a] = v;
-      }
+      for (int a = 0; a < N; ++a)
+        out[k * N + a] = A.rhs_only ? L[a] : A.b * fma(A.dt, L[a], c[k][a]);
     }
+    if (comb) {
+      const double* un = A.un + (size_t)gx * NLE;
+#pragma unroll
+      for (int j = 0; j < NLE; ++j) out[j] = fma(A.a, un[j], out[j]);
+    }
+    double* dst = A.out + (size_t)gx * NLE;
+#pragma unroll
+    for (int j = 0; j < NLE; ++j) dst[j] = out[j];
   }
 }
 
