@@ -796,15 +796,25 @@ __global__ void __launch_bounds__(DIM == 2 ? TX * TY : TX) adj_grad_kernel(const
   if (!active) return;
   double Gr[NL];
   AC::grad(Ad, lds + sc, ldsv + sc, c, v, gx, gy, cell, Gr);
-  double* dst = Ad.out + cell * NL;
+  // the combination term by term over the whole cell, then one burst of
+  // stores (loads of X and Y are not held behind stores to the same cell)
+  double o[NL];
 #pragma unroll
   for (int j = 0; j < NL; ++j) {
-    double o = Ad.beta * Gr[j];
-    if (Ad.alpha != 0.0) o = fma(Ad.alpha, ldsv[j * S + sc], o);  // LDS: v is dead in registers by now
-    if (Ad.X) o = fma(Ad.g1, Ad.X[cell * NL + j], o);
-    if (Ad.Y) o = fma(Ad.g2, Ad.Y[cell * NL + j], o);
-    dst[j] = o;
+    o[j] = Ad.beta * Gr[j];
+    if (Ad.alpha != 0.0) o[j] = fma(Ad.alpha, ldsv[j * S + sc], o[j]);  // LDS: v is dead in registers by now
   }
+  if (Ad.X) {
+#pragma unroll
+    for (int j = 0; j < NL; ++j) o[j] = fma(Ad.g1, Ad.X[cell * NL + j], o[j]);
+  }
+  if (Ad.Y) {
+#pragma unroll
+    for (int j = 0; j < NL; ++j) o[j] = fma(Ad.g2, Ad.Y[cell * NL + j], o[j]);
+  }
+  double* dst = Ad.out + cell * NL;
+#pragma unroll
+  for (int j = 0; j < NL; ++j) dst[j] = o[j];
 }
 
 // Pass B of one RK stage followed by pass A of the stage before it, in one
@@ -857,16 +867,22 @@ __global__ void __launch_bounds__(DIM == 2 ? TX * TY : TX) adj_grad_sensor_kerne
   if (active) {
     double Gr[NL];
     AC::grad(Ad, lds + sc, ldsv + sc, c, v, gx, gy, cell, Gr);
-    double* dst = Ad.out + cell * NL;
 #pragma unroll
     for (int j = 0; j < NL; ++j) {
-      double oj = Ad.beta * Gr[j];
-      if (Ad.alpha != 0.0) oj = fma(Ad.alpha, ldsv[j * S + sc], oj);
-      if (Ad.X) oj = fma(Ad.g1, Ad.X[cell * NL + j], oj);
-      if (Ad.Y) oj = fma(Ad.g2, Ad.Y[cell * NL + j], oj);
-      dst[j] = oj;
-      o[j] = oj;
+      o[j] = Ad.beta * Gr[j];
+      if (Ad.alpha != 0.0) o[j] = fma(Ad.alpha, ldsv[j * S + sc], o[j]);
     }
+    if (Ad.X) {
+#pragma unroll
+      for (int j = 0; j < NL; ++j) o[j] = fma(Ad.g1, Ad.X[cell * NL + j], o[j]);
+    }
+    if (Ad.Y) {
+#pragma unroll
+      for (int j = 0; j < NL; ++j) o[j] = fma(Ad.g2, Ad.Y[cell * NL + j], o[j]);
+    }
+    double* dst = Ad.out + cell * NL;
+#pragma unroll
+    for (int j = 0; j < NL; ++j) dst[j] = o[j];
   }
   if constexpr (!early) {
     load_cell_at<DIM, NL>(A, Ad.unext, gx, gy, cn);
