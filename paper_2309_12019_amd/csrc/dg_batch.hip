@@ -13,13 +13,13 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
-#include <map>
 #include <new>
 #include <numeric>
 #include <string>
 #include <vector>
 
 #include "../../include/dgweno.h"
+#include "dg_batch_plan.hpp"
 #include "dg_launch.hpp"
 
 using dgk::BatchProblem;
@@ -55,8 +55,10 @@ struct Class {
   std::vector<int> probs;     // problem indices
   // schedule
   int tx = 0, ty = 1, grid_per_cu = 2, order = 0, branch = 0;
-  // device tables for the current schedule
+  // device tile list for the current schedule, allocated once at creation
+  // with room for the longest list any supported tile shape gives
   BatchTile* d_tiles = nullptr;
+  long long cap = 0;
   int ntiles = 0;
   double cost_us = 0.0;       // measured per-stage time (tuner)
 };
@@ -65,6 +67,7 @@ struct Class {
 
 struct dg_batch {
   std::vector<dg_mesh_desc> d;
+  std::vector<dgk::BatchMesh> mesh;  // the plan's view of each problem
   std::vector<long long> off;       // count + 1
   std::vector<StageArgs> args;      // per problem (pointers unset)
   std::vector<Class> cls;
@@ -97,53 +100,24 @@ size_t lds_bytes(int dim, int nl, int tx, int ty) {
   return sizeof(double) * (size_t)dgk::tile_lds_doubles(dim, nl, tx, dim == 2 ? ty : 1);
 }
 
-// Build the tile list of a class for its current schedule and upload it.
+// Build the tile list of a class for its current schedule and upload it into
+// the class's device list (no allocation).  Work already queued on the
+// batch's streams may still read the list, so they are drained first.
 int build_tiles(dg_batch* b, Class& c) {
-  std::vector<int> order = c.probs;
-  auto cells = [&](int i) { return (long long)b->d[i].nx * (b->d[i].dim == 2 ? b->d[i].ny : 1); };
-  if (c.order == 1)
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cells(x) < cells(y); });
-  else
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cells(x) > cells(y); });
-  std::vector<std::vector<BatchTile>> per;
-  for (int i : order) {
-    const dg_mesh_desc& d = b->d[i];
-    const int ny = d.dim == 2 ? d.ny : 1;
-    std::vector<BatchTile> t;
-    for (int y = 0; y < ny; y += (d.dim == 2 ? c.ty : 1))
-      for (int x = 0; x < d.nx; x += c.tx) t.push_back(BatchTile{i, x, y, 0});
-    per.push_back(std::move(t));
-  }
   std::vector<BatchTile> all;
-  if (c.order == 2) {  // interleave the problems' tiles round robin
-    size_t k = 0;
-    bool more = true;
-    while (more) {
-      more = false;
-      for (auto& t : per)
-        if (k < t.size()) {
-          all.push_back(t[k]);
-          more = true;
-        }
-      ++k;
-    }
-  } else {
-    for (auto& t : per) all.insert(all.end(), t.begin(), t.end());
-  }
-  if (c.d_tiles) (void)hipFree(c.d_tiles);
-  c.d_tiles = nullptr;
+  dgk::batch_tile_list(b->mesh, c.probs, c.tx, c.ty, c.order, all);
+  if ((long long)all.size() > c.cap) return bfail(DG_EINVAL, "tile list exceeds its capacity");
+  hipError_t e = hipStreamSynchronize(b->stream);
+  for (int k = 0; k < kMaxBranches && e == hipSuccess; ++k)
+    if (b->cap[k]) e = hipStreamSynchronize(b->cap[k]);
+  if (e != hipSuccess) return bfail(DG_EDEVICE, "stream synchronisation: %s", hipGetErrorString(e));
   c.ntiles = (int)all.size();
-  hipError_t e = hipMalloc(&c.d_tiles, sizeof(BatchTile) * all.size());
-  if (e != hipSuccess) return bfail(DG_ENOMEM, "tile list: %s", hipGetErrorString(e));
   e = hipMemcpy(c.d_tiles, all.data(), sizeof(BatchTile) * all.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) return bfail(DG_EDEVICE, "tile list upload: %s", hipGetErrorString(e));
   return DG_OK;
 }
 
-int class_grid(const dg_batch* b, const Class& c) {
-  const long long g = (long long)c.grid_per_cu * b->cus;
-  return (int)std::max<long long>(1, std::min<long long>(g, c.ntiles));
-}
+int class_grid(const dg_batch* b, const Class& c) { return dgk::batch_grid(c.grid_per_cu, b->cus, c.ntiles); }
 
 // one RK stage of one class: out = a*un + b*(uin + dt*L(uin)) per problem
 int class_stage(dg_batch* b, Class& c, hipStream_t st, const double* uin, const double* un, double* out, double a,
@@ -250,13 +224,13 @@ int dg_batch_create(const dg_mesh_desc* descs, int32_t count, dg_batch** out) {
   if (!b) return bfail(DG_ENOMEM, "host allocation failed");
   b->d.assign(descs, descs + count);
   b->stream = static_cast<hipStream_t>(descs[0].stream);
-  b->off.assign(count + 1, 0);
   for (int i = 0; i < count; ++i) {
     dg_mesh_desc& d = b->d[i];
     if (d.dim == 1) d.ny = 1;
-    b->off[i + 1] = b->off[i] + (long long)d.nx * d.ny * nl_of(d);
+    b->mesh.push_back(dgk::BatchMesh{d.dim, d.nx, d.ny, d.p, d.flux, d.mode});
     b->args.push_back(args_of(d));
   }
+  b->off = dgk::batch_offsets(b->mesh);
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) {
@@ -267,26 +241,20 @@ int dg_batch_create(const dg_mesh_desc* descs, int32_t count, dg_batch** out) {
     }
   }
   // classes
-  std::map<std::tuple<int, int, int, int>, int> key;
-  for (int i = 0; i < count; ++i) {
-    const dg_mesh_desc& d = b->d[i];
-    auto k = std::make_tuple(d.dim, d.p, d.flux, d.mode);
-    auto it = key.find(k);
-    if (it == key.end()) {
-      Class c;
-      c.dim = d.dim;
-      c.p = d.p;
-      c.flux = d.flux;
-      c.mode = d.mode;
-      c.nl = nl_of(d);
-      c.tx = d.dim == 1 ? 256 : 16;
-      c.ty = d.dim == 1 ? 1 : 16;
-      if (lds_bytes(c.dim, c.nl, c.tx, c.ty) > (size_t)b->max_lds) c.tx = c.ty = 8;
-      key[k] = (int)b->cls.size();
-      b->cls.push_back(c);
-      it = key.find(k);
-    }
-    b->cls[it->second].probs.push_back(i);
+  for (const auto& probs : dgk::batch_classes(b->mesh)) {
+    const dg_mesh_desc& d = b->d[probs[0]];
+    Class c;
+    c.dim = d.dim;
+    c.p = d.p;
+    c.flux = d.flux;
+    c.mode = d.mode;
+    c.nl = nl_of(d);
+    c.tx = d.dim == 1 ? 256 : 16;
+    c.ty = d.dim == 1 ? 1 : 16;
+    if (lds_bytes(c.dim, c.nl, c.tx, c.ty) > (size_t)b->max_lds) c.tx = c.ty = 8;
+    c.probs = probs;
+    c.cap = dgk::batch_tile_capacity(b->mesh, probs);
+    b->cls.push_back(c);
   }
   const size_t total = (size_t)b->off[count];
   if ((e = hipMalloc(&b->U1, total * sizeof(double))) != hipSuccess ||
@@ -294,6 +262,23 @@ int dg_batch_create(const dg_mesh_desc* descs, int32_t count, dg_batch** out) {
       (e = hipMalloc(&b->d_probs, sizeof(BatchProblem) * count)) != hipSuccess) {
     dg_batch_destroy(b);
     return bfail(DG_ENOMEM, "batch buffers: %s", hipGetErrorString(e));
+  }
+  for (auto& c : b->cls) {
+    if ((e = hipMalloc(&c.d_tiles, sizeof(BatchTile) * (size_t)c.cap)) != hipSuccess) {
+      dg_batch_destroy(b);
+      return bfail(DG_ENOMEM, "tile lists: %s", hipGetErrorString(e));
+    }
+  }
+  for (int k = 0; k < kMaxBranches; ++k) {
+    if ((e = hipStreamCreateWithFlags(&b->cap[k], hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&b->ev[k], hipEventDisableTiming)) != hipSuccess) {
+      dg_batch_destroy(b);
+      return bfail(DG_EDEVICE, "streams: %s", hipGetErrorString(e));
+    }
+  }
+  if ((e = hipEventCreateWithFlags(&b->ev[kMaxBranches], hipEventDisableTiming)) != hipSuccess) {
+    dg_batch_destroy(b);
+    return bfail(DG_EDEVICE, "events: %s", hipGetErrorString(e));
   }
   for (auto& c : b->cls) {
     // estimated cost for the initial branch assignment: DOFs of the class
@@ -306,17 +291,6 @@ int dg_batch_create(const dg_mesh_desc* descs, int32_t count, dg_batch** out) {
   }
   b->branches = std::min<int>(kMaxBranches, (int)b->cls.size());
   assign_branches(b);
-  for (int k = 0; k < kMaxBranches; ++k) {
-    if ((e = hipStreamCreateWithFlags(&b->cap[k], hipStreamNonBlocking)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&b->ev[k], hipEventDisableTiming)) != hipSuccess) {
-      dg_batch_destroy(b);
-      return bfail(DG_EDEVICE, "streams: %s", hipGetErrorString(e));
-    }
-  }
-  if ((e = hipEventCreateWithFlags(&b->ev[kMaxBranches], hipEventDisableTiming)) != hipSuccess) {
-    dg_batch_destroy(b);
-    return bfail(DG_EDEVICE, "events: %s", hipGetErrorString(e));
-  }
   *out = b;
   return DG_OK;
 }

@@ -5,7 +5,9 @@
 // kernels use; no device code is executed.
 #include <cstdio>
 #include <cstdlib>
+#include <vector>
 
+#include "../../paper_2309_12019_amd/csrc/dg_batch_plan.hpp"
 #include "../../paper_2309_12019_amd/csrc/dg_launch.hpp"
 
 using namespace dgk;
@@ -192,7 +194,145 @@ void sweep_step() {
     }
 }
 
-int main() {
+// ---------------------------------------------------------------------------
+// Batched runs: the classes, arena offsets, tile lists and persistent grids
+// of the library's plan (dg_batch_plan.hpp) for a list of problems.  For one
+// class and tile shape: every order's list holds the same tiles (each
+// problem's mesh tiled once) within the class's preallocated capacity; every
+// grid size visits each list entry exactly once; and for every tile and
+// thread of batch_stage_kernel's loop, the problem index, the LDS planes and
+// slots (own, halo and the four face-neighbour reads) and the arena entries
+// of the loaded, combined and written cells stay inside their buffers, and
+// every mesh cell of every problem is written exactly once per stage.
+// ---------------------------------------------------------------------------
+struct BatchProblemDesc {
+  BatchMesh m;
+  int per_x, per_y;
+};
+
+template <int DIM, int TX, int TY>
+void check_batch_class(const std::vector<BatchProblemDesc>& pd, const std::vector<BatchMesh>& m,
+                       const std::vector<long long>& off, const std::vector<int>& probs) {
+  using G = TileGeom<DIM, TX, TY>;
+  const int nl = m[probs[0]].nl();
+  const long long lds = tile_lds_doubles(DIM, nl, TX, TY);
+  const long long cap = batch_tile_capacity(m, probs);
+  const long long total = off.back();
+  std::vector<BatchTile> base, list;
+  batch_tile_list(m, probs, TX, TY, 0, base);
+  auto key = [](const BatchTile& t) { return ((long long)t.prob << 40) | ((long long)t.iy0 << 20) | t.ix0; };
+  std::vector<long long> kb;
+  for (auto& t : base) kb.push_back(key(t));
+  std::sort(kb.begin(), kb.end());
+  for (int order = 0; order < 3; ++order) {
+    batch_tile_list(m, probs, TX, TY, order, list);
+    CHECK((long long)list.size() <= cap, "batch: %zu tiles exceed the capacity %lld", list.size(), cap);
+    std::vector<long long> kl;
+    for (auto& t : list) kl.push_back(key(t));
+    std::sort(kl.begin(), kl.end());
+    CHECK(kl == kb, "batch: order %d lists other tiles than order 0", order);
+    for (int g : {1, 2, 4, 8, 64}) {
+      const int grid = batch_grid(g, 256, (long long)list.size());
+      CHECK(grid >= 1 && grid <= (long long)std::max<size_t>(1, list.size()), "batch: grid %d", grid);
+      std::vector<int> seen(list.size(), 0);
+      for (int b = 0; b < grid; ++b)
+        for (long long k = b; k < (long long)list.size(); k += grid) seen[k]++;
+      for (size_t k = 0; k < seen.size(); ++k) CHECK(seen[k] == 1, "batch: tile %zu visited %d times", k, seen[k]);
+    }
+  }
+  // every tile and thread of the loop (the order only permutes the tiles)
+  std::vector<unsigned char> written(total + 1, 0);
+  for (const BatchTile& tl : base) {
+    CHECK(tl.prob >= 0 && tl.prob < (int)m.size(), "batch: problem index %d", tl.prob);
+    if (tl.prob < 0 || tl.prob >= (int)m.size()) continue;
+    const BatchMesh& bm = m[tl.prob];
+    CHECK(bm.dim == DIM && bm.nl() == nl, "batch: tile of another class");
+    CHECK(tl.ix0 >= 0 && tl.ix0 < bm.nx && tl.iy0 >= 0 && tl.iy0 < bm.ny, "batch: tile origin outside the mesh");
+    StageArgs A{};
+    A.nx = bm.nx;
+    A.ny = DIM == 2 ? bm.ny : 1;
+    A.per_x = pd[tl.prob].per_x;
+    A.per_y = DIM == 2 ? pd[tl.prob].per_y : 0;
+    const long long o = off[tl.prob], ncells = bm.cells();
+    const int offs[4] = {-1, 1, -G::W, G::W};
+    for (int t = 0; t < G::NT; ++t) {
+      int sc, gx, gy, hs, hgx, hgy;
+      const bool halo = tile_slots<DIM, TX, TY>(t, tl.ix0, tl.iy0, sc, gx, gy, hs, hgx, hgy);
+      CHECK(sc >= 0 && sc < G::NS && (long long)(nl - 1) * G::S + sc < lds, "batch: own LDS slot %d", sc);
+      for (int f = 0; f < 2 * DIM; ++f)
+        CHECK(sc + offs[f] >= 0 && sc + offs[f] < G::NS && (long long)(nl - 1) * G::S + sc + offs[f] < lds,
+              "batch: neighbour LDS slot %d", sc + offs[f]);
+      size_t cell;
+      if (slot_cell<DIM>(A, gx, gy, cell))
+        CHECK((long long)cell < ncells && o + ((long long)cell + 1) * nl <= off[tl.prob + 1],
+              "batch: own load outside problem %d", tl.prob);
+      if (halo) {
+        CHECK(hs >= 0 && hs < G::NS && (long long)(nl - 1) * G::S + hs < lds, "batch: halo LDS slot %d", hs);
+        if (slot_cell<DIM>(A, hgx, hgy, cell))
+          CHECK((long long)cell < ncells && o + ((long long)cell + 1) * nl <= off[tl.prob + 1],
+                "batch: halo load outside problem %d", tl.prob);
+      }
+      if (gx < A.nx && gy < A.ny) {
+        const long long c = (long long)gy * A.nx + gx;
+        CHECK(c < ncells && o + (c + 1) * nl <= total, "batch: output outside the arena");
+        if (c < ncells) written[o + c * nl]++;
+      }
+    }
+  }
+  for (int i : probs)
+    for (long long c = 0; c < m[i].cells(); ++c)
+      CHECK(written[off[i] + c * m[i].nl()] == 1, "batch: cell %lld of problem %d written %d times", c, i,
+            written[off[i] + c * m[i].nl()]);
+}
+
+// problems: one line each, "dim nx ny p flux mode per_x per_y"
+int check_batch(const char* path) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) {
+    std::printf("cannot open %s\n", path);
+    return 1;
+  }
+  std::vector<BatchProblemDesc> pd;
+  BatchProblemDesc d{};
+  while (std::fscanf(f, "%d %d %d %d %d %d %d %d", &d.m.dim, &d.m.nx, &d.m.ny, &d.m.p, &d.m.flux, &d.m.mode,
+                     &d.per_x, &d.per_y) == 8) {
+    if (d.m.dim == 1) d.m.ny = 1;
+    pd.push_back(d);
+  }
+  std::fclose(f);
+  std::vector<BatchMesh> m;
+  for (auto& x : pd) m.push_back(x.m);
+  const std::vector<long long> off = batch_offsets(m);
+  for (size_t i = 0; i < m.size(); ++i) CHECK(off[i + 1] - off[i] == m[i].cells() * m[i].nl(), "batch: offsets");
+  const auto classes = batch_classes(m);
+  size_t members = 0;
+  for (const auto& probs : classes) {
+    members += probs.size();
+    const BatchMesh& c0 = m[probs[0]];
+    for (int i : probs)
+      CHECK(m[i].dim == c0.dim && m[i].p == c0.p && m[i].flux == c0.flux && m[i].mode == c0.mode,
+            "batch: class with mixed kernels");
+    const int nl = c0.nl();
+    if (c0.dim == 1) {
+      check_batch_class<1, 256, 1>(pd, m, off, probs);
+      check_batch_class<1, 64, 1>(pd, m, off, probs);
+    } else {
+      // the 16x16 tile where its LDS fits the 64 KB a workgroup gets by default
+      if (tile_lds_doubles(2, nl, 16, 16) * 8 <= 65536) check_batch_class<2, 16, 16>(pd, m, off, probs);
+      check_batch_class<2, 8, 8>(pd, m, off, probs);
+    }
+  }
+  CHECK(members == m.size(), "batch: %zu problems in classes, %zu given", members, m.size());
+  std::printf("batch: %zu problems, %zu classes, %lld doubles\n", m.size(), classes.size(), off.back());
+  return 0;
+}
+
+int main(int argc, char** argv) {
+  if (argc > 1) {
+    if (check_batch(argv[1])) return 1;
+    std::printf("%s (%d failures)\n", failures ? "FAIL" : "ok", failures);
+    return failures ? 1 : 0;
+  }
   check_split<2, kStepTile2D, kStepTile2D, 2>();
   check_split<2, kStepTile2D, kStepTile2D, 1>();
   check_split<2, kStepTile2D, kStepTile2D, 0>();
