@@ -247,6 +247,39 @@ class FourierModes:
         return 1.0 / float(np.max(-du))
 
 
+class ShockedFourier:
+    """The Fourier data of FourierModes plus seeded jumps: four periodic
+    square waves sq(n_m . x - c_m) (1 on the first half of each period, 0 on
+    the second), n_m integer vectors with 1 <= |n_m|_inf <= 3, c_m ~ U[0, 1),
+    heights ~ U[-1, 1] times the Fourier bound.  A periodic state with
+    discontinuities along straight lines in several directions: where the
+    state drops along (1, 1) they are shocks of the 2D Burgers flux, where it
+    rises rarefactions, so a few steps from it have the structure of a state
+    past the shock time."""
+
+    def __init__(self, seed: int, njumps: int = 4):
+        self.fm = FourierModes(seed)
+        rng = np.random.default_rng(seed + 7919)
+        self.n = []
+        while len(self.n) < njumps:
+            v = rng.integers(-3, 4, size=2)
+            if v.any():
+                self.n.append(v.astype(np.float64))
+        self.c = rng.uniform(0.0, 1.0, size=njumps)
+        self.h = rng.uniform(-1.0, 1.0, size=njumps) * self.fm.bound()
+
+    def __call__(self, x, y):
+        o = _Ops(x)
+        u = self.fm(x, y)
+        for (nx, ny), c, h in zip(self.n, self.c, self.h):
+            s = nx * x + ny * y - c
+            u = u + h * o.fl((s - o.m.floor(s)) < 0.5)
+        return u
+
+    def bound(self) -> float:
+        return self.fm.bound() + float(np.abs(self.h).sum())
+
+
 # ---------------------------------------------------------------------------
 # the benchmark workloads
 # ---------------------------------------------------------------------------
@@ -317,6 +350,15 @@ def burgers2d(n: int = 1024, p: int = 2, seed: int = 0, mode: int = MODE_WENO,
         steps = int(math.ceil(t_end_factor * fm.shock_time() / w.dt()))
     w.steps = steps
     return w
+
+
+def burgers2d_shocked(n: int = 1024, p: int = 2, seed: int = 0, mode: int = MODE_WENO,
+                      steps: int = 100, cfl: float = 0.1) -> Workload:
+    """2D Burgers as burgers2d, from the ShockedFourier state (the Fourier
+    data with seeded jumps): a state with shocks at t = 0."""
+    sf = ShockedFourier(seed)
+    return Workload(name=f"burgers2d_shocked_{n}_p{p}_s{seed}", dim=2, nx=n, ny=n, p=p, flux=BURGERS,
+                    vx=1.0, vy=1.0, mode=mode, cfl=cfl, ic=sf, umax=sf.bound(), steps=steps)
 
 
 def batch_mix(seed: int = 0, count: int = 512, steps: int = 100) -> List[Workload]:

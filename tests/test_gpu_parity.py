@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 import torch
 
-from helpers import oracle_for, oracle_initial, oracle_problem
+from helpers import oracle_for, oracle_initial, oracle_problem, run_bar
 from paper_2309_12019_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -90,19 +90,9 @@ def test_projection_parity(kind, p):
     assert relinf(Ug.cpu(), Uo) <= 1e-13
 
 
-def self_divergence(O, U0, dt, steps, seed=0):
-    """Spread of the oracle against itself when its input is perturbed by about
-    one unit in the last place: the conditioning floor of the discrete map."""
-    rng = np.random.default_rng(seed)
-    U1 = U0 * (1 + 2.2e-16 * torch.from_numpy(rng.standard_normal(U0.shape)))
-    return relinf(O.run(U1, dt, steps), O.run(U0, dt, steps))
-
-
 def _run_parity(w, U0, steps, tol=1e-11, O=None):
-    """100-step parity.  Bar: 1e-11 relative L-inf, or 10x the oracle's own
-    one-ulp spread where the sensor map amplifies rounding beyond that (p = 4:
-    there ||U - U*|| is ~1e-10 ||U|| on smooth data, so c - c* cancels ~6
-    digits and gamma = sqrt(.)/den has a derivative ~ 1/||U - U*||)."""
+    """100-step parity at the bar of helpers.run_bar (1e-11 relative L-inf;
+    for p = 4 WENO 10x the oracle's own one-ulp spread where larger, capped)."""
     O = O or oracle_for(w)
     ref = O.run(U0, w.dt(), steps)
     g = _dg().DG.from_workload(w)
@@ -110,10 +100,9 @@ def _run_parity(w, U0, steps, tol=1e-11, O=None):
     g.run(U, w.dt(), steps)
     torch.cuda.synchronize()
     err = relinf(U.cpu(), ref)
-    bar = tol
-    if w.p == 4 and w.mode == inputs.MODE_WENO:
-        spread = self_divergence(O, U0, w.dt(), steps)
-        bar = max(tol, 10 * spread)
+    bar, spread = run_bar(w, lambda V: O.run(V, w.dt(), steps), U0)
+    bar = max(bar, tol)
+    if spread is not None:
         _note(f"    oracle one-ulp spread = {spread:.3e}")
     _note(f"    rel Linf after {steps} steps = {err:.3e} (bar {bar:.1e})")
     assert err <= bar
