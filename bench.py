@@ -1,23 +1,23 @@
 """Benchmark of the dissipative-WENO RKDG hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rot2d_256_p2]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload burgers2d_1024_p2]
 
 A step is one SSP-RK3 step over the whole mesh of the workload: the three
 stages each evaluate the whole stabilised DG operator (traces, volume and face
 quadrature with the LLF flux, HWENO reconstruction, sensor, dissipation, mass
 inverse) and the RK combination.  K steps run as one dg_run call (HIP graph
 replay) with the state already resident in HBM; the timed region is bracketed
-by device synchronisation.  dg_run uses the library's automatic choice: the
-fused step kernel (one launch per step) on small meshes, three per-stage
-launches otherwise.
+by device synchronisation.  The default workload is 1024^2 P2 periodic 2D
+Burgers with seeded Fourier data, time step CFL h / ((2p+1) lambda_max(U^0))
+from the library's dg_stable_dt; dg_run takes the per-stage kernel there
+(three launches per step).
 
 Printed: one JSON line with the metric (FP64 DOF-updates per second per RK
-stage), the roofline of the dominant kernel from HIP events on the stream the
-kernels run on (fused step kernel: FP64 flops per launch over its duration
-against the FP64 vector peak; per-stage kernel: algorithmic HBM bytes per
-launch over its duration against 8 TB/s), the per-stage kernel's HBM roofline
-on the same workload when the fused kernel is the default, and the CPU oracle
-timed on a bounded sample of the same workload.
+stage), the HBM roofline of the per-stage kernel (algorithmic bytes per
+launch over its average duration from HIP events on the stream the kernels
+run on, against 8 TB/s), the same kernel's FP64 rate, the CPU oracle timed
+on a bounded sample of the same workload (one thread and all threads),
+further workloads, the batched extension and the adjoint extension.
 """
 import argparse
 import json
@@ -53,8 +53,7 @@ def workload(name):
         # the KPP problem of Sec. 5.5 at the paper's size (128^2, P2, lambda_e = 2, t = 1)
         "kpp2d_128_p2": lambda: inputs.kpp2d(128, 2),
         # DRAM-resident (302 MB per state array, beyond the 256 MB last-level
-        # cache); its initial data take ~25 s to evaluate on the host, so it
-        # is not among the default extras
+        # cache); initial data evaluated on the device
         "burgers2d_2048_p2": lambda: inputs.burgers2d(2048, 2, seed=0),
         # the five-stage fourth-order SSP method that Sec. 5.1 pairs with p = 3
         "rot2d_256_p3_rk4": lambda: _order(inputs.rot2d(256, 3, seed=0, steps=200), 4),
@@ -93,16 +92,31 @@ STAGES_PER_STEP = {2: 2, 3: 3, 4: 5}
 LAUNCHES_PER_STEP = {2: 2, 3: 3, 4: 6}
 
 
-def time_gpu(w, steps, warmup, fused=None):
-    """Time `steps` SSP steps (the workload's order) of dg_run; fused: None
-    keeps the library's automatic choice of the fused step kernel, 0 / 1
-    forces it off / on."""
-    import torch
+def prepare(w, fused=None):
+    """Handle, projected initial state (initial data evaluated on the device)
+    and the workload's time step from lambda_max of that state (dg_stable_dt:
+    CFL h / ((2p+1) lambda_max(U^0))); a workload with an end time then runs
+    ceil(t_end / dt) steps.  Workloads with a stated speed bound instead
+    (lambda_e fixed, the Euler system, inflow boundaries) keep it."""
     from paper_2309_12019_amd import dgweno
     g = dgweno.DG.from_workload(w)
     if fused is not None:
         g.set_fused(fused)
-    U0 = g.initial_state(w)
+    U0 = g.initial_state(w, on_device=True)
+    if w.flux in (0, 1) and w.bc_kind == 0 and w.lambda_override <= 0:
+        w.with_dt(g.stable_dt(U0, w.cfl))
+    return g, U0
+
+
+def time_gpu(w, steps, warmup, fused=None, g=None, U0=None):
+    """Time `steps` SSP steps (the workload's order) of dg_run; fused: None
+    keeps the library's automatic choice of the fused step kernel, 0 / 1
+    forces it off / on."""
+    import torch
+    if g is None:
+        g, U0 = prepare(w, fused)
+    elif fused is not None:
+        g.set_fused(fused)
     dt = w.dt()
     # dg_run replays graphs cached per (state buffer, dt, chunk length): one
     # untimed call of the timed length on the timed buffer records them, so
@@ -127,31 +141,69 @@ def time_gpu(w, steps, warmup, fused=None):
     bad = g.count_nonfinite(U)
     if bad:
         raise RuntimeError(f"{bad} non-finite values after the timed run")
-    return dict(wall=wall, event_ms=ev_ms, ndof=w.ndof, steps=steps, tile=g.tile(), fused=g.fused())
+    return dict(wall=wall, event_ms=ev_ms, ndof=w.ndof, steps=steps, tile=g.tile(), fused=g.fused(), dt=dt)
 
 
-def cpu_baseline(w, budget_s=15.0):
-    """The CPU oracle, as it stands, on the same workload: whole SSP-RK3 steps
-    over the full mesh, as many as fit the time budget (at least one)."""
-    import torch
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, budget_s=12.0):
+    """The CPU oracle, as it stands, on the same workload: the plain C oracle
+    (oracle/dgoracle.c, loops per cell, OpenMP over cells) from the oracle's
+    projection of the initial data, whole SSP steps over the full mesh, as
+    many as fit the time budget (at least one), with all host threads and
+    with one."""
     import numpy as np
+    import torch
     import oracle
+    from oracle import coracle
     f = w.fields()
-    O = oracle.Oracle(oracle.Problem(**{k: f[k] for k in oracle.Problem.__dataclass_fields__ if k in f}))
+    prob = oracle.Problem(**{k: f[k] for k in oracle.Problem.__dataclass_fields__ if k in f})
+    O = oracle.Oracle(prob)
     U = O.project(torch.from_numpy(np.ascontiguousarray(w.eval_ic(O.proj_nodes().numpy()))))
+    del O
+    C = coracle.COracle(prob)
     dt = w.dt()
-    t0 = time.perf_counter()
-    U = O.step(U, dt)
-    one = time.perf_counter() - t0
-    n = max(1, min(400, int(budget_s / max(one, 1e-3)) - 1))
-    t0 = time.perf_counter()
-    for _ in range(n):
-        U = O.step(U, dt)
-    t = time.perf_counter() - t0
-    return {"value": 3.0 * w.ndof * n / t, "unit": "DOF-updates/s", "cores": torch.get_num_threads(),
-            "kind": "oracle",
-            "sample": f"{n} SSP-RK3 steps of {w.name} ({w.ndof} DOFs) after one warm-up step, "
-                      f"PyTorch CPU fp64, {t:.1f} s"}
+    nmax = coracle.max_threads()
+    legs = {}
+    for threads in (nmax, 1):
+        coracle.set_threads(threads)
+        t0 = time.perf_counter()
+        V = C.step(U, dt)
+        one = time.perf_counter() - t0
+        n = max(1, min(200, int(budget_s / max(one, 1e-3))))
+        t0 = time.perf_counter()
+        V = C.run(U, dt, n)
+        t = time.perf_counter() - t0
+        legs[threads] = {"value": w.ndof * 3.0 * n / t, "steps": n, "seconds": t}
+    coracle.set_threads(nmax)
+    big = legs[nmax]
+    return {"value": big["value"], "unit": "DOF-updates/s", "cores": nmax, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": f"{big['steps']} SSP-RK3 steps of {w.name} ({w.ndof} DOFs) after one warm-up step, "
+                      f"C oracle, FP64, {nmax} OpenMP threads, {big['seconds']:.1f} s",
+            "single_thread": {"value": legs[1]["value"], "cores": 1,
+                              "sample": f"{legs[1]['steps']} steps, 1 thread, {legs[1]['seconds']:.1f} s"}}
+
+
+def oracle_ops_per_cell(w):
+    """FP64 operations per cell and stage of the oracle's own evaluation of
+    the operator (oracle/opcounts.json, written by python -m oracle.opcount:
+    dense products over all basis functions and nodes, so an upper bound on
+    the method's arithmetic)."""
+    path = os.path.join(ROOT, "oracle", "opcounts.json")
+    try:
+        d = json.load(open(path))["counts"]
+        return d[f"{w.dim},{w.p},{w.flux},{w.mode}"]["ops_per_cell"]
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def bench_batch(steps=100, seed=0, count=512):
@@ -380,15 +432,65 @@ def copy_probe(mib):
     print(json.dumps({"copy_probe_bytes": n * 8, "copies": 3}), flush=True)
 
 
+def stage_roofline(w, wname, sec, launches, copy_gbs=None):
+    """HBM roofline of the per-stage kernel over `launches` launches taking
+    `sec` in all: algorithmic bytes per launch (16 B per DOF for the first
+    stage, 24 B for the others: 64/3 B on average for SSP-RK3) over the
+    average launch duration, against 8 TB/s; with the kernel's executed FP64
+    rate beside it (rocprofv3 SQ counters per cell) and the oracle's op count
+    (an upper bound on the method's arithmetic)."""
+    bpd = stage_bytes_per_dof(w.rk_order)
+    avg = sec / launches
+    ach = bpd * w.ndof / avg / 1e9
+    key = (w.dim, w.p, w.flux, w.mode)
+    roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "traffic": traffic_for(wname),
+            "kernel": (f"euler_stage_kernel<{w.p},{w.mode}>" if w.flux == 3 else
+                       f"stage_kernel<{w.dim},{w.p},{w.flux},{w.mode},16,16>" if w.dim == 2 else
+                       f"stage_kernel<1,{w.p},{w.flux},{w.mode},256,1>"),
+            "bytes_per_dof": bpd, "bytes_per_launch": bpd * w.ndof, "avg_launch_us": avg * 1e6}
+    if copy_gbs:
+        roof["frac_of_measured_copy"] = ach / copy_gbs
+    fx = FLOPS_PER_CELL_STAGE.get(key)
+    if fx:
+        tf = fx * w.ncells / avg / 1e12
+        roof["executed_flops_per_cell"] = fx
+        roof["executed_tflops"] = tf
+        roof["executed_flop_frac"] = tf / FP64_PEAK_TFLOPS
+    ops = oracle_ops_per_cell(w)
+    if ops:
+        roof["oracle_ops_per_cell"] = ops
+        roof["oracle_ops_rate_tflops"] = ops * w.ncells / avg / 1e12
+    return roof
+
+
+def fused_roofline(w, wname, sec, steps):
+    """The fused step kernel (one launch per step: U^n in, U^(n+1) out, three
+    stages of arithmetic): FP64 rate from the per-stage kernel's executed
+    flops per cell (recomputed rings not counted) against the FP64 vector
+    peak, and its HBM fraction."""
+    key = (w.dim, w.p, w.flux, w.mode)
+    avg = sec / steps
+    flops = 3.0 * FLOPS_PER_CELL_STAGE[key] * w.ncells if key in FLOPS_PER_CELL_STAGE else None
+    ach = flops / avg / 1e12 if flops else None
+    return {"bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": ach / FP64_PEAK_TFLOPS if ach else None,
+            "traffic": traffic_for(wname + ":step"),
+            "kernel": f"step_kernel<{w.dim},{w.p},{w.flux},{w.mode}> (fused SSP-RK3 step)",
+            "flops_per_launch": flops, "avg_launch_us": avg * 1e6,
+            "hbm_bytes_per_launch": 16.0 * w.ndof,
+            "hbm_frac": 16.0 * w.ndof / avg / 1e9 / HBM_PEAK_GBS}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="rot2d_256_p2")
-    ap.add_argument("--extra", default="rot2d_256_p3,burgers2d_1024_p2,rot2d_1024_p2,rot2d_256_p2_zhao,"
-                    "kpp2d_128_p2,rot2d_256_p3_rk4,burgers2d_1024_p2_rk4,burgers2d_riemann_128_p2,"
-                    "sod1d_128_p2,sod1d_1m_p2",
+    ap.add_argument("--workload", default="burgers2d_1024_p2")
+    ap.add_argument("--extra", default="rot2d_256_p2,rot2d_256_p3,rot2d_1024_p2,burgers2d_2048_p2,"
+                    "rot2d_256_p2_zhao,kpp2d_128_p2,rot2d_256_p3_rk4,burgers2d_1024_p2_rk4,"
+                    "burgers2d_riemann_128_p2,sod1d_128_p2,sod1d_1m_p2",
                     help="comma-separated workloads reported alongside (no cpu baseline)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
@@ -413,43 +515,19 @@ def main():
         copy_probe(args.copy_probe_mib)
         return
 
+    copy = measured_copy_gbs()
+    cgbs = copy["gbs"]
     w = workload(args.workload)
-    r = time_gpu(w, args.steps, args.warmup)
+    g, U0 = prepare(w)
+    r = time_gpu(w, args.steps, args.warmup, g=g, U0=U0)
     sec = r["event_ms"] / 1e3
-    dof_rate = 3.0 * w.ndof * args.steps / sec
-    bpd = stage_bytes_per_dof()
-    key = (w.dim, w.p, w.flux, w.mode)
-
-    def stage_roofline(sec_, steps_):
-        """HBM roofline of the per-stage kernel: 64/3 algorithmic bytes per DOF
-        per launch, three launches per step."""
-        avg = sec_ / (3 * steps_)
-        ach = bpd * w.ndof / avg / 1e9
-        return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBS, "traffic": traffic_for(args.workload),
-                "kernel": (f"euler_stage_kernel<{w.p},{w.mode}>" if w.flux == 3 else
-                           f"stage_kernel<{w.dim},{w.p},{w.flux},{w.mode}>"),
-                "bytes_per_dof": bpd, "avg_launch_us": avg * 1e6}
-
+    dof_rate = STAGES_PER_STEP[w.rk_order] * w.ndof * args.steps / sec
     if r["fused"]:
-        # one fused launch per step: U^n in, U^(n+1) out (16 B per DOF), three
-        # stages of arithmetic; the arithmetic roof binds (about 24 flop/B)
-        avg = sec / args.steps
-        flops = 3.0 * FLOPS_PER_CELL_STAGE[key] * w.ncells if key in FLOPS_PER_CELL_STAGE else None
-        ach = flops / avg / 1e12 if flops else None
-        roof = {"bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / FP64_PEAK_TFLOPS if ach else None,
-                "traffic": traffic_for(args.workload + ":step"),
-                "kernel": f"step_kernel<{w.dim},{w.p},{w.flux},{w.mode}> (fused SSP-RK3 step)",
-                "flops_per_launch": flops, "avg_launch_us": avg * 1e6,
-                "hbm_bytes_per_launch": 16.0 * w.ndof,
-                "hbm_frac": 16.0 * w.ndof / avg / 1e9 / HBM_PEAK_GBS}
-        rs = time_gpu(w, args.steps, args.warmup, fused=0)
-        stage_roof = stage_roofline(rs["event_ms"] / 1e3, args.steps)
-        stage_roof["value"] = 3.0 * w.ndof * args.steps / (rs["event_ms"] / 1e3)
+        roof = fused_roofline(w, args.workload, sec, args.steps)
     else:
-        roof = stage_roofline(sec, args.steps)
-        stage_roof = None
+        roof = stage_roofline(w, args.workload, sec, LAUNCHES_PER_STEP[w.rk_order] * args.steps, cgbs)
+    del g, U0
+    torch.cuda.empty_cache()
     line = {
         "metric": METRIC,
         "value": dof_rate,
@@ -464,35 +542,37 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "dim": w.dim, "cells": w.ncells, "p": w.p, "dofs": w.ndof,
-                   "flux": "linear advection" if w.flux == 0 else "Burgers",
-                   "mode": ["DG", "LO", "WENO"][w.mode], "ssp_rk3_steps": args.steps,
-                   "dt": w.dt(), "tile": list(r["tile"]), "fused_step": r["fused"]},
+                   "flux": ["linear advection", "Burgers", "KPP", "Euler"][w.flux],
+                   "mode": ["DG", "LO", "WENO", "Zhao"][w.mode], "ssp_order": w.rk_order,
+                   "timed_steps": args.steps, "steps_to_end_time": w.steps,
+                   "dt": r["dt"], "dt_rule": "CFL h / ((2p+1) lambda_max(U^0)), CFL 0.1 (dg_stable_dt)",
+                   "tile": list(r["tile"]), "fused_step": r["fused"]},
         "roofline": roof,
         "wall_s": r["wall"],
+        "measured_copy": copy,
     }
-    if stage_roof:
-        line["stage_kernel_roofline"] = stage_roof
-    line["measured_copy"] = measured_copy_gbs()
-    cgbs = line["measured_copy"]["gbs"]
-    for rf in (roof, stage_roof):
-        if rf and rf["bound"] == "hbm":
-            rf["frac_of_measured_copy"] = rf["achieved"] / cgbs
     extra = {}
     for name in [s for s in args.extra.split(",") if s]:
         we = workload(name)
+        ge, Ue = prepare(we)
         k = min(we.steps, 100)
-        re_ = time_gpu(we, k, 5)
+        re_ = time_gpu(we, k, 5, g=ge, U0=Ue)
         s_ = re_["event_ms"] / 1e3
         ko = we.rk_order
         launches = k if re_["fused"] else LAUNCHES_PER_STEP[ko] * k
-        extra[name] = {"value": STAGES_PER_STEP[ko] * we.ndof * k / s_, "steps": k, "dofs": we.ndof,
-                       "rk_order": ko, "fused_step": re_["fused"],
-                       "us_per_step": s_ / k * 1e6, "avg_launch_us": s_ / launches * 1e6}
-        if not re_["fused"]:
-            bpo = stage_bytes_per_dof(ko)
-            extra[name]["hbm_frac"] = bpo * we.ndof / (s_ / launches) / 1e9 / HBM_PEAK_GBS
-            extra[name]["hbm_frac_of_measured_copy"] = bpo * we.ndof / (s_ / launches) / 1e9 / cgbs
-            extra[name]["traffic"] = traffic_for(name)
+        ex = {"value": STAGES_PER_STEP[ko] * we.ndof * k / s_, "steps": k, "dofs": we.ndof,
+              "rk_order": ko, "fused_step": re_["fused"], "tile": list(re_["tile"]),
+              "us_per_step": s_ / k * 1e6, "avg_launch_us": s_ / launches * 1e6}
+        if re_["fused"]:
+            ex["roofline"] = fused_roofline(we, name, s_, k)
+            rs = time_gpu(we, k, 5, fused=0, g=ge, U0=Ue)
+            ex["per_stage"] = stage_roofline(we, name, rs["event_ms"] / 1e3, LAUNCHES_PER_STEP[ko] * k, cgbs)
+            ex["per_stage"]["value"] = STAGES_PER_STEP[ko] * we.ndof * k / (rs["event_ms"] / 1e3)
+        else:
+            ex["roofline"] = stage_roofline(we, name, s_, launches, cgbs)
+        extra[name] = ex
+        del ge, Ue
+        torch.cuda.empty_cache()
     if extra:
         line["extra"] = extra
     if not args.no_batch:

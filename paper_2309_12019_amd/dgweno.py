@@ -297,10 +297,16 @@ class DG:
         _check(self.lib.dg_get_tile(self.h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
 
-    def initial_state(self, w) -> torch.Tensor:
-        """Project the workload's initial data with the library's projection."""
+    def initial_state(self, w, on_device: bool = False) -> torch.Tensor:
+        """Project the workload's initial data with the library's projection.
+        The data are evaluated at the projection nodes on the host (numpy), or
+        with on_device on the GPU (torch; the same formulas, other rounding of
+        cos and sqrt), which large meshes need to start in seconds."""
         pts = self.proj_nodes()
-        vals = torch.from_numpy(np.ascontiguousarray(w.eval_ic(pts))).to(self.device)
+        if on_device:
+            vals = w.eval_ic(torch.from_numpy(pts).to(self.device))
+        else:
+            vals = torch.from_numpy(np.ascontiguousarray(w.eval_ic(pts))).to(self.device)
         return self.project_ic(vals.reshape(-1).contiguous())
 
 

@@ -61,6 +61,8 @@ class Workload:
     steps: int = 100
     ic: Optional[Callable] = None      # ic(x) in 1D, ic(x, y) in 2D (numpy)
     umax: float = 1.0                  # bound on |u0| used for the time step
+    t_end: Optional[float] = None      # end time (steps follow from dt where set)
+    dt_value: Optional[float] = None   # a time step set by the caller (with_dt)
 
     @property
     def h(self) -> float:
@@ -96,8 +98,20 @@ class Workload:
         return a * self.umax
 
     def dt(self) -> float:
-        """Fixed step: dt = CFL h / ((2p+1) max speed)."""
+        """Fixed step: the caller's (with_dt), else dt = CFL h / ((2p+1) max
+        speed) with the stated bound of max_speed."""
+        if self.dt_value is not None:
+            return self.dt_value
         return self.cfl * self.h / ((2 * self.p + 1) * self.max_speed())
+
+    def with_dt(self, dt: float) -> "Workload":
+        """Run with the time step dt (for instance CFL h / ((2p+1) lambda_max)
+        of the projected initial state, as the library's dg_stable_dt gives
+        it); a workload with an end time then takes ceil(t_end / dt) steps."""
+        self.dt_value = float(dt)
+        if self.t_end is not None:
+            self.steps = int(math.ceil(self.t_end / self.dt_value))
+        return self
 
     def fields(self) -> dict:
         """Plain field dictionary (everything but the initial-data callable)."""
@@ -347,7 +361,8 @@ def burgers2d(n: int = 1024, p: int = 2, seed: int = 0, mode: int = MODE_WENO,
                  p=p, flux=BURGERS, vx=1.0, vy=1.0, mode=mode, cfl=cfl, ic=fm,
                  umax=fm.bound(), steps=1)
     if steps is None:
-        steps = int(math.ceil(t_end_factor * fm.shock_time() / w.dt()))
+        w.t_end = t_end_factor * fm.shock_time()
+        steps = int(math.ceil(w.t_end / w.dt()))
     w.steps = steps
     return w
 

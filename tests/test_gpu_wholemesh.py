@@ -15,8 +15,9 @@ against the plain C oracle (oracle/dgoracle.c, pinned in test_oracle_c.py).
 * A batch whose members include 2D degree-4 problems, a 512^2 rotation and
   4096-cell 1D problems, 100 steps, every member against the oracle, on the
   tuned and on the one-wave (8x8) schedule.
-Bar: relative L-inf <= 1e-11 (for p = 4 WENO the capped bar of
-helpers.run_bar).
+Bar: relative L-inf <= 1e-11; for p = 4 WENO and the 200-step P3 run, 10x
+the oracle's own one-ulp spread where that is larger, capped at
+helpers.SPREAD_CAP (helpers.run_bar).
 """
 import sys
 import time
@@ -25,7 +26,7 @@ import numpy as np
 import pytest
 import torch
 
-from helpers import oracle_for, oracle_initial, oracle_problem, run_bar
+from helpers import SPREAD_CAP, oracle_for, oracle_initial, oracle_problem, run_bar
 from oracle import coracle
 from paper_2309_12019_amd import inputs
 
@@ -49,11 +50,10 @@ def relinf(a, b):
 def _compare(w, got, run, U0, label):
     ref = run(U0)
     err = relinf(got, ref)
-    bar, spread = run_bar(w, run, U0)
+    bar, spread = run_bar(w, run, U0, ref=ref)
     extra = f", oracle one-ulp spread {spread:.2e}" if spread is not None else ""
     _note(f"    {label}: rel Linf {err:.3e} (bar {bar:.1e}{extra})")
-    assert err <= bar, label
-    return err
+    return err, bar
 
 
 def test_burgers_1024_p2_shocked_state_100_steps_whole_mesh():
@@ -72,7 +72,9 @@ def test_burgers_1024_p2_shocked_state_100_steps_whole_mesh():
     C = coracle.COracle(oracle_problem(w))
     _, gam = C.rhs(U0, with_gamma=True)
     _note(f"    cells with gamma > 0.1 at the start: {int((gam > 0.1).sum())}")
-    _compare(w, U.cpu(), lambda V: C.run(V, w.dt(), 100), U0, "1024^2 P2 Burgers, shocked state, 100 steps")
+    err, bar = _compare(w, U.cpu(), lambda V: C.run(V, w.dt(), 100), U0,
+                        "1024^2 P2 Burgers, shocked state, 100 steps")
+    assert err <= bar <= SPREAD_CAP
 
 
 def test_burgers_1024_p2_post_shock_100_steps_whole_mesh():
@@ -96,20 +98,27 @@ def test_burgers_1024_p2_post_shock_100_steps_whole_mesh():
     torch.cuda.synchronize()
     C = coracle.COracle(oracle_problem(w))
     t0 = time.time()
-    _compare(w, U.cpu(), lambda V: C.run(V, w.dt(), 100), Us, "1024^2 P2 Burgers, 100 post-shock steps")
+    err, bar = _compare(w, U.cpu(), lambda V: C.run(V, w.dt(), 100), Us, "1024^2 P2 Burgers, 100 post-shock steps")
+    assert err <= bar <= SPREAD_CAP
     _note(f"    (oracle {time.time() - t0:.0f} s on {coracle.max_threads()} threads)")
 
 
 def test_rotation_256_p3_200_steps_whole_mesh():
     """256^2 P3 solid-body rotation (hump + slotted cylinder, seed 0) over its
     200 steps: the library's automatic path (the fused step kernel at this
-    size) and the per-stage kernel, both against 200 oracle steps."""
+    size) and the per-stage kernel, both against 200 oracle steps.  Over 200
+    steps the oracle's own one-ulp spread (1-2e-10) exceeds 1e-11: the
+    capped spread bar applies."""
     w = inputs.rot2d(256, 3, seed=0, steps=200)
     _note("[whole mesh] rot2d 256^2 P3: 200 steps, fused and per-stage paths")
     O = oracle_for(w)
     U0 = oracle_initial(w, O)
     C = coracle.COracle(oracle_problem(w))
-    ref = C.run(U0, w.dt(), w.steps)
+    run = lambda V: C.run(V, w.dt(), w.steps)  # noqa: E731
+    ref = run(U0)
+    bar, spread = run_bar(w, run, U0, measure=True, ref=ref)
+    _note(f"    oracle one-ulp spread {spread:.2e}, bar {bar:.1e}")
+    errs = []
     for fused in (None, 0):
         g = _dg().DG.from_workload(w)
         if fused is not None:
@@ -119,7 +128,8 @@ def test_rotation_256_p3_200_steps_whole_mesh():
         torch.cuda.synchronize()
         err = relinf(U.cpu(), ref)
         _note(f"    {'fused' if g.fused() else 'per-stage'}: rel Linf {err:.3e}")
-        assert err <= 1e-11
+        errs.append(err)
+    assert max(errs) <= bar <= SPREAD_CAP
 
 
 @pytest.mark.parametrize("kind", ["rot2d", "burgers2d"])
@@ -145,7 +155,8 @@ def test_2d_p4_100_steps(kind, tile):
     U = U0.cuda().contiguous()
     g.run(U, w.dt(), 100)
     torch.cuda.synchronize()
-    _compare(w, U.cpu(), lambda V: O.run(V, w.dt(), 100), U0, f"{kind} P4 {tile[0]}x{tile[1]}")
+    err, bar = _compare(w, U.cpu(), lambda V: O.run(V, w.dt(), 100), U0, f"{kind} P4 {tile[0]}x{tile[1]}")
+    assert err <= bar <= SPREAD_CAP
 
 
 def _batch_members():
@@ -191,6 +202,9 @@ def test_batch_members_against_the_oracle_100_steps(schedule):
                 B.set_schedule(c, 8, 8, 4, 2)
     B.run(arena, dts, 100)
     torch.cuda.synchronize()
+    res = []
     for w, v, U0 in zip(ws, B.views(arena), U0s):
         C = coracle.COracle(oracle_problem(w))
-        _compare(w, v.cpu(), lambda V: C.run(V, w.dt(), 100), U0, w.name)
+        res.append(_compare(w, v.cpu(), lambda V: C.run(V, w.dt(), 100), U0, w.name))
+    for w, (err, bar) in zip(ws, res):
+        assert err <= bar <= SPREAD_CAP, w.name
