@@ -167,6 +167,21 @@ int dg_rhs(dg_ctx* ctx, const double* U, double* dUdt, double* gamma);
  * finite and > 0. */
 int dg_step(dg_ctx* ctx, double* U, double dt);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): one SSP step of the
+ * descriptor's order, as dg_step, without a context.  desc is validated as
+ * for dg_init_mesh; work is queued on desc->stream; t is the time of U (it
+ * enters through bc_kind RIEMANN only).  The stage states live in a static
+ * device array of the library (three buffers of 2^20 doubles, 24 MiB, held
+ * on every device the library runs on until the process ends); nothing is
+ * allocated.  Every call on a device shares that device's array: calls that
+ * overlap on one device (other streams, other threads) race.  The stage
+ * kernels are dg_step's per-stage kernels, so results equal dg_step's bit
+ * for bit.  Errors: DG_EINVAL for a bad descriptor, U NULL, dt not finite
+ * and > 0, t not finite, or n_cells * n_loc above 2^20 (checked before any
+ * device call); DG_EDEVICE. */
+int dg_step_static(const dg_mesh_desc* desc, double* U, double dt, double t);
+
 /* nsteps SSP steps of size dt, in place on U.  With bc_kind RIEMANN the
  * stage launches go to the stream directly (their exterior state changes with
  * time); otherwise the stage launches (3, 2 or 6 per step) are recorded once into a HIP graph (cached for the same U, dt and

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <tuple>
 #include <utility>
@@ -78,6 +79,43 @@ struct dg_ctx {
   double* Z = nullptr;     // sensor records
   double* Z2 = nullptr;    // second record buffer: launches that read one set and write another
 };
+
+// ---------------------------------------------------------------------------
+// Stage buffers of dg_step_static, for callers that cannot allocate: three
+// buffers of kStaticStageDoubles doubles in one file-scope device array
+// (24 MiB, held on every device the library runs on until the process
+// ends).  Host code never uses the array's name as an address: its address on
+// each device comes from hipGetSymbolAddress, taken once per device.
+// ---------------------------------------------------------------------------
+constexpr long long kStaticStageDoubles = 1LL << 20;
+static __device__ __align__(256) double scratch[3 * kStaticStageDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of `scratch` on the current device (looked up on first use there).
+int scratch_on_current_device(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(DG_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(DG_EUNSUPPORTED, "device %d beyond the %d the library tracks", dev,
+                                                 kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(DG_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return DG_OK;
+}
+
+}  // namespace
 
 namespace {
 
@@ -729,6 +767,49 @@ int dg_step(dg_ctx* c, double* U, double dt) {
   const int rc = rk_steps(c, c->stream, U, dt, 1, c->t);
   if (rc == DG_OK) c->t += dt;
   return rc;
+}
+
+int dg_step_static(const dg_mesh_desc* desc, double* U, double dt, double t) {
+  g_err[0] = 0;
+  int rc = validate(desc);
+  if (rc) return rc;
+  if (!U) return fail(DG_EINVAL, "U is NULL");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite and > 0");
+  if (!std::isfinite(t)) return fail(DG_EINVAL, "t must be finite");
+  // the same problem a context would hold, on the stack: no stage buffers of
+  // its own, no tables (the kernels' tables are compile-time constants)
+  dg_ctx c;
+  c.d = *desc;
+  if (c.d.dim == 1) c.d.ny = 1;
+  c.nl = c.d.dim == 1 ? c.d.p + 1 : (c.d.p + 1) * (c.d.p + 1);
+  if (c.d.flux == DG_FLUX_EULER) c.nl *= 3;
+  c.ncells = (long long)c.d.nx * c.d.ny;
+  const long long ndof = c.ncells * c.nl;
+  if (ndof > kStaticStageDoubles)
+    return fail(DG_EINVAL, "dg_step_static: %lld coefficients exceed its static stage buffers (%lld)", ndof,
+                kStaticStageDoubles);
+  c.h = (c.d.x1 - c.d.x0) / c.d.nx;
+  c.stream = static_cast<hipStream_t>(desc->stream);
+  c.launch = launcher(c.d.dim, c.d.p);
+  c.fused = false;   // the per-stage kernels (the fused kernel needs a second state buffer)
+  int dev = 0, lds = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
+    c.max_lds = lds;
+  if (c.d.dim == 1) {
+    c.tx = 256;
+    c.ty = 1;
+  } else {
+    c.tx = c.ty = 16;
+    if (stage_lds_bytes(2, c.nl, 16, 16) > (size_t)c.max_lds) c.tx = c.ty = 8;
+  }
+  double* base = nullptr;
+  if ((rc = scratch_on_current_device(&base))) return rc;
+  c.U1 = base;
+  c.U2 = base + kStaticStageDoubles;
+  c.U3 = base + 2 * kStaticStageDoubles;
+  return ssp_step(&c, c.stream, U, dt, t);
 }
 
 int dg_set_time(dg_ctx* c, double t) {

@@ -96,6 +96,8 @@ EXPORTS = {
     "dg_batch_set_branches": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "dg_batch_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                      ctypes.c_char_p, ctypes.c_int32]),
+    "dg_step_static": (ctypes.c_int, [ctypes.POINTER(MeshDesc), ctypes.c_void_p, ctypes.c_double,
+                                      ctypes.c_double]),
 }
 
 _lib = None
@@ -398,6 +400,26 @@ class Batch:
 
     def set_branches(self, n: int) -> None:
         _check(self.lib.dg_batch_set_branches(self.h, int(n)))
+
+
+# coefficients one dg_step_static call can hold (its static stage buffers)
+STATIC_STAGE_DOUBLES = 1 << 20
+
+
+def step_static(desc: "MeshDesc", U: torch.Tensor, dt: float, t: float = 0.0,
+                stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """dg_step_static: one SSP step of U (contiguous float64, [n_cells, n_loc])
+    in place, with no context and no allocation (stage states in the
+    library's static device array), queued on `stream` (default: torch's
+    current stream).  The descriptor's own stream field is overwritten."""
+    lib = load()
+    st = stream if stream is not None else torch.cuda.current_stream()
+    d = MeshDesc.from_buffer_copy(desc)
+    d.stream = ctypes.c_void_p(st.cuda_stream)
+    if not (U.is_cuda and U.dtype == torch.float64 and U.is_contiguous()):
+        raise ValueError("U must be a contiguous float64 GPU tensor")
+    _check(lib.dg_step_static(ctypes.byref(d), ctypes.c_void_p(U.data_ptr()), float(dt), float(t)))
+    return U
 
 
 def stream_copy(src: torch.Tensor, dst: torch.Tensor) -> None:

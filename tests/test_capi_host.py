@@ -140,3 +140,17 @@ def test_product_code_does_not_import_the_oracle():
         if name.endswith(".py"):
             text = open(os.path.join(pkg, name)).read()
             assert not re.search(r"^\s*(import|from)\s+oracle", text, re.M), name
+
+
+def test_static_step_checks_arguments_on_host(lib):
+    """dg_step_static refuses bad arguments and problems beyond its static
+    stage buffers (2^20 coefficients) before any device call."""
+    U = ctypes.c_void_p(0x1000)   # never dereferenced: every case fails on the host
+    assert lib.dg_step_static(None, U, 0.1, 0.0) == -1
+    assert lib.dg_step_static(ctypes.byref(_desc(p=0)), U, 0.1, 0.0) == -1
+    assert lib.dg_step_static(ctypes.byref(_desc()), None, 0.1, 0.0) == -1
+    assert lib.dg_step_static(ctypes.byref(_desc()), U, -0.1, 0.0) == -1
+    assert lib.dg_step_static(ctypes.byref(_desc()), U, 0.1, float("inf")) == -1
+    big = _desc(dim=2, nx=342, ny=342, p=2)          # 342^2 * 9 = 1,052,676 coefficients
+    assert lib.dg_step_static(ctypes.byref(big), U, 0.1, 0.0) == -1
+    assert b"exceed" in lib.dg_last_error()
