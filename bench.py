@@ -256,12 +256,19 @@ def bench_batch(steps=100, seed=0, count=512):
             "tuned_schedule": [B.schedule(c) for c in range(B.num_classes())]}
 
 
-def bench_adjoint(n=512, steps=400, ndir=32, nsnaps=None, seed=0):
+def bench_adjoint(n=512, steps=400, ndir=32, seed=0, budget_bytes=1 << 30):
     """Gradient of J = int_W u(T)^2 dx, W = [0.25, 0.75]^2, with respect to all
     initial DOFs of 2D Burgers (n x n, P2, seeded Fourier data, `steps` steps)
-    by the checkpointed discrete adjoint; cost relative to the plain forward
-    run; central differences (Richardson over delta, delta/2) of the GPU
-    forward run along `ndir` random unit directions at six step sizes."""
+    by the checkpointed discrete adjoint.  Cost (forward with checkpoints +
+    backward) over the plain forward run for three memory budgets: binomial
+    checkpointing within ~1 GB of snapshots (the headline), one snapshot per
+    step, and every step's stage states kept (the upper-memory reference).
+    Finite differences of the GPU forward map along `ndir` random unit
+    directions: central differences Richardson-extrapolated over (delta,
+    delta/2), delta = 1e-4 ||U^0||_inf (and 1e-5 for comparison); every
+    direction's runs record their branches (dg_run_signature), and a
+    direction whose records at U^0 +- delta d (or +- delta/2 d) differ has
+    crossed a kink of the map, reported per kind (sensor, lambda_e, LLF)."""
     import numpy as np
     import torch
     from paper_2309_12019_amd import dgweno, inputs
@@ -276,11 +283,7 @@ def bench_adjoint(n=512, steps=400, ndir=32, nsnaps=None, seed=0):
     mh = torch.tensor([4.0 / ((2 * a + 1) * (2 * b + 1)) for b in range(3) for a in range(3)],
                       dtype=torch.float64, device=dev) * (0.5 / n) ** 2
 
-    def J(U):
-        return ((U * U * mh[None, :]).sum(1) * inside).sum()
-
     st = torch.cuda.current_stream()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
 
     def timed(fn):
         torch.cuda.synchronize()
@@ -296,10 +299,14 @@ def bench_adjoint(n=512, steps=400, ndir=32, nsnaps=None, seed=0):
     g.run(U, dt, steps)             # records the graphs (untimed)
     U.copy_(U0)
     _, t_fwd = timed(lambda: g.run(U, dt, steps))
+    state_bytes = w.ndof * 8
     res = {"workload": f"2D Burgers {n}x{n} P2 WENO, seeded Fourier data, {steps} SSP-RK3 steps, "
-                       f"J = int over [0.25,0.75]^2 of u(T)^2", "dofs": w.ndof, "forward_s": t_fwd}
-    main = steps if nsnaps is None else nsnaps
-    for ns, keep in ((main, True), (main, False), (20, False)):
+                       f"J = int over [0.25,0.75]^2 of u(T)^2", "dofs": w.ndof, "forward_s": t_fwd,
+           "state_bytes": state_bytes}
+    budget_snaps = max(1, budget_bytes // state_bytes - 2)   # + 2 working slots
+    grad = None
+    for key, ns, keep in (("budget_1GiB", budget_snaps, False), ("snapshot_every_step", steps, False),
+                          ("every_stage_state_kept", steps, True)):
         ck = g.checkpoints(ns)
         stg = g.stage_checkpoints(steps) if keep else None
         for rep in range(2):  # the first pass warms the buffers, as the forward run above
@@ -308,48 +315,62 @@ def bench_adjoint(n=512, steps=400, ndir=32, nsnaps=None, seed=0):
             _, t_b = timed(lambda: g.adjoint_backward(dt, steps, ns, ck, lam, stages=stg))
         del ck, stg
         torch.cuda.empty_cache()
-        st_ = dgweno.revolve_stats(steps, ns)
-        key = f"snapshots_{ns}" + ("_with_stage_states" if keep else "")
-        res[key] = {"forward_with_checkpoints_s": t_f, "backward_s": t_b,
-                    "cost_vs_forward": (t_f + t_b) / t_fwd,
-                    "recomputed_steps": st_["recomputed_steps"],
-                    "checkpoint_bytes": (ns + 2 + (2 * steps if keep else 0)) * w.ndof * 8}
-        if keep:
+        rs = dgweno.revolve_stats(steps, ns)
+        res[key] = {"snapshots": ns, "forward_with_checkpoints_s": t_f, "backward_s": t_b,
+                    "cost_vs_forward": (t_f + t_b) / t_fwd, "recomputed_steps": rs["recomputed_steps"],
+                    "checkpoint_bytes": (ns + 2 + (2 * steps if keep else 0)) * state_bytes}
+        if grad is None:
             grad = lam.clone()
-            JT = float(J(UT))
-            res["cost_vs_forward"] = (t_f + t_b) / t_fwd
-            res["schedule"] = key
-    # finite differences of the forward map
+            JT = float(((UT * UT * mh[None, :]).sum(1) * inside).sum())
+    res["cost_vs_forward"] = res["budget_1GiB"]["cost_vs_forward"]
+    res["schedule"] = "budget_1GiB"
+    res["upper_memory_reference"] = "every_stage_state_kept"
+
+    # finite differences of the forward map, with branch records
     rng = np.random.default_rng(1)
-    umax = float(U0.abs().max())
+    u0max = float(U0.abs().max())
+    sig = [torch.empty((3, g.ncells), dtype=torch.int32, device=dev) for _ in range(4)]
 
-    def dJ(d, s):
-        """J(U(s)) - J(U(-s)) summed as (U+ - U-)(U+ + U-): the two values of
-        J agree to ~1e-9 of J, below the rounding of each sum on its own."""
-        Up = (U0 + s * d).contiguous()
-        Um = (U0 - s * d).contiguous()
-        g.run(Up, dt, steps)
-        g.run(Um, dt, steps)
-        return float((((Up - Um) * (Up + Um) * mh[None, :]).sum(1) * inside).sum())
+    def runs(d, delta):
+        """J(U(+s)) - J(U(-s)) for s = delta and delta/2, summed as (U+ - U-)(U+ + U-)
+        (the two values of J agree to ~1e-9 of J, below the rounding of each sum),
+        and the cells whose branch records differ between +s and -s, per kind."""
+        out, crossed = [], np.zeros(3, dtype=np.int64)
+        for k, s_ in enumerate((delta, 0.5 * delta)):
+            Up = (U0 + s_ * d).contiguous()
+            Um = (U0 - s_ * d).contiguous()
+            g.run_signature(Up, dt, steps, sig[2 * k])
+            g.run_signature(Um, dt, steps, sig[2 * k + 1])
+            out.append(float((((Up - Um) * (Up + Um) * mh[None, :]).sum(1) * inside).sum()))
+            crossed += (sig[2 * k] != sig[2 * k + 1]).sum(1).cpu().numpy()
+        return out, crossed
 
-    rows = []
-    for k in range(ndir):
+    deltas = (("1e-4", 1e-4 * u0max), ("1e-5", 1e-5 * u0max))
+    rows = {tag: [] for tag, _ in deltas}
+    for j in range(ndir):
         d = torch.from_numpy(rng.standard_normal(U0.shape)).to(dev)
         d /= d.norm()
         ad = float((grad * d).sum())
-        row = {"ad": ad}
-        for tag, delta in (("1e-4", 1e-4 * umax), ("1e-5", 1e-5 * umax), ("3e-6", 3e-6 * umax),
-                           ("1e-6", 1e-6 * umax), ("1e-7", 1e-7 * umax), ("1e-8", 1e-8 * umax)):
-            fd1 = dJ(d, delta) / (2 * delta)
-            fd2 = dJ(d, delta / 2) / delta
+        for tag, delta in deltas:
+            (j1, j2), crossed = runs(d, delta)
+            fd1, fd2 = j1 / (2 * delta), j2 / delta
             fd = (4 * fd2 - fd1) / 3
-            row[tag] = abs(fd - ad) / abs(ad)
-        rows.append(row)
-    for tag in ("1e-4", "1e-5", "3e-6", "1e-6", "1e-7", "1e-8"):
-        errs = [r[tag] for r in rows]
-        res[f"fd_delta_{tag}_umax"] = {"directions": ndir, "max_rel_err": max(errs),
-                                       "median_rel_err": float(np.median(errs)),
-                                       "within_1e-6": int(sum(e <= 1e-6 for e in errs))}
+            rows[tag].append({"rel_err": abs(fd - ad) / abs(ad), "crossed": crossed.tolist()})
+    for tag, delta in deltas:
+        r = rows[tag]
+        kink = [x for x in r if sum(x["crossed"]) > 0]
+        clean = [x for x in r if sum(x["crossed"]) == 0]
+        res[f"fd_delta_{tag}_u0max"] = {
+            "delta": delta, "directions": ndir, "within_1e-6": int(sum(x["rel_err"] <= 1e-6 for x in r)),
+            "kink_crossing": len(kink),
+            "kink_crossing_by_kind": {k: int(sum(x["crossed"][i] > 0 for x in r))
+                                      for i, k in enumerate(("sensor", "lambda_e", "llf"))},
+            "without_kink": len(clean),
+            "without_kink_within_1e-6": int(sum(x["rel_err"] <= 1e-6 for x in clean)),
+            "failures_not_at_a_kink": int(sum(x["rel_err"] > 1e-6 for x in clean)),
+            "max_rel_err": max(x["rel_err"] for x in r), "median_rel_err": float(np.median([x["rel_err"] for x in r])),
+            "max_rel_err_without_kink": max((x["rel_err"] for x in clean), default=None),
+            "median_cells_crossed": float(np.median([sum(x["crossed"]) for x in r]))}
     res["J"] = JT
     return res
 

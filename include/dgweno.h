@@ -107,22 +107,46 @@ typedef struct dg_mesh_desc {
   int32_t rk_order;          /* SSP Runge-Kutta order of dg_step/dg_run: 3 (eq. ssp,
                                 default), 2 or 4 (Sec. 5.1 runs order p + 1) */
   int32_t bc_kind;           /* enum dg_bc */
+  /* Gauss-Legendre points per axis (the paper leaves its quadrature to the
+   * finite element library it uses).  0 selects the built rule: volume and
+   * faces exact for the polynomial part of the integrands, p + 1 for
+   * LINADV, ceil(3p/2) (1D) or ceil((3p+1)/2) (2D) for BURGERS, p + 2 for
+   * KPP and EULER; projection p + 2.  The rules are compile-time tables: any
+   * other value is DG_EUNSUPPORTED (DG_EINVAL outside 0..8). */
+  int32_t quad_vol, quad_face, quad_proj;
+  /* dg_stable_dt's reading of "CFL" (the paper never states its step):
+   * 0 scaled (default), dt = cfl h / ((2p+1) lambda_max); 1 literal,
+   * dt = cfl h / lambda_max. */
+  int32_t cfl_mode;
+  /* 1: dg_step and dg_run count the non-finite entries of U on the device
+   * once their steps are queued, wait for them, and return DG_ENONFINITE if
+   * there are any (the call then synchronises the stream); 0 (default): no
+   * check. */
+  int32_t check_finite;
+  /* HIP device the context runs on: -1 (default) the device current at
+   * dg_init_mesh; otherwise that device, made current for the duration of
+   * every call on the context and restored afterwards. */
+  int32_t device;
 } dg_mesh_desc;
 
 typedef struct dg_ctx dg_ctx;   /* opaque, owned by the library */
 
 /* Fill a descriptor with the defaults: 1D, 64 cells on [0,1] periodic, p = 2,
  * LINADV with vel_x = 1, mode WENO, q = 1, b = 0, w_nb = 0.01, eps = 1e-6,
- * pow = 2, no lambda override, default stream, zhao_theta = 1, rk_order = 3,
- * bc_kind CONSTANT.  Never fails. */
+ * pow = 2 (the values of Sec. 5), no lambda override, default stream,
+ * zhao_theta = 1, rk_order = 3, bc_kind CONSTANT, built quadrature rules,
+ * cfl_mode 0, no finite check, device -1.  Never fails. */
 void dg_default_desc(dg_mesh_desc* desc);
 
-/* Validate `desc` and create a context on the current HIP device: mesh,
- * compile-time tables for degree p, and two stage buffers of
- * n_cells * n_loc doubles (three for rk_order 4; the only allocations the
- * context makes besides the adjoint's, on first use).
+/* Validate `desc` and create a context for the problem of Sec. 2 (the
+ * conservation law on the mesh T_h, discretised in the broken space V_p of
+ * degree p) on the descriptor's HIP device: mesh, compile-time tables for
+ * degree p, and two stage buffers of n_cells * n_loc doubles for the stages
+ * of eq. (ssp) (three for rk_order 4; the only allocations the context makes
+ * besides the adjoint's, on first use).
  * Errors: DG_EINVAL (bad field, null pointer, non-square 2D cells),
- * DG_ENOMEM, DG_EDEVICE.  On failure *out is set to NULL. */
+ * DG_EUNSUPPORTED (a quadrature rule that is not built), DG_ENOMEM,
+ * DG_EDEVICE.  On failure *out is set to NULL. */
 int dg_init_mesh(const dg_mesh_desc* desc, dg_ctx** out);
 
 /* Release the context and its device buffers (synchronises its stream). */
@@ -164,7 +188,8 @@ int dg_rhs(dg_ctx* ctx, const double* U, double* dUdt, double* gamma);
  * re-evaluated in every stage (Sec. 3, the stabilisation is part of the
  * semi-discrete operator).  The five-stage method evaluates the operator six
  * times per step (its last stage needs L(U^(3)) a second time).  dt must be
- * finite and > 0. */
+ * finite and > 0.  With check_finite, DG_ENONFINITE if U holds NaN or Inf
+ * after the step. */
 int dg_step(dg_ctx* ctx, double* U, double dt);
 
 /* For callers that cannot allocate (code under HIP graph capture, tight
@@ -182,15 +207,22 @@ int dg_step(dg_ctx* ctx, double* U, double dt);
  * device call); DG_EDEVICE. */
 int dg_step_static(const dg_mesh_desc* desc, double* U, double dt, double t);
 
-/* nsteps SSP steps of size dt, in place on U.  With bc_kind RIEMANN the
- * stage launches go to the stream directly (their exterior state changes with
- * time); otherwise the stage launches (3, 2 or 6 per step) are recorded once into a HIP graph (cached for the same U, dt and
- * chunk length) and replayed on the context stream.  nsteps >= 0. */
+/* nsteps SSP steps of size dt (eq. ssp, or the order rk_order selects), in
+ * place on U (device): the fully discrete scheme of Sec. 2 run over a fixed
+ * step, the stabilisation of Secs. 3 and 4 re-evaluated in every stage.
+ * With bc_kind RIEMANN the stage launches go to the stream directly (their
+ * exterior state changes with time); otherwise the stage launches (3, 2 or 6
+ * per step; one fused launch per step where dg_set_fused selects it) are
+ * recorded once into a HIP graph (cached for the same U, dt and chunk
+ * length) and replayed on the context stream.  nsteps >= 0.  With
+ * check_finite, DG_ENONFINITE if U holds NaN or Inf after the run. */
 int dg_run(dg_ctx* ctx, double* U, double dt, int32_t nsteps);
 
-/* Stable step for the fixed-step reading of "CFL": dt = cfl * h /
- * ((2p+1) * lambda_max) where lambda_max is the largest lambda_e of U (device)
- * over the mesh.  Synchronous; writes the host double *dt_host. */
+/* Stable step for the fixed-step reading of "CFL" (the configurations quote
+ * a CFL number; the paper states no step): dt = cfl * h / ((2p+1) *
+ * lambda_max) (cfl_mode 0) or cfl * h / lambda_max (cfl_mode 1), where
+ * lambda_max is the largest lambda_e of eq. (visc) of U (device) over the
+ * mesh.  Synchronous; writes the host double *dt_host. */
 int dg_stable_dt(dg_ctx* ctx, const double* U, double cfl, double* dt_host);
 
 /* Check U (device) for NaN/Inf: counted on the device, summed on the host.
@@ -276,6 +308,21 @@ int dg_adjoint_forward(dg_ctx* ctx, const double* U0, double* UT, double dt, int
                        double* ckpt, double* stages);
 int dg_adjoint_backward(dg_ctx* ctx, double dt, int32_t nsteps, int32_t nsnaps, double* ckpt,
                         const double* stages, double* lam);
+
+/* Branch records of a run, for finite-difference checks of the adjoint: the
+ * computed map is differentiable except where a branch of the method
+ * switches: min(1, ratio) and the threshold b of the sensor (eqs.
+ * sensor/gensensor), the node of the largest |F'| in lambda_e (eq. visc) and
+ * the larger trace in the LLF wave speed (Sec. 2).  This runs nsteps SSP-RK3
+ * steps of U in place, as dg_run (same per-stage kernels, launched directly,
+ * bitwise the same result), and folds for every cell the branches its
+ * operator evaluations took in every stage into three 32-bit hashes,
+ * sig[k * n_cells + cell] (device, caller-owned, 3 * n_cells uint32; cleared
+ * by the call): k = 0 the sensor, 1 lambda_e, 2 the LLF wave speeds.  Two
+ * runs whose records differ in a cell crossed a kink of the map there; two
+ * equal records mean no recorded branch switched (up to hash collisions).
+ * DG_EUNSUPPORTED outside the adjoint's coverage (see above). */
+int dg_run_signature(dg_ctx* ctx, double* U, double dt, int32_t nsteps, uint32_t* sig);
 
 /* Host-only statistics of the checkpoint schedule: stats[6] = {forward-sweep
  * steps, recomputed steps, stores, adjoint steps, highest slot, actions}. */

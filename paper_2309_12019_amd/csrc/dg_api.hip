@@ -37,6 +37,19 @@ int hip_fail(hipError_t e, const char* what) {
   return fail(DG_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
+// Makes `dev` the current HIP device for a scope (no-op when it already is)
+// and restores the previous one.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    int cur = -1;
+    if (dev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != dev && hipSetDevice(dev) == hipSuccess) prev = cur;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
 LaunchFn launcher(int dim, int p) {
   static const LaunchFn tab[2][4] = {{dgk_launch_1_1, dgk_launch_1_2, dgk_launch_1_3, dgk_launch_1_4},
                                      {dgk_launch_2_1, dgk_launch_2_2, dgk_launch_2_3, dgk_launch_2_4}};
@@ -54,6 +67,7 @@ struct GraphKey {
 
 struct dg_ctx {
   dg_mesh_desc d;
+  int dev = 0;             // HIP device of the context
   int nl = 0;
   long long ncells = 0;
   int tx = 0, ty = 1;
@@ -327,8 +341,27 @@ int validate(const dg_mesh_desc* d) {
   const double vals[] = {d->vel_x, d->vel_y, d->omega, d->rot_cx, d->rot_cy, d->bc_value};
   for (double v : vals)
     if (!std::isfinite(v)) return fail(DG_EINVAL, "non-finite flux parameter");
+  // quadrature: 0 or the compile-time rule of this flux and degree
+  const int qv = dgk::quad_points(d->dim, d->p, d->flux);
+  const int32_t qs[3] = {d->quad_vol, d->quad_face, d->quad_proj};
+  const int built[3] = {qv, qv, d->p + 2};
+  const char* which[3] = {"quad_vol", "quad_face", "quad_proj"};
+  for (int k = 0; k < 3; ++k) {
+    if (qs[k] < 0 || qs[k] > dgk::kMaxQ) return fail(DG_EINVAL, "%s must be 0 or 1..%d (got %d)", which[k], dgk::kMaxQ, qs[k]);
+    if (qs[k] != 0 && qs[k] != built[k])
+      return fail(DG_EUNSUPPORTED, "%s = %d is not built: the rule for this flux and degree has %d points", which[k],
+                  qs[k], built[k]);
+  }
+  if (d->cfl_mode != 0 && d->cfl_mode != 1) return fail(DG_EINVAL, "cfl_mode must be 0 or 1 (got %d)", d->cfl_mode);
+  if (d->check_finite != 0 && d->check_finite != 1)
+    return fail(DG_EINVAL, "check_finite must be 0 or 1 (got %d)", d->check_finite);
+  if (d->device < -1) return fail(DG_EINVAL, "device must be -1 or a device index (got %d)", d->device);
   return DG_OK;
 }
+
+// With check_finite: count the non-finite entries of U (queued after the
+// caller's work on the context stream, then waited for).
+int finite_or_fail(dg_ctx* c, const double* U);
 
 int check_tile(const dg_ctx* c, int tx, int ty) {
   const int dim = c->d.dim;
@@ -590,6 +623,7 @@ void dg_default_desc(dg_mesh_desc* d) {
   d->zhao_theta = 1.0;
   d->rk_order = 3;
   d->bc_kind = DG_BC_CONSTANT;
+  d->device = -1;
 }
 
 const char* dg_last_error(void) { return g_err; }
@@ -647,12 +681,22 @@ int dg_init_mesh(const dg_mesh_desc* desc, dg_ctx** out) {
   c->h = (c->d.x1 - c->d.x0) / c->d.nx;
   c->stream = static_cast<hipStream_t>(desc->stream);
   c->launch = launcher(c->d.dim, c->d.p);
-  int dev = 0;
+  int dev = 0, ndev = 0;
   hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess && desc->device >= 0) {
+    e = hipGetDeviceCount(&ndev);
+    if (e == hipSuccess && desc->device >= ndev) {
+      delete c;
+      return fail(DG_EINVAL, "device %d: only %d devices", desc->device, ndev);
+    }
+    dev = desc->device;
+  }
   if (e != hipSuccess) {
     delete c;
     return hip_fail(e, "hipGetDevice");
   }
+  c->dev = dev;
+  DeviceGuard guard(dev);
   int lds = 0;
   if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
     c->max_lds = lds;
@@ -689,6 +733,7 @@ int dg_init_mesh(const dg_mesh_desc* desc, dg_ctx** out) {
 
 void dg_destroy(dg_ctx* c) {
   if (!c) return;
+  DeviceGuard guard(c->dev);
   if (c->stream || c->U1) (void)hipStreamSynchronize(c->stream);
   drop_graphs(c);
   if (c->U1) (void)hipFree(c->U1);
@@ -744,6 +789,7 @@ int dg_proj_nodes(const dg_ctx* c, double* xy) {
 
 int dg_project_ic(dg_ctx* c, const double* u_at_nodes, double* U) {
   if (!c || !u_at_nodes || !U) return fail(DG_EINVAL, "NULL argument");
+  DeviceGuard guard(c->dev);
   LaunchReq r{};
   r.kind = dgk::LAUNCH_PROJECT;
   r.src = u_at_nodes;
@@ -757,6 +803,7 @@ int dg_project_ic(dg_ctx* c, const double* u_at_nodes, double* U) {
 
 int dg_rhs(dg_ctx* c, const double* U, double* dUdt, double* gamma) {
   if (!c || !U || !dUdt) return fail(DG_EINVAL, "NULL argument");
+  DeviceGuard guard(c->dev);
   if (U == dUdt) return fail(DG_EINVAL, "U and dUdt must not overlap");
   return stage(c, c->stream, U, nullptr, dUdt, gamma, 0.0, 1.0, 0.0, 1, c->t);
 }
@@ -764,8 +811,10 @@ int dg_rhs(dg_ctx* c, const double* U, double* dUdt, double* gamma) {
 int dg_step(dg_ctx* c, double* U, double dt) {
   if (!c || !U) return fail(DG_EINVAL, "NULL argument");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite and > 0");
+  DeviceGuard guard(c->dev);
   const int rc = rk_steps(c, c->stream, U, dt, 1, c->t);
   if (rc == DG_OK) c->t += dt;
+  if (rc == DG_OK && c->d.check_finite) return finite_or_fail(c, U);
   return rc;
 }
 
@@ -854,11 +903,21 @@ static int run_graph(dg_ctx* c, double* U, double dt, int len, hipGraphExec_t* o
   return DG_OK;
 }
 
+static int run_steps(dg_ctx* c, double* U, double dt, int32_t nsteps);
+
 int dg_run(dg_ctx* c, double* U, double dt, int32_t nsteps) {
   if (!c || !U) return fail(DG_EINVAL, "NULL argument");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite and > 0");
   if (nsteps < 0) return fail(DG_EINVAL, "nsteps must be >= 0");
   if (nsteps == 0) return DG_OK;
+  DeviceGuard guard(c->dev);
+  const int rc = run_steps(c, U, dt, nsteps);
+  if (rc == DG_OK && c->d.check_finite) return finite_or_fail(c, U);
+  return rc;
+}
+
+// dg_run's steps (arguments checked by the caller)
+static int run_steps(dg_ctx* c, double* U, double dt, int32_t nsteps) {
   if (c->d.bc_kind != DG_BC_CONSTANT) {
     // the exterior state depends on the stage times, which a replayed graph
     // would repeat: launch the steps directly
@@ -887,8 +946,45 @@ int dg_run(dg_ctx* c, double* U, double dt, int32_t nsteps) {
   return DG_OK;
 }
 
+int dg_run_signature(dg_ctx* c, double* U, double dt, int32_t nsteps, uint32_t* sig) {
+  if (!c || !U || !sig) return fail(DG_EINVAL, "NULL argument");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite and > 0");
+  if (nsteps < 0) return fail(DG_EINVAL, "nsteps must be >= 0");
+  if ((c->d.flux != DG_FLUX_LINADV && c->d.flux != DG_FLUX_BURGERS) || c->d.mode == DG_MODE_ZHAO ||
+      c->d.bc_kind != DG_BC_CONSTANT || c->d.rk_order != 3)
+    return fail(DG_EUNSUPPORTED, "branch records cover what the adjoint covers: linear and Burgers fluxes, "
+                                 "modes DG/LO/WENO, the constant exterior state, SSP-RK3");
+  DeviceGuard guard(c->dev);
+  hipError_t e = hipMemsetAsync(sig, 0, sizeof(uint32_t) * 3 * (size_t)c->ncells, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "branch record clear");
+  auto record = [&](const double* uin) -> int {
+    LaunchReq r{};
+    r.kind = dgk::LAUNCH_SIGNATURE;
+    r.flux = c->d.flux;
+    r.mode = c->d.mode;
+    r.args = base_args(c);
+    r.args.uin = uin;
+    r.sig = sig;
+    r.stream = c->stream;
+    const hipError_t le = c->launch(&r);
+    return le == hipSuccess ? DG_OK : hip_fail(le, "branch record launch");
+  };
+  const double as[3] = {0.0, 0.75, 1.0 / 3.0}, bs[3] = {1.0, 0.25, 2.0 / 3.0};
+  double* in[3] = {U, c->U1, c->U2};
+  double* out[3] = {c->U1, c->U2, U};
+  for (int s = 0; s < nsteps; ++s)
+    for (int k = 0; k < 3; ++k) {
+      int rc = record(in[k]);
+      if (rc == DG_OK) rc = stage(c, c->stream, in[k], U, out[k], nullptr, as[k], bs[k], dt, 0, c->t);
+      if (rc) return rc;
+    }
+  c->t += nsteps * dt;
+  return DG_OK;
+}
+
 int dg_stable_dt(dg_ctx* c, const double* U, double cfl, double* dt_host) {
   if (!c || !U || !dt_host) return fail(DG_EINVAL, "NULL argument");
+  DeviceGuard guard(c->dev);
   if (!(cfl > 0.0) || !std::isfinite(cfl)) return fail(DG_EINVAL, "cfl must be finite and > 0");
   LaunchReq r{};
   r.kind = dgk::LAUNCH_LAMBDA;
@@ -908,12 +1004,13 @@ int dg_stable_dt(dg_ctx* c, const double* U, double cfl, double* dt_host) {
   double lam = 0.0;
   for (double v : h) lam = v > lam ? v : lam;
   if (!(lam > 0.0) || !std::isfinite(lam)) return fail(DG_ENONFINITE, "maximal wave speed is %g", lam);
-  *dt_host = cfl * c->h / ((2 * c->d.p + 1) * lam);
+  *dt_host = c->d.cfl_mode == 1 ? cfl * c->h / lam : cfl * c->h / ((2 * c->d.p + 1) * lam);
   return DG_OK;
 }
 
 int dg_check_finite(dg_ctx* c, const double* U, int64_t* count) {
   if (!c || !U) return fail(DG_EINVAL, "NULL argument");
+  DeviceGuard guard(c->dev);
   const long long n = (long long)c->ncells * c->nl;
   // per-block counts on the device (grid-stride), summed here
   long long nb = (n + 255) / 256;
@@ -931,6 +1028,19 @@ int dg_check_finite(dg_ctx* c, const double* U, int64_t* count) {
   if (count) *count = (int64_t)bad;
   return bad > 0.0 ? fail(DG_ENONFINITE, "%lld non-finite entries", (long long)bad) : DG_OK;
 }
+
+}  // extern "C"
+
+namespace {
+int finite_or_fail(dg_ctx* c, const double* U) {
+  int64_t bad = 0;
+  const int rc = dg_check_finite(c, U, &bad);
+  if (rc == DG_ENONFINITE) return fail(DG_ENONFINITE, "%lld non-finite entries after the steps", (long long)bad);
+  return rc;
+}
+}  // namespace
+
+extern "C" {
 
 int dg_stream_copy(const double* src, double* dst, int64_t n, void* stream) {
   if (n < 0) return fail(DG_EINVAL, "n must be >= 0");
@@ -985,6 +1095,7 @@ int dg_get_tile(const dg_ctx* c, int32_t* tx, int32_t* ty) {
 
 int dg_rhs_vjp(dg_ctx* c, const double* U, const double* v, double* out) {
   if (!c || !U || !v || !out) return fail(DG_EINVAL, "NULL argument");
+  DeviceGuard guard(c->dev);
   if (out == U || out == v) return fail(DG_EINVAL, "out must not overlap U or v");
   int rc = ensure_adjoint(c);
   if (rc) return rc;
@@ -993,6 +1104,7 @@ int dg_rhs_vjp(dg_ctx* c, const double* U, const double* v, double* out) {
 
 int dg_step_adjoint(dg_ctx* c, const double* Un, double dt, const double* lam_out, double* lam_in) {
   if (!c || !Un || !lam_out || !lam_in) return fail(DG_EINVAL, "NULL argument");
+  DeviceGuard guard(c->dev);
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite and > 0");
   if (lam_in == Un) return fail(DG_EINVAL, "lam_in must not overlap Un");
   if (c->d.rk_order != 3) return fail(DG_EUNSUPPORTED, "the step adjoint covers the three-stage SSP method only");
@@ -1032,6 +1144,7 @@ int dg_revolve_stats(int32_t nsteps, int32_t nsnaps, int64_t* stats) {
 int dg_adjoint_forward(dg_ctx* c, const double* U0, double* UT, double dt, int32_t nsteps, int32_t nsnaps,
                        double* ckpt, double* stages) {
   if (!c || !U0 || !UT || !ckpt) return fail(DG_EINVAL, "NULL argument");
+  DeviceGuard guard(c->dev);
   if (c->d.rk_order != 3) return fail(DG_EUNSUPPORTED, "the step adjoint covers the three-stage SSP method only");
   if (c->d.bc_kind != DG_BC_CONSTANT)
     return fail(DG_EUNSUPPORTED, "the adjoint does not cover the exact-solution exterior state");
@@ -1092,6 +1205,7 @@ int dg_adjoint_forward(dg_ctx* c, const double* U0, double* UT, double dt, int32
 int dg_adjoint_backward(dg_ctx* c, double dt, int32_t nsteps, int32_t nsnaps, double* ckpt, const double* stages,
                         double* lam) {
   if (!c || !ckpt || !lam) return fail(DG_EINVAL, "NULL argument");
+  DeviceGuard guard(c->dev);
   if (c->d.rk_order != 3) return fail(DG_EUNSUPPORTED, "the step adjoint covers the three-stage SSP method only");
   if (nsteps < 1 || nsnaps < 0) return fail(DG_EINVAL, "need nsteps >= 1 and nsnaps >= 0");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite and > 0");

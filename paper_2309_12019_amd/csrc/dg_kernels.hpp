@@ -607,6 +607,109 @@ struct Cell {
     }
   }
 
+  // Branch record of the cell's evaluation, for checks of the discrete
+  // adjoint by finite differences: the decisions the operator takes where the
+  // computed map is not differentiable, each folded into its own 32-bit hash.
+  //   v[0] the sensor (eqs. sensor/gensensor): gamma_e >= 1 (min(1, ratio) at
+  //        its cap) and gamma_e == 0 (below the threshold b);
+  //   v[1] lambda_e of eq. (visc) for Burgers: the volume node of the largest
+  //        |u| (strict running maximum, as in residual) and the sign of u there;
+  //   v[2] the LLF wave speed for Burgers (Sec. 2): at every face node which
+  //        of |u^-|, |u^+| is larger, and their signs.
+  // The node values and traces are computed with the same explicit fma chains
+  // as residual(), so the decisions are those of the operator itself.  The
+  // linear flux has no such point in U (its wave speeds depend on x only).
+  __device__ static inline void branches(const StageArgs& A, const double* b, const double (&c)[NL], double gam,
+                                         uint32_t (&v)[3]) {
+    auto fold = [](uint32_t h, uint32_t x) { return (h ^ x) * 16777619u; };
+    v[0] = v[1] = v[2] = 2166136261u;
+    if constexpr (MODE == MODE_WENO) v[0] = fold(v[0], (gam >= 1.0 ? 1u : 0u) | (gam == 0.0 ? 2u : 0u));
+    if constexpr (FLUX == FLUX_BURGERS) {
+      double umax = 0.0;
+      uint32_t arg = 0xffffu, sgn = 0;
+      if constexpr (DIM == 1) {
+#pragma unroll
+        for (int qn = 0; qn < Q; ++qn) {
+          double u = c[0];
+#pragma unroll
+          for (int a = 1; a < N; ++a) u = fma(c[a], TB::nd.L[a][qn], u);
+          if (fabs(u) > umax) {
+            umax = fabs(u);
+            arg = qn;
+            sgn = u < 0.0;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int qx = 0; qx < Q; ++qx) {
+          double s1[N];
+#pragma unroll
+          for (int bb = 0; bb < N; ++bb) {
+            double t = c[N * bb];
+#pragma unroll
+            for (int a = 1; a < N; ++a) t = fma(c[a + N * bb], TB::nd.L[a][qx], t);
+            s1[bb] = t;
+          }
+#pragma unroll
+          for (int qy = 0; qy < Q; ++qy) {
+            double u = s1[0];
+#pragma unroll
+            for (int bb = 1; bb < N; ++bb) u = fma(s1[bb], TB::nd.L[bb][qy], u);
+            if (fabs(u) > umax) {
+              umax = fabs(u);
+              arg = qx * Q + qy;
+              sgn = u < 0.0;
+            }
+          }
+        }
+      }
+      v[1] = fold(v[1], arg | (sgn << 16));
+      // faces: the traces and node values of residual()'s face loop
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const bool plus = f & 1;
+        if constexpr (DIM == 1) {
+          double um = 0.0, up = 0.0;
+#pragma unroll
+          for (int a = 0; a < N; ++a) {
+            const double so = f ? 1.0 : TB::dg.sgn[a];
+            const double sn = f ? TB::dg.sgn[a] : 1.0;
+            um = fma(so, c[a], um);
+            up = fma(sn, b[a * S + off(f)], up);
+          }
+          v[2] = fold(v[2], (fabs(um) > fabs(up) ? 1u : 0u) | (um < 0.0 ? 2u : 0u) | (up < 0.0 ? 4u : 0u));
+        } else {
+          const int axis = f >> 1;
+          double tm[N], tp[N];
+#pragma unroll
+          for (int k = 0; k < N; ++k) {
+            double t = 0.0, tn = 0.0;
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+              const int j = axis == 0 ? i + N * k : k + N * i;
+              const double so = plus ? 1.0 : TB::dg.sgn[i];
+              const double sn = plus ? TB::dg.sgn[i] : 1.0;
+              t = fma(so, c[j], t);
+              tn = fma(sn, b[j * S + off(f)], tn);
+            }
+            tm[k] = t;
+            tp[k] = tn;
+          }
+#pragma unroll
+          for (int r = 0; r < Q; ++r) {
+            double um = tm[0], up = tp[0];
+#pragma unroll
+            for (int k = 1; k < N; ++k) {
+              um = fma(tm[k], TB::nd.L[k][r], um);
+              up = fma(tp[k], TB::nd.L[k][r], up);
+            }
+            v[2] = fold(v[2], (fabs(um) > fabs(up) ? 1u : 0u) | (um < 0.0 ? 2u : 0u) | (up < 0.0 ? 4u : 0u));
+          }
+        }
+      }
+    }
+  }
+
   // Dissipation gamma nu int grad(phi).grad(u_h) and M^-1:
   // L = (2/h) Mhat^-1 [ vol - face - (gamma lambda / p) Khat c ]
   __device__ static inline void finish(const StageArgs& A, const double (&c)[NL], double gam, double lam,
@@ -807,6 +910,41 @@ __global__ void __launch_bounds__(DIM == 2 ? TX * TY : TX) stage_kernel(const St
   extern __shared__ double lds[];
   stage_tile<DIM, P, FLUX, MODE, TX, TY, DIM == 2 && FLUX == FLUX_BURGERS>(A, lds, blockIdx.x * TX,
                                                                          DIM == 2 ? blockIdx.y * TY : 0);
+}
+
+// Branch records of the stage input (Cell::branches) of every cell, folded
+// into sig[k * cells + cell] (k = 0 sensor, 1 wave speed lambda_e, 2 LLF):
+// the tile is loaded as in stage_tile's general path; nothing is written but
+// the records.  Grid as for stage_kernel.
+template <int DIM, int P, int FLUX, int MODE, int TX, int TY>
+__global__ void __launch_bounds__(DIM == 2 ? TX * TY : TX) signature_kernel(const StageArgs A, uint32_t* sig) {
+  extern __shared__ double lds[];
+  using G = TileGeom<DIM, TX, TY>;
+  using C = Cell<DIM, P, FLUX, MODE, G::S, G::W>;
+  constexpr int NL = C::NL;
+  constexpr int S = G::S;
+  const int ix0 = blockIdx.x * TX, iy0 = DIM == 2 ? blockIdx.y * TY : 0;
+  const int nx = A.nx, ny = DIM == 2 ? A.ny : 1;
+  const int t = threadIdx.x;
+  int sc, gx, gy, hs, hgx, hgy;
+  const bool halo = tile_slots<DIM, TX, TY>(t, ix0, iy0, sc, gx, gy, hs, hgx, hgy);
+  double c[NL];
+  load_cell<DIM, NL>(A, gx, gy, c);
+  if (halo) load_slot<DIM, NL, S>(A, lds, hs, hgx, hgy);
+#pragma unroll
+  for (int j = 0; j < NL; ++j) lds[j * S + sc] = c[j];
+  tile_barrier();
+  if (gx < nx && gy < ny) {
+    const size_t cell = (size_t)gy * nx + gx, ncells = (size_t)nx * ny;
+    const double gam = C::template gamma_of<true>(A, lds + sc, c, gx, gy);
+    uint32_t v[3];
+    C::branches(A, lds + sc, c, gam, v);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const uint32_t h = sig[k * ncells + cell];
+      sig[k * ncells + cell] = ((h << 7) | (h >> 25)) ^ v[k];
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------

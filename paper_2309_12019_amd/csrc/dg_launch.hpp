@@ -6,7 +6,8 @@
 namespace dgk {
 
 enum LaunchKind { LAUNCH_STAGE = 0, LAUNCH_PROJECT = 1, LAUNCH_LAMBDA = 2, LAUNCH_BATCH = 3,
-                  LAUNCH_ADJ_SENSOR = 4, LAUNCH_ADJ_GRAD = 5, LAUNCH_STEP = 6, LAUNCH_ADJ_GRAD_SENSOR = 7 };
+                  LAUNCH_ADJ_SENSOR = 4, LAUNCH_ADJ_GRAD = 5, LAUNCH_STEP = 6, LAUNCH_ADJ_GRAD_SENSOR = 7,
+                  LAUNCH_SIGNATURE = 8 };
 
 // the fused step kernel's tiles
 constexpr int kStepTile1D = 256;
@@ -27,6 +28,7 @@ struct LaunchReq {
   hipStream_t stream;
   BatchStageArgs batch;  // LAUNCH_BATCH (tile shape in args.tx/args.ty, grid in ncells)
   AdjArgs adj;           // LAUNCH_ADJ_* (tile shape in adj.s.tx/adj.s.ty)
+  uint32_t* sig;         // LAUNCH_SIGNATURE: branch records [3][cells] (stage input in args.uin)
 };
 
 typedef hipError_t (*LaunchFn)(const LaunchReq*);

@@ -192,6 +192,45 @@ hipError_t launch_euler(int mode, const StageArgs& A, hipStream_t s) {
   }
 }
 
+// branch records of a stage input (linear and Burgers fluxes, modes DG, LO,
+// WENO: the adjoint's coverage), on the context's tile
+template <int FLUX, int MODE, int TX, int TY>
+hipError_t launch_sig_tile(const LaunchReq* r) {
+  constexpr int NL = DGK_DIM == 1 ? DGK_P + 1 : (DGK_P + 1) * (DGK_P + 1);
+  const StageArgs& A = r->args;
+  auto k = signature_kernel<DGK_DIM, DGK_P, FLUX, MODE, TX, TY>;
+  const size_t lds = sizeof(double) * (size_t)tile_lds_doubles(DGK_DIM, NL, TX, TY);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  dim3 grid((A.nx + TX - 1) / TX, DGK_DIM == 2 ? (A.ny + TY - 1) / TY : 1);
+  hipLaunchKernelGGL(k, grid, dim3(DGK_DIM == 2 ? TX * TY : TX), lds, r->stream, A, r->sig);
+  return hipGetLastError();
+}
+
+template <int FLUX, int MODE>
+hipError_t launch_sig_fm(const LaunchReq* r) {
+  if constexpr (DGK_DIM == 1) {
+    if (r->args.tx == 64) return launch_sig_tile<FLUX, MODE, 64, 1>(r);
+    return launch_sig_tile<FLUX, MODE, 256, 1>(r);
+  } else {
+    if (r->args.tx == 8) return launch_sig_tile<FLUX, MODE, 8, 8>(r);
+    return launch_sig_tile<FLUX, MODE, 16, 16>(r);
+  }
+}
+
+template <int FLUX>
+hipError_t launch_sig_f(const LaunchReq* r) {
+  switch (r->mode) {
+    case MODE_DG: return launch_sig_fm<FLUX, MODE_DG>(r);
+    case MODE_LO: return launch_sig_fm<FLUX, MODE_LO>(r);
+    case MODE_WENO: return launch_sig_fm<FLUX, MODE_WENO>(r);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <int FLUX>
 hipError_t launch_stage_f(int mode, const StageArgs& A, hipStream_t s) {
   switch (mode) {
@@ -241,6 +280,11 @@ extern "C" hipError_t DGK_CAT(dgk_launch, DGK_DIM, DGK_P)(const LaunchReq* r) {
       // the adjoint covers the linear and Burgers fluxes
       if (r->flux == FLUX_LINADV) return launch_adj_f<FLUX_LINADV>(r);
       if (r->flux == FLUX_BURGERS) return launch_adj_f<FLUX_BURGERS>(r);
+      return hipErrorInvalidValue;
+    }
+    case LAUNCH_SIGNATURE: {
+      if (r->flux == FLUX_LINADV) return launch_sig_f<FLUX_LINADV>(r);
+      if (r->flux == FLUX_BURGERS) return launch_sig_f<FLUX_BURGERS>(r);
       return hipErrorInvalidValue;
     }
     case LAUNCH_PROJECT: {

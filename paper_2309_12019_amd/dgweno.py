@@ -47,6 +47,10 @@ class MeshDesc(ctypes.Structure):
         ("zhao_theta", ctypes.c_double),
         ("rk_order", ctypes.c_int32),
         ("bc_kind", ctypes.c_int32),
+        ("quad_vol", ctypes.c_int32), ("quad_face", ctypes.c_int32), ("quad_proj", ctypes.c_int32),
+        ("cfl_mode", ctypes.c_int32),
+        ("check_finite", ctypes.c_int32),
+        ("device", ctypes.c_int32),
     ]
 
 
@@ -98,6 +102,8 @@ EXPORTS = {
                                      ctypes.c_char_p, ctypes.c_int32]),
     "dg_step_static": (ctypes.c_int, [ctypes.POINTER(MeshDesc), ctypes.c_void_p, ctypes.c_double,
                                       ctypes.c_double]),
+    "dg_run_signature": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int32,
+                                        ctypes.c_void_p]),
 }
 
 _lib = None
@@ -152,6 +158,9 @@ def desc_from_fields(f: dict) -> MeshDesc:
     d.zhao_theta = f.get("theta", 1.0)
     d.rk_order = f.get("rk_order", 3)
     d.bc_kind = f.get("bc_kind", 0)
+    d.quad_vol, d.quad_face, d.quad_proj = f.get("quad_vol", 0), f.get("quad_face", 0), f.get("quad_proj", 0)
+    d.cfl_mode = f.get("cfl_mode", 0)
+    d.check_finite = int(f.get("check_finite", 0))
     return d
 
 
@@ -171,7 +180,7 @@ class DG:
         _check(lib.dg_sizes(h, ctypes.byref(nc), ctypes.byref(nl), ctypes.byref(nq)))
         self.ncells, self.nloc, self.nproj = nc.value, nl.value, nq.value
         self.ncomp = 3 if desc.flux == DG_FLUX_EULER else 1   # values per projection node
-        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.device = torch.device("cuda", desc.device if desc.device >= 0 else torch.cuda.current_device())
 
     @classmethod
     def from_workload(cls, w, stream=None) -> "DG":
@@ -222,6 +231,19 @@ class DG:
     def run(self, U: torch.Tensor, dt: float, nsteps: int) -> torch.Tensor:
         _check(self.lib.dg_run(self.h, _ptr(U, self.ncells * self.nloc, "U"), float(dt), int(nsteps)))
         return U
+
+    def run_signature(self, U: torch.Tensor, dt: float, nsteps: int,
+                      sig: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """dg_run_signature: nsteps SSP-RK3 steps of U in place (as run) and
+        the branch records, an int32 tensor [3, n_cells] (sensor, lambda_e,
+        LLF hashes) holding the uint32 bits."""
+        if sig is None:
+            sig = torch.empty((3, self.ncells), dtype=torch.int32, device=self.device)
+        if not (sig.is_cuda and sig.dtype == torch.int32 and sig.is_contiguous() and sig.numel() == 3 * self.ncells):
+            raise ValueError("sig must be a contiguous int32 GPU tensor of 3 * n_cells entries")
+        _check(self.lib.dg_run_signature(self.h, _ptr(U, self.ncells * self.nloc, "U"), float(dt), int(nsteps),
+                                         ctypes.c_void_p(sig.data_ptr())))
+        return sig
 
     def set_time(self, t: float) -> None:
         """Set the context's clock (dg_set_time): the time of the state the

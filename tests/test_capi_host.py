@@ -62,6 +62,8 @@ def test_default_desc(lib):
     dict(bc_kind=2), dict(bc_kind=1, flux=1),                         # the exact exterior state is 2D
     dict(dim=2, nx=8, ny=8, flux=1, bc_kind=1),                       # ... on non-periodic boundaries
     dict(dim=2, nx=8, ny=8, flux=0, bc_kind=1, periodic_x=0, periodic_y=0),   # ... for Burgers
+    dict(quad_vol=9), dict(quad_face=-1), dict(quad_proj=12), dict(cfl_mode=2), dict(check_finite=3),
+    dict(device=-2),
 ])
 def test_invalid_descriptors_rejected_on_host(lib, bad):
     d = _desc(**bad)
@@ -154,3 +156,21 @@ def test_static_step_checks_arguments_on_host(lib):
     big = _desc(dim=2, nx=342, ny=342, p=2)          # 342^2 * 9 = 1,052,676 coefficients
     assert lib.dg_step_static(ctypes.byref(big), U, 0.1, 0.0) == -1
     assert b"exceed" in lib.dg_last_error()
+
+
+@pytest.mark.parametrize("field,value", [("quad_vol", 5), ("quad_face", 2), ("quad_proj", 3)])
+def test_quadrature_rules_that_are_not_built_are_refused_on_host(lib, field, value):
+    """The rules are compile-time tables (p + 1 points for the linear flux of
+    degree 2, projection p + 2): another count is valid but not built."""
+    from paper_2309_12019_amd import dgweno
+    d = _desc(**{field: value})
+    h = ctypes.c_void_p(123)
+    assert lib.dg_init_mesh(ctypes.byref(d), ctypes.byref(h)) == dgweno.DG_EUNSUPPORTED
+    assert h.value is None
+    assert b"not built" in lib.dg_last_error()
+
+
+def test_built_quadrature_rules_named_explicitly_validate(lib):
+    assert lib.dg_validate_desc(ctypes.byref(_desc(quad_vol=3, quad_face=3, quad_proj=4))) == 0
+    assert lib.dg_validate_desc(ctypes.byref(_desc(dim=2, nx=8, ny=8, flux=1, quad_vol=4, quad_face=4))) == 0
+    assert lib.dg_validate_desc(ctypes.byref(_desc(cfl_mode=1, check_finite=1, device=0))) == 0

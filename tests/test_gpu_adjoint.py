@@ -218,3 +218,35 @@ def test_shared_launches_equal_separate_passes_bitwise(kind, p):
     ref = out[(0, nsteps, True)]
     for key, val in out.items():
         assert torch.equal(val, ref), key
+
+
+def test_branch_records_follow_the_run_and_its_kinks():
+    """dg_run_signature advances U exactly as dg_run does (bitwise) and its
+    records are deterministic; a perturbation large enough to move shocks
+    changes the records of some cells, and an exact copy of the state
+    reproduces them.  On the linear flux only the sensor record can change."""
+    dgweno = _dg()
+    w = inputs.burgers2d(40, 2, seed=0, ny=36, steps=30)
+    g = dgweno.DG.from_workload(w)
+    U0 = g.initial_state(w)
+    A, B = U0.clone(), U0.clone()
+    g.run(A, w.dt(), 30)
+    s1 = g.run_signature(B, w.dt(), 30)
+    torch.cuda.synchronize()
+    assert torch.equal(A, B)
+    C = U0.clone()
+    s2 = g.run_signature(C, w.dt(), 30)
+    torch.cuda.synchronize()
+    assert torch.equal(s1, s2)
+    D = U0 + 1e-3 * U0.abs().max() * torch.sin(torch.arange(U0.numel(), device=U0.device, dtype=U0.dtype)).view_as(U0)
+    s3 = g.run_signature(D, w.dt(), 30)
+    torch.cuda.synchronize()
+    assert int((s3 != s1).sum()) > 0
+    wl = inputs.rot2d(40, 2, ny=36, steps=10)
+    gl = dgweno.DG.from_workload(wl)
+    V = gl.initial_state(wl)
+    sl = gl.run_signature(V, wl.dt(), 10)
+    W = gl.initial_state(wl) * 1.001
+    sl2 = gl.run_signature(W, wl.dt(), 10)
+    torch.cuda.synchronize()
+    assert torch.equal(sl[1:], sl2[1:])      # no wave-speed or LLF branches for the linear flux

@@ -262,6 +262,58 @@ def test_stable_dt_and_finite_check():
     assert g.count_nonfinite(U) == 2
 
 
+def test_run_reports_non_finite_states_with_check_finite():
+    """check_finite: dg_run and dg_step count the non-finite entries of U once
+    their steps are queued and return DG_ENONFINITE if there are any."""
+    _note("[check_finite]")
+    dgweno = _dg()
+    w = inputs.burgers2d(40, 2, ny=36, steps=1)
+    d = dgweno.desc_from_fields(w.fields())
+    d.check_finite = 1
+    g = dgweno.DG(d)
+    U = g.initial_state(w)
+    g.run(U, w.dt(), 3)            # finite: no error
+    g.step(U, w.dt())
+    U[5, 1] = float("nan")
+    with pytest.raises(dgweno.DGError) as ex:
+        g.run(U, w.dt(), 2)
+    assert ex.value.code == dgweno.DG_ENONFINITE
+    U[:] = 0.0
+    U[7, 0] = float("inf")
+    with pytest.raises(dgweno.DGError) as ex:
+        g.step(U, w.dt())
+    assert ex.value.code == dgweno.DG_ENONFINITE
+    # without the flag the same run returns normally (the caller checks)
+    g2 = dgweno.DG.from_workload(w)
+    U2 = g2.initial_state(w)
+    U2[5, 1] = float("nan")
+    g2.run(U2, w.dt(), 2)
+    torch.cuda.synchronize()
+    assert g2.count_nonfinite(U2) > 0
+
+
+def test_cfl_mode_and_named_quadrature_rules():
+    """cfl_mode 1 (literal) gives (2p + 1) times the scaled step; naming the
+    built quadrature rules explicitly changes nothing (bitwise)."""
+    _note("[cfl_mode, quadrature fields]")
+    dgweno = _dg()
+    w = inputs.burgers2d(48, 2, ny=40, steps=1)
+    d0 = dgweno.desc_from_fields(w.fields())
+    d1 = dgweno.desc_from_fields(w.fields())
+    d1.cfl_mode = 1
+    d1.quad_vol, d1.quad_face, d1.quad_proj = 4, 4, 4
+    g0, g1 = dgweno.DG(d0), dgweno.DG(d1)
+    U0 = g0.initial_state(w)
+    U1 = g1.initial_state(w)
+    assert torch.equal(U0, U1)
+    dt0, dt1 = g0.stable_dt(U0, 0.1), g1.stable_dt(U1, 0.1)
+    assert abs(dt1 - 5 * dt0) <= 1e-15 * dt1
+    g0.run(U0, dt0, 5)
+    g1.run(U1, dt0, 5)
+    torch.cuda.synchronize()
+    assert torch.equal(U0, U1)
+
+
 def test_invalid_arguments_through_the_binding():
     dgweno = _dg()
     w = inputs.adv1d(64, 2)
