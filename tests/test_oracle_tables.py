@@ -130,3 +130,71 @@ def test_poly_deriv():
     F = Fraction
     assert poly_deriv([F(1), F(2), F(3)], 1) == [F(2), F(6)]
     assert poly_deriv([F(1), F(2), F(3)], 3) == [F(0)]
+
+
+# ---------------------------------------------------------------------------
+# Oracle.project and Oracle.l1_error against numpy's Legendre routines
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("dim", [1, 2])
+def test_projection_reproduces_polynomials_of_degree_p(dim, p):
+    """The L2 projection onto V_p (Sec. 2) is the identity on V_p: a global
+    polynomial of degree <= p per axis comes back as its own Legendre
+    coefficients on every cell (numpy's poly2leg of the polynomial written in
+    the cell's reference coordinate)."""
+    import numpy.polynomial.legendre as npleg
+    import numpy.polynomial.polynomial as nppoly
+    from oracle import Oracle, Problem
+    rng = np.random.default_rng(10 * dim + p)
+    n = 5
+    prob = Problem(dim=dim, nx=n, ny=n if dim == 2 else 1, p=p, x0=-0.3, x1=0.7, y0=0.1, y1=1.1)
+    O = Oracle(prob)
+    ax = rng.standard_normal(p + 1)
+    ay = rng.standard_normal(p + 1) if dim == 2 else None
+    h = prob.h
+
+    def cell_leg(a, c0):
+        # sum_k a_k (c0 + (h/2) xi)^k in powers of xi, then Legendre
+        mono = np.zeros(p + 1)
+        for k, ak in enumerate(a):
+            mono[: k + 1] += ak * nppoly.polypow([c0, 0.5 * h], k)[: k + 1]
+        leg = np.zeros(p + 1)
+        l_ = npleg.poly2leg(mono)
+        leg[: len(l_)] = l_[: p + 1]
+        return leg
+
+    nodes = O.proj_nodes().numpy()
+    if dim == 1:
+        vals = nppoly.polyval(nodes[..., 0], ax)
+    else:
+        vals = nppoly.polyval(nodes[..., 0], ax) * nppoly.polyval(nodes[..., 1], ay)
+    U = O.project(torch.from_numpy(vals)).numpy()
+    for e in range(prob.ncells):
+        ix, iy = e % n, e // n
+        leg_x = cell_leg(ax, prob.x0 + (ix + 0.5) * h)
+        if dim == 1:
+            want = leg_x
+        else:
+            cy = cell_leg(ay, prob.y0 + (iy + 0.5) * h)
+            want = np.outer(cy, leg_x).reshape(-1)        # j = a + (p+1) b
+        assert np.allclose(U[e], want, rtol=1e-12, atol=1e-12)
+
+
+def test_l1_error_of_known_fields():
+    """l1_error integrates |u_h - u| with the node weights (h/2)^d w_q: for a
+    state that is the constant c on every cell and exact values 0 it is
+    |c| |Omega|; for u_h = x - x_c (a linear mode) it is the Q-point rule
+    applied to |x - x_c| on every cell (numpy's Gauss rule)."""
+    from oracle import Oracle, Problem
+    O = Oracle(Problem(dim=2, nx=6, ny=6, p=2, x0=0.0, x1=1.5, y0=0.0, y1=1.5))
+    U = torch.zeros(36, 9, dtype=torch.float64)
+    U[:, 0] = -0.7
+    assert abs(O.l1_error(U, torch.zeros(36, 16, dtype=torch.float64), 4) - 0.7 * 1.5 ** 2) < 1e-14
+    O1 = Oracle(Problem(dim=1, nx=8, p=2))
+    V = torch.zeros(8, 3, dtype=torch.float64)
+    V[:, 1] = 0.5 * O1.h                 # u_h = (h/2) xi = x - x_c
+    exact = torch.zeros(8, 6, dtype=torch.float64)
+    # |xi| is not a polynomial: the 6-point rule integrates it only approximately
+    xi, w = np.polynomial.legendre.leggauss(6)
+    want = 8 * (0.5 * O1.h) ** 2 * float(np.sum(w * np.abs(xi)))
+    assert abs(O1.l1_error(V, exact, 6) - want) < 1e-15
