@@ -163,8 +163,8 @@ StageArgs base_args(const dg_ctx* c) {
   return A;
 }
 
-size_t stage_lds_bytes(int dim, int nl, int tx, int ty) {
-  return sizeof(double) * (size_t)dgk::tile_lds_doubles(dim, nl, tx, dim == 2 ? ty : 1);
+size_t stage_lds_bytes(int dim, int nl, int flux, int tx, int ty) {
+  return sizeof(double) * (size_t)dgk::stage_lds_doubles(dim, nl, flux, tx, dim == 2 ? ty : 1);
 }
 
 // one stage: out = a*un + b*(uin + dt*L(uin)), or out = L(uin) when rhs_only;
@@ -375,9 +375,9 @@ int check_tile(const dg_ctx* c, int tx, int ty) {
   if (!ok)
     return fail(DG_EINVAL, dim == 1 ? "1D tile must be 256 or 64 cells (got %d)"
                                      : "2D tile must be 16x16 or 8x8 (got %dx%d)", tx, ty);
-  if (stage_lds_bytes(dim, c->nl, tx, ty) > (size_t)c->max_lds)
+  if (stage_lds_bytes(dim, c->nl, c->d.flux, tx, ty) > (size_t)c->max_lds)
     return fail(DG_EUNSUPPORTED, "tile %dx%d needs %zu bytes of LDS (limit %d)", tx, ty,
-                stage_lds_bytes(dim, c->nl, tx, ty), c->max_lds);
+                stage_lds_bytes(dim, c->nl, c->d.flux, tx, ty), c->max_lds);
   return DG_OK;
 }
 
@@ -707,7 +707,7 @@ int dg_init_mesh(const dg_mesh_desc* desc, dg_ctx** out) {
   } else {
     c->tx = 16;
     c->ty = 16;
-    if (stage_lds_bytes(2, c->nl, 16, 16) > (size_t)c->max_lds) c->tx = c->ty = 8;
+    if (stage_lds_bytes(2, c->nl, c->d.flux, 16, 16) > (size_t)c->max_lds) c->tx = c->ty = 8;
   }
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0) c->cus = cus;
@@ -851,7 +851,7 @@ int dg_step_static(const dg_mesh_desc* desc, double* U, double dt, double t) {
     c.ty = 1;
   } else {
     c.tx = c.ty = 16;
-    if (stage_lds_bytes(2, c.nl, 16, 16) > (size_t)c.max_lds) c.tx = c.ty = 8;
+    if (stage_lds_bytes(2, c.nl, c.d.flux, 16, 16) > (size_t)c.max_lds) c.tx = c.ty = 8;
   }
   double* base = nullptr;
   if ((rc = scratch_on_current_device(&base))) return rc;

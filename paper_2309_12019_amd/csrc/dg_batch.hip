@@ -96,8 +96,8 @@ void drop_graph(dg_batch* b) {
 
 int nl_of(const dg_mesh_desc& d) { return d.dim == 1 ? d.p + 1 : (d.p + 1) * (d.p + 1); }
 
-size_t lds_bytes(int dim, int nl, int tx, int ty) {
-  return sizeof(double) * (size_t)dgk::tile_lds_doubles(dim, nl, tx, dim == 2 ? ty : 1);
+size_t lds_bytes(int dim, int nl, int flux, int tx, int ty) {
+  return sizeof(double) * (size_t)dgk::stage_lds_doubles(dim, nl, flux, tx, dim == 2 ? ty : 1);
 }
 
 // Build the tile list of a class for its current schedule and upload it into
@@ -251,7 +251,7 @@ int dg_batch_create(const dg_mesh_desc* descs, int32_t count, dg_batch** out) {
     c.nl = nl_of(d);
     c.tx = d.dim == 1 ? 256 : 16;
     c.ty = d.dim == 1 ? 1 : 16;
-    if (lds_bytes(c.dim, c.nl, c.tx, c.ty) > (size_t)b->max_lds) c.tx = c.ty = 8;
+    if (lds_bytes(c.dim, c.nl, c.flux, c.tx, c.ty) > (size_t)b->max_lds) c.tx = c.ty = 8;
     c.probs = probs;
     c.cap = dgk::batch_tile_capacity(b->mesh, probs);
     b->cls.push_back(c);
@@ -348,7 +348,7 @@ int dg_batch_set_schedule(dg_batch* b, int32_t cls, int32_t tx, int32_t ty, int3
     for (auto& t : dgk::kTiles2D) ok |= tx == t[0] && ty == t[1];
   }
   if (!ok) return bfail(DG_EINVAL, "unsupported tile %dx%d", tx, ty);
-  if (lds_bytes(c.dim, c.nl, tx, ty) > (size_t)b->max_lds) return bfail(DG_EUNSUPPORTED, "tile exceeds LDS");
+  if (lds_bytes(c.dim, c.nl, c.flux, tx, ty) > (size_t)b->max_lds) return bfail(DG_EUNSUPPORTED, "tile exceeds LDS");
   if (grid_per_cu < 1 || grid_per_cu > 64) return bfail(DG_EINVAL, "grid_per_cu must be in 1..64");
   if (order < 0 || order > 2) return bfail(DG_EINVAL, "order must be 0, 1 or 2");
   c.tx = tx;
@@ -446,7 +446,7 @@ int dg_batch_run_sequential(dg_batch* b, double* arena, const double* dts, int32
         r.args = b->args[i];
         r.args.tx = d.dim == 1 ? 256 : 16;
         r.args.ty = d.dim == 1 ? 1 : 16;
-        if (lds_bytes(d.dim, nl_of(d), r.args.tx, r.args.ty) > (size_t)b->max_lds) r.args.tx = r.args.ty = 8;
+        if (lds_bytes(d.dim, nl_of(d), d.flux, r.args.tx, r.args.ty) > (size_t)b->max_lds) r.args.tx = r.args.ty = 8;
         r.args.uin = in[k];
         r.args.un = U;
         r.args.out = out[k];
@@ -488,7 +488,7 @@ int dg_batch_tune(dg_batch* b, double* arena, const double* dts, int32_t reps, c
     float best = 1e30f;
     int bt = c.tx, bty = c.ty, bg = c.grid_per_cu, bo = c.order;
     for (auto& tt : tiles) {
-      if (lds_bytes(c.dim, c.nl, tt.first, tt.second) > (size_t)b->max_lds) continue;
+      if (lds_bytes(c.dim, c.nl, c.flux, tt.first, tt.second) > (size_t)b->max_lds) continue;
       for (int order : {0, 2}) {
         c.tx = tt.first;
         c.ty = tt.second;

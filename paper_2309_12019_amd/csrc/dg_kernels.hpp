@@ -75,6 +75,79 @@ __host__ __device__ inline int tile_lds_doubles(int dim, int nl, int tx, int ty)
   return nl * (ns | 1);   // the tile with its face halo
 }
 
+// Shared faces.  In a 2D tile of at least four waves the per-stage and
+// batched kernels can evaluate the flux moments of every face of the tile
+// once, in a face phase, and keep them in LDS after the tile: the x faces
+// ((TX + 1) per row, row-major) in N planes of stride XS, then the y faces
+// (TX per row of faces, TY + 1 rows) in N planes of stride YS.  A cell's own
+// four face evaluations compute each interior face twice.  The face phase
+// costs a second barrier and LDS; it pays where the flux is expensive (the
+// Burgers and KPP fluxes) at p = 2, and is used there only.  (A one-wave 8 x 8
+// tile has as many face rounds either way.)
+__host__ __device__ constexpr bool shares_faces(int dim, int p, int flux, int tx, int ty) {
+  return dim == 2 && p == 2 && (flux == FLUX_BURGERS || flux == FLUX_KPP) && tx * ty >= 256;
+}
+
+template <int TX, int TY>
+struct FaceGeom {
+  static constexpr int NXF = (TX + 1) * TY;  // x faces
+  static constexpr int NYF = TX * (TY + 1);  // y faces
+  static constexpr int XS = NXF | 1, YS = NYF | 1;
+};
+
+__host__ __device__ inline int face_lds_doubles(int n, int tx, int ty) {
+  return n * ((((tx + 1) * ty) | 1) + ((tx * (ty + 1)) | 1));
+}
+
+// LDS of the per-stage and batched stage kernels: the tile, and the shared
+// faces where the tile has them (nl = (p + 1)^dim)
+__host__ __device__ inline int stage_lds_doubles(int dim, int nl, int flux, int tx, int ty) {
+  int n = 1;
+  while ((dim == 2 ? n * n : n) < nl) ++n;
+  const int t = tile_lds_doubles(dim, nl, tx, ty);
+  return shares_faces(dim, n - 1, flux, tx, ty) ? t + face_lds_doubles(n, tx, ty) : t;
+}
+
+// The face thread t of a tile evaluates in round k (0..3) of the face phase:
+// round 0 x face t, round 1 y face t (every thread), round 2 x face NT + lane
+// on wave `rot` only, round 3 y face NT + lane on wave (rot + NW / 2) mod NW
+// only (NW waves of 64 lanes, NT = TX TY threads): the faces left over after
+// a full round of the workgroup (a column of x faces, a row of y faces).
+// Returns false where the thread has no face in that round; axis = k & 1.
+template <int TX, int TY>
+__host__ __device__ inline bool face_task(int t, int rot, int k, int& e) {
+  constexpr int NT = TX * TY, NW = NT / 64;
+  if (k < 2) {
+    e = t;
+    return true;
+  }
+  e = NT + (t & 63);
+  const int w = t >> 6;
+  if (k == 2) return w == rot && e < (TX + 1) * TY;
+  return w == (rot + NW / 2) % NW && e < TX * (TY + 1);
+}
+
+// Face e of a tile's shared faces: axis 0 the x faces (e < (TX + 1) TY), 1
+// the y faces (e < TX (TY + 1)).  Returns the LDS slot of the cell below the
+// face (the cell above is slot + 1 for x faces, slot + W for y faces) and in
+// (gx, gy) that cell's mesh coordinates before wrapping.  The faces of tile
+// cell (lx, ly): x faces ly (TX + 1) + lx (-x) and the next (+x), y faces
+// ly TX + lx (-y) and that + TX (+y).
+template <int TX, int TY>
+__host__ __device__ inline int face_slot(int axis, int e, int ix0, int iy0, int& gx, int& gy) {
+  constexpr int W = TX + 2;
+  if (axis == 0) {
+    const int fx = e % (TX + 1), ly = e / (TX + 1);
+    gx = ix0 - 1 + fx;
+    gy = iy0 + ly;
+    return (ly + 1) * W + fx;
+  }
+  const int lx = e % TX, fy = e / TX;
+  gx = ix0 + lx;
+  gy = iy0 - 1 + fy;
+  return fy * W + lx + 1;
+}
+
 // Workgroup barrier around LDS traffic between lanes.  For workgroups of a
 // single wave (8x8 and 64-cell tiles) the compiler removes s_barrier, and with
 // it the ordering of one lane's LDS accesses relative to another lane's: it
@@ -85,6 +158,25 @@ __host__ __device__ inline int tile_lds_doubles(int dim, int nl, int tx, int ty)
 __device__ inline void tile_barrier() {
   __syncthreads();
   asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+}
+
+// x, hidden from the optimiser: a value computed in two phases of a kernel
+// would otherwise be shared between them and held in registers in between
+__device__ inline int opaque(int x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+// XCD-aware tile order.  The dispatcher hands workgroup k (x fastest) to
+// XCD k mod 8, and each XCD has its own L2.  Workgroup k takes tile
+// xcd_tile(k, g) of the g tiles (row-major), a bijection under which every
+// XCD works through one contiguous band of tiles in order: the halos a tile
+// shares with its neighbours are then read on one XCD and hit its L2 instead
+// of being fetched again by another.
+constexpr int kXcds = 8;
+__host__ __device__ inline int xcd_tile(int k, int g) {
+  const int q = g / kXcds, r = g % kXcds, x = k % kXcds, i = k / kXcds;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
 }
 
 // x mod n for x in [-1, n + tile]: cheap for the common single wrap
@@ -316,32 +408,145 @@ struct Cell {
     return A.q == 1.0 ? r1 : pow_cold(r1, A.q);
   }
 
-  // KPP flux F(u) = (sin u, cos u) of Sec. 5.5: H(um, up, n), n = s e_axis,
-  // with s+ = max |F'(w) . n| over w between the states, i.e. max |cos w|
-  // (x faces) or |sin w| (y faces): 1 where that interval holds a peak
-  // (k pi, resp. pi/2 + k pi), else the larger end value
-  __device__ static inline double llf_kpp(int axis, double s, double um, double up) {
+  // Every face flux is taken in one orientation: n = +e_axis, from the cell
+  // below the face (state ul) to the cell above it (state uh).  The cell above
+  // uses H(uh, ul, -n) = -H(ul, uh, n) (the LLF flux is conservative), so both
+  // cells of a face, and a tile's shared face phase, compute the same face
+  // moments bit for bit.  The roundings are fixed by explicit fma.
+  //
+  // KPP flux F(u) = (sin u, cos u) of Sec. 5.5: H(ul, uh, e_axis) with
+  // s+ = max |F'(w) . n| over w between the states, i.e. max |cos w| (x
+  // faces) or |sin w| (y faces): 1 where that interval holds a peak (k pi,
+  // resp. pi/2 + k pi), else the larger end value
+  __device__ static inline double llf_kpp(int axis, double ul, double uh) {
     constexpr double kPi = 3.141592653589793238462643383279502884;
-    double sm, cm, sp, cp;
-    sincos_cold(um, &sm, &cm);
-    sincos_cold(up, &sp, &cp);
-    const double Fm = axis == 0 ? sm : cm, Fp = axis == 0 ? sp : cp;
-    const double dm = axis == 0 ? fabs(cm) : fabs(sm), dp = axis == 0 ? fabs(cp) : fabs(sp);
+    double sl, cl, sh, ch;
+    sincos_cold(ul, &sl, &cl);
+    sincos_cold(uh, &sh, &ch);
+    const double Fl = axis == 0 ? sl : cl, Fh = axis == 0 ? sh : ch;
+    const double dl = axis == 0 ? fabs(cl) : fabs(sl), dh = axis == 0 ? fabs(ch) : fabs(sh);
     const double shift = axis == 0 ? 0.0 : 0.5 * kPi;
-    const bool peak = floor((fmax(um, up) - shift) / kPi) >= ceil((fmin(um, up) - shift) / kPi);
-    const double splus = peak ? 1.0 : fmax(dm, dp);
-    return 0.5 * (s * Fm + s * Fp) - 0.5 * splus * (up - um);
+    const bool peak = floor((fmax(ul, uh) - shift) / kPi) >= ceil((fmin(ul, uh) - shift) / kPi);
+    const double splus = peak ? 1.0 : fmax(dl, dh);
+    return fma(-0.5 * splus, uh - ul, 0.5 * (Fl + Fh));
   }
 
-  // numerical flux H(um, up, n), n = s e_axis, v = normal velocity component
-  __device__ static inline double llf(const StageArgs& A, double s, double vax, double um, double up) {
+  // LLF flux H(ul, uh, e_axis) of Sec. 2 for the linear and Burgers fluxes;
+  // v: the velocity component along the axis (linear) or the axis component
+  // of the Burgers direction
+  __device__ static inline double llf(double v, double ul, double uh) {
     if constexpr (FLUX == FLUX_LINADV) {
-      const double vn = s * vax;
-      return 0.5 * vn * (um + up) - 0.5 * fabs(vn) * (up - um);
+      return fma(-0.5 * fabs(v), uh - ul, (0.5 * v) * (ul + uh));
     } else {
-      const double an = s * vax;
-      const double sp = fabs(an) * fmax(fabs(um), fabs(up));
-      return 0.25 * an * (um * um + up * up) - 0.5 * sp * (up - um);
+      const double sp = fabs(v) * fmax(fabs(ul), fabs(uh));
+      return fma(-0.5 * sp, uh - ul, (0.25 * v) * fma(ul, ul, uh * uh));
+    }
+  }
+
+  // Velocity component along `axis` at the Q Gauss points of a line of
+  // faces normal to it (linear flux): v_x on the row of cells i (it depends
+  // on y only), v_y on the column i (x only); the Burgers direction
+  // otherwise.
+  __device__ static inline void line_velocity(const StageArgs& A, int axis, int i, double (&v)[Q]) {
+    const double hh = 0.5 * A.h;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      if constexpr (FLUX == FLUX_LINADV) {
+        if (axis == 0) {
+          const double yc = fma(i + 0.5, A.h, A.y0);
+          v[k] = fma(-A.omega, fma(hh, TB::nd.x[k], yc) - A.cy, A.vx);
+        } else {
+          const double xc = fma(i + 0.5, A.h, A.x0);
+          v[k] = fma(A.omega, fma(hh, TB::nd.x[k], xc) - A.cx, A.vy);
+        }
+      } else {
+        v[k] = axis == 0 ? A.vx : A.vy;
+      }
+    }
+  }
+
+  // Trace of a cell on one of its faces normal to `axis`, in the face's
+  // Legendre basis: t_k = sum_i P_i(+-1) c(i, k), c(i, k) the coefficient of
+  // P_i along the axis times P_k along the face (in 1D the single value).
+  // UPPER: the cell above the face (its -axis side, P_i(-1) = (-1)^i); else
+  // the cell below (P_i(+1) = 1).  coef(j) returns coefficient j.
+  template <bool UPPER, class Coef>
+  __device__ static inline void trace(int axis, Coef coef, double (&t)[DIM == 2 ? N : 1]) {
+    if constexpr (DIM == 1) {
+      double acc = 0.0;
+#pragma unroll
+      for (int a = 0; a < N; ++a) acc = fma(UPPER ? TB::dg.sgn[a] : 1.0, coef(a), acc);
+      t[0] = acc;
+    } else {
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+          acc = fma(UPPER ? TB::dg.sgn[i] : 1.0, coef(axis == 0 ? i + N * k : k + N * i), acc);
+        t[k] = acc;
+      }
+    }
+  }
+
+  // The two states at Gauss point r of a 2D face from the traces
+  __device__ static inline void face_node(const double (&tl)[N], const double (&th)[N], int r, double& ul,
+                                          double& uh) {
+    ul = tl[0];
+    uh = th[0];
+#pragma unroll
+    for (int k = 1; k < N; ++k) {
+      ul = fma(tl[k], TB::nd.L[k][r], ul);
+      uh = fma(th[k], TB::nd.L[k][r], uh);
+    }
+  }
+
+  // Moments g_k = sum_r w_r L_k(x_r) H(ul(x_r), uh(x_r), e_axis) of a 2D face
+  // from the traces of the cells below (tl) and above (th) it; v as from
+  // line_velocity.  XBC: where xl (xh) is set, the state below (above) at
+  // point r is ext[r * S] instead (the BC_RIEMANN exterior slot).
+  template <bool XBC>
+  __device__ static inline void face_moments(int axis, const double (&tl)[N], const double (&th)[N],
+                                             const double (&v)[Q], bool xl, bool xh, const double* ext,
+                                             double (&g)[N]) {
+#pragma unroll
+    for (int r = 0; r < Q; ++r) {
+      double ul, uh;
+      face_node(tl, th, r, ul, uh);
+      if constexpr (XBC && FLUX == FLUX_BURGERS) {
+        if (xl) ul = ext[r * S];
+        if (xh) uh = ext[r * S];
+      }
+      double H;
+      if constexpr (FLUX == FLUX_KPP)
+        H = llf_kpp(axis, ul, uh);
+      else
+        H = llf(v[r], ul, uh);
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        const double cw = TB::nd.w[r] * TB::nd.L[k][r];
+        g[k] = r == 0 ? cw * H : fma(cw, H, g[k]);
+      }
+    }
+  }
+
+  // Adds face f's term - int_f phi H(u^-, u^+, n) to R from the face's
+  // moments: the cell below the face (f = 1, 3) subtracts them, the cell
+  // above (f = 0, 2) adds them with P_i(-1) = (-1)^i.
+  __device__ static inline void add_face(int f, const double (&g)[DIM == 2 ? N : 1], double (&R)[NL]) {
+    const bool below = f & 1;
+    if constexpr (DIM == 1) {
+#pragma unroll
+      for (int a = 0; a < N; ++a) R[a] = fma(below ? -1.0 : TB::dg.sgn[a], g[0], R[a]);
+    } else {
+      const int axis = f >> 1;
+#pragma unroll
+      for (int k = 0; k < N; ++k)
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          const int j = axis == 0 ? i + N * k : k + N * i;
+          R[j] = fma(below ? -1.0 : TB::dg.sgn[i], g[k], R[j]);
+        }
     }
   }
 
@@ -416,19 +621,52 @@ struct Cell {
     finish(A, c, gam, lam, R, L);
   }
 
-  // Volume minus face terms of the weak form (R) and the cell's wave speed
-  // lambda_e (before the override)
+  // The moments of face f of the cell (0: -x, 1: +x, 2: -y, 3: +y), oriented
+  // from the cell below the face to the cell above it: this cell's
+  // coefficients from registers, the neighbour's from its LDS slot.
   template <bool XBC = false>
+  __device__ static inline void cell_face(const StageArgs& A, const double* b, const double (&c)[NL], int ix, int iy,
+                                          int f, double (&g)[DIM == 2 ? N : 1]) {
+    const bool below = f & 1;  // this cell lies below the face
+    const int axis = f >> 1;
+    const int o = off(f);
+    auto own = [&](int j) { return c[j]; };
+    auto nbr = [&](int j) { return b[j * S + o]; };
+    constexpr int NT_ = DIM == 2 ? N : 1;
+    double tl[NT_], th[NT_];
+    if (below) {
+      trace<false>(axis, own, tl);
+      trace<true>(axis, nbr, th);
+    } else {
+      trace<false>(axis, nbr, tl);
+      trace<true>(axis, own, th);
+    }
+    if constexpr (DIM == 1) {
+      g[0] = llf(A.vx, tl[0], th[0]);
+    } else {
+      double v[Q];
+      line_velocity(A, axis, axis == 0 ? iy : ix, v);
+      // a boundary face under BC_RIEMANN reads the exterior state at its
+      // nodes from the neighbour's slot
+      bool xb = false;
+      if constexpr (XBC && FLUX == FLUX_BURGERS) {
+        if (A.bc_kind == BC_RIEMANN)
+          xb = f == 0 ? ix == 0 : f == 1 ? ix == A.nx - 1 : f == 2 ? iy == 0 : iy == A.ny - 1;
+      }
+      face_moments<XBC>(axis, tl, th, v, xb && !below, xb && below, b + o, g);
+    }
+  }
+
+  // Volume minus face terms of the weak form (R) and the cell's wave speed
+  // lambda_e (before the override); the faces in the order -x, +x, -y, +y.
+  // FACES = false: the volume terms only (a tile's shared faces are added
+  // by the caller, in the same order).
+  template <bool XBC = false, bool FACES = true>
   __device__ static inline void residual(const StageArgs& A, const double* b, const double (&c)[NL], int ix, int iy,
                                          double (&R)[NL], double& lam) {
-    const double hh = 0.5 * A.h;
-    const double xc = A.x0 + (ix + 0.5) * A.h;
-    const double yc = DIM == 2 ? A.y0 + (iy + 0.5) * A.h : 0.0;
 #pragma unroll
     for (int j = 0; j < NL; ++j) R[j] = 0.0;
-
     if constexpr (DIM == 1) {
-      // ---- volume
       double umax = 0.0;
 #pragma unroll
       for (int qn = 0; qn < Q; ++qn) {
@@ -447,39 +685,13 @@ struct Cell {
         for (int a = 1; a < N; ++a) R[a] = fma(TB::nd.D[a][qn], wF, R[a]);
       }
       lam = FLUX == FLUX_LINADV ? fabs(A.vx) : A.anorm * umax;
-      // ---- faces
-#pragma unroll
-      for (int f = 0; f < 2; ++f) {
-        double um = 0.0, up = 0.0;
-#pragma unroll
-        for (int a = 0; a < N; ++a) {
-          const double so = f ? 1.0 : TB::dg.sgn[a];  // P_a(s)
-          const double sn = f ? TB::dg.sgn[a] : 1.0;  // P_a(-s)
-          um = fma(so, c[a], um);
-          up = fma(sn, b[a * S + off(f)], up);
-        }
-        const double H = llf(A, f ? 1.0 : -1.0, A.vx, um, up);
-#pragma unroll
-        for (int a = 0; a < N; ++a) R[a] = fma(f ? -1.0 : -TB::dg.sgn[a], H, R[a]);
-      }
     } else {
-      // normal velocity components along the node lines (linear flux):
-      // v_x depends on y only, v_y on x only
+      // velocity components along the node lines (linear flux): v_x depends
+      // on y only, v_y on x only
       double vxl[Q], vyl[Q];
-      if constexpr (FLUX == FLUX_LINADV) {
-#pragma unroll
-        for (int k = 0; k < Q; ++k) {
-          vxl[k] = A.vx - A.omega * (fma(hh, TB::nd.x[k], yc) - A.cy);
-          vyl[k] = A.vy + A.omega * (fma(hh, TB::nd.x[k], xc) - A.cx);
-        }
-      } else {
-#pragma unroll
-        for (int k = 0; k < Q; ++k) {
-          vxl[k] = A.vx;
-          vyl[k] = A.vy;
-        }
-      }
-      // ---- volume  int grad(phi) . F(u_h), sum factorised over x nodes
+      line_velocity(A, 0, iy, vxl);
+      line_velocity(A, 1, ix, vyl);
+      // int grad(phi) . F(u_h), sum factorised over x nodes
       double umax = 0.0;
 #pragma unroll
       for (int qx = 0; qx < Q; ++qx) {
@@ -544,65 +756,13 @@ struct Cell {
       } else {
         lam = A.anorm * umax;
       }
-      // ---- faces  - int_dK phi H(u^-, u^+, n)
+    }
+    if constexpr (FACES) {
 #pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        const int axis = f >> 1;
-        const bool plus = f & 1;
-        const double s = plus ? 1.0 : -1.0;
-        // a boundary face under BC_RIEMANN reads u^+ at its nodes from the slot
-        bool xb = false;
-        if constexpr (XBC && FLUX == FLUX_BURGERS) {
-          if (A.bc_kind == BC_RIEMANN)
-            xb = f == 0 ? ix == 0 : f == 1 ? ix == A.nx - 1 : f == 2 ? iy == 0 : iy == A.ny - 1;
-        }
-        double tm[N], tp[N];
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-          double t = 0.0, tn = 0.0;
-#pragma unroll
-          for (int i = 0; i < N; ++i) {
-            const int j = axis == 0 ? i + N * k : k + N * i;
-            const double so = plus ? 1.0 : TB::dg.sgn[i];
-            const double sn = plus ? TB::dg.sgn[i] : 1.0;
-            t = fma(so, c[j], t);
-            tn = fma(sn, b[j * S + off(f)], tn);
-          }
-          tm[k] = t;
-          tp[k] = tn;
-        }
-        double g[N];
-#pragma unroll
-        for (int r = 0; r < Q; ++r) {
-          double um = tm[0], up = tp[0];
-#pragma unroll
-          for (int k = 1; k < N; ++k) {
-            um = fma(tm[k], TB::nd.L[k][r], um);
-            up = fma(tp[k], TB::nd.L[k][r], up);
-          }
-          if constexpr (XBC && FLUX == FLUX_BURGERS) {
-            if (xb) up = b[r * S + off(f)];
-          }
-          const double vax = axis == 0 ? vxl[r] : vyl[r];
-          double H;
-          if constexpr (FLUX == FLUX_KPP)
-            H = llf_kpp(axis, s, um, up);
-          else
-            H = llf(A, s, vax, um, up);
-#pragma unroll
-          for (int k = 0; k < N; ++k) {
-            const double cw = TB::nd.w[r] * TB::nd.L[k][r];
-            g[k] = r == 0 ? cw * H : fma(cw, H, g[k]);
-          }
-        }
-#pragma unroll
-        for (int k = 0; k < N; ++k)
-#pragma unroll
-          for (int i = 0; i < N; ++i) {
-            const int j = axis == 0 ? i + N * k : k + N * i;
-            const double so = plus ? 1.0 : TB::dg.sgn[i];
-            R[j] = fma(-so, g[k], R[j]);
-          }
+      for (int f = 0; f < NF; ++f) {
+        double g[DIM == 2 ? N : 1];
+        cell_face<XBC>(A, b, c, ix, iy, f, g);
+        add_face(f, g, R);
       }
     }
   }
@@ -613,11 +773,11 @@ struct Cell {
   //   v[0] the sensor (eqs. sensor/gensensor): gamma_e >= 1 (min(1, ratio) at
   //        its cap) and gamma_e == 0 (below the threshold b);
   //   v[1] lambda_e of eq. (visc) for Burgers: the volume node of the largest
-  //        |u| (strict running maximum, as in residual) and the sign of u there;
+  //        |u| (strict running maximum, as in volume) and the sign of u there;
   //   v[2] the LLF wave speed for Burgers (Sec. 2): at every face node which
-  //        of |u^-|, |u^+| is larger, and their signs.
+  //        of |u_below|, |u_above| is larger, and their signs.
   // The node values and traces are computed with the same explicit fma chains
-  // as residual(), so the decisions are those of the operator itself.  The
+  // as the operator (trace, face_node), so the decisions are its own.  The
   // linear flux has no such point in U (its wave speeds depend on x only).
   __device__ static inline void branches(const StageArgs& A, const double* b, const double (&c)[NL], double gam,
                                          uint32_t (&v)[3]) {
@@ -664,46 +824,33 @@ struct Cell {
         }
       }
       v[1] = fold(v[1], arg | (sgn << 16));
-      // faces: the traces and node values of residual()'s face loop
+      // faces: the traces and node values of cell_face
+      auto rec = [&](double ul, double uh) {
+        v[2] = fold(v[2], (fabs(ul) > fabs(uh) ? 1u : 0u) | (ul < 0.0 ? 2u : 0u) | (uh < 0.0 ? 4u : 0u));
+      };
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
-        const bool plus = f & 1;
-        if constexpr (DIM == 1) {
-          double um = 0.0, up = 0.0;
-#pragma unroll
-          for (int a = 0; a < N; ++a) {
-            const double so = f ? 1.0 : TB::dg.sgn[a];
-            const double sn = f ? TB::dg.sgn[a] : 1.0;
-            um = fma(so, c[a], um);
-            up = fma(sn, b[a * S + off(f)], up);
-          }
-          v[2] = fold(v[2], (fabs(um) > fabs(up) ? 1u : 0u) | (um < 0.0 ? 2u : 0u) | (up < 0.0 ? 4u : 0u));
+        const bool below = f & 1;
+        const int axis = f >> 1;
+        auto own = [&](int j) { return c[j]; };
+        auto nbr = [&](int j) { return b[j * S + off(f)]; };
+        constexpr int NT_ = DIM == 2 ? N : 1;
+        double tl[NT_], th[NT_];
+        if (below) {
+          trace<false>(axis, own, tl);
+          trace<true>(axis, nbr, th);
         } else {
-          const int axis = f >> 1;
-          double tm[N], tp[N];
-#pragma unroll
-          for (int k = 0; k < N; ++k) {
-            double t = 0.0, tn = 0.0;
-#pragma unroll
-            for (int i = 0; i < N; ++i) {
-              const int j = axis == 0 ? i + N * k : k + N * i;
-              const double so = plus ? 1.0 : TB::dg.sgn[i];
-              const double sn = plus ? TB::dg.sgn[i] : 1.0;
-              t = fma(so, c[j], t);
-              tn = fma(sn, b[j * S + off(f)], tn);
-            }
-            tm[k] = t;
-            tp[k] = tn;
-          }
+          trace<false>(axis, nbr, tl);
+          trace<true>(axis, own, th);
+        }
+        if constexpr (DIM == 1) {
+          rec(tl[0], th[0]);
+        } else {
 #pragma unroll
           for (int r = 0; r < Q; ++r) {
-            double um = tm[0], up = tp[0];
-#pragma unroll
-            for (int k = 1; k < N; ++k) {
-              um = fma(tm[k], TB::nd.L[k][r], um);
-              up = fma(tp[k], TB::nd.L[k][r], up);
-            }
-            v[2] = fold(v[2], (fabs(um) > fabs(up) ? 1u : 0u) | (um < 0.0 ? 2u : 0u) | (up < 0.0 ? 4u : 0u));
+            double ul, uh;
+            face_node(tl, th, r, ul, uh);
+            rec(ul, uh);
           }
         }
       }
@@ -843,7 +990,10 @@ __device__ inline void load_slot(const StageArgs& A, double* lds, int slot, int 
 // coefficient-major LDS tile (NL * S doubles) for its neighbours; the first
 // threads also load the halo ring.  After one barrier each thread evaluates
 // its cell from registers (own) and LDS (face neighbours), reads U^n of its
-// cell and writes the RK combination straight to HBM.
+// cell and writes the RK combination straight to HBM.  Tiles that share
+// faces (shares_faces) first evaluate every face once into LDS (a second
+// barrier); the cells then add their faces' moments in the order of the
+// per-cell evaluation, so the result is the same bit for bit.
 // XBC: compile the BC_RIEMANN exterior state in (2D Burgers per-stage kernel).
 template <int DIM, int P, int FLUX, int MODE, int TX, int TY, bool XBC = false>
 __device__ inline void stage_tile(const StageArgs& A, double* lds, int ix0, int iy0) {
@@ -880,9 +1030,66 @@ __device__ inline void stage_tile(const StageArgs& A, double* lds, int ix0, int 
 #pragma unroll
   for (int j = 0; j < NL; ++j) lds[j * S + sc] = c[j];
   tile_barrier();
+  constexpr bool SHARE = shares_faces(DIM, P, FLUX, TX, TY);
+  using FG = FaceGeom<TX, TY>;
+  constexpr int N = P + 1;
+  double* const fxl = lds + NL * S;      // shared x faces (SHARE)
+  double* const fyl = fxl + N * FG::XS;  // shared y faces
+  if constexpr (SHARE) {
+    // face phase: every x face of the tile, then every y face, one per
+    // thread and round (face_task); the two waves that take the faces left
+    // over change with the tile, so that no SIMD takes them on every tile
+    constexpr int NT = TX * TY, NW = NT / 64;
+    static_assert(NT % 64 == 0 && FG::NXF - NT <= 64 && FG::NYF - NT <= 64, "one extra round of faces");
+    auto face = [&](int axis, int e) {
+      int fgx, fgy;
+      const int lo = face_slot<TX, TY>(axis, e, ix0, iy0, fgx, fgy);
+      const int hi = lo + (axis == 0 ? 1 : G::W);
+      double tl[N], th[N], v[C::Q], g[N];
+      C::template trace<false>(axis, [&](int j) { return lds[j * S + lo]; }, tl);
+      C::template trace<true>(axis, [&](int j) { return lds[j * S + hi]; }, th);
+      C::line_velocity(A, axis, opaque(axis == 0 ? fgy : fgx), v);
+      bool xl = false, xh = false;
+      if constexpr (XBC) {
+        if (xbc) {
+          const int l = axis == 0 ? fgx : fgy, n = axis == 0 ? nx : ny;
+          xl = l == -1;
+          xh = l == n - 1;
+        }
+      }
+      C::template face_moments<XBC>(axis, tl, th, v, xl, xh, lds + (xl ? lo : hi), g);
+      double* dst = axis == 0 ? fxl + e : fyl + e;
+#pragma unroll
+      for (int k = 0; k < N; ++k) dst[k * (axis == 0 ? FG::XS : FG::YS)] = g[k];
+    };
+    const int rot = (int)(((unsigned)ix0 / TX + (unsigned)iy0 / TY) % NW);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      int e;
+      if (face_task<TX, TY>(t, rot, k, e)) face(k & 1, e);
+    }
+    tile_barrier();
+  }
   if (active) {
     double L[NL], gam;
-    C::template rhs<true, XBC>(A, lds + sc, c, gx, gy, L, gam);
+    if constexpr (SHARE) {
+      gam = C::template gamma_of<true>(A, lds + sc, c, gx, gy);
+      double R[NL], lam;
+      C::template residual<false, false>(A, lds + sc, c, gx, gy, R, lam);
+      const int lx = t % TX, ly = t / TX;
+      const int ex = ly * (TX + 1) + lx, ey = ly * TX + lx;
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        const double* src = f < 2 ? fxl + ex + (f & 1) : fyl + ey + (f & 1) * TX;
+        double g[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) g[k] = src[k * (f < 2 ? FG::XS : FG::YS)];
+        C::add_face(f, g, R);
+      }
+      C::finish(A, c, gam, lam, R, L);
+    } else {
+      C::template rhs<true, XBC>(A, lds + sc, c, gx, gy, L, gam);
+    }
     if (A.gamma) A.gamma[cell] = gam;
     double* dst = A.out + cell * NL;
     if (A.rhs_only) {
@@ -904,12 +1111,14 @@ __device__ inline void stage_tile(const StageArgs& A, double* lds, int ix0, int 
   }
 }
 
-// The fused stage kernel.  Grid: (ceil(nx/TX), ceil(ny/TY)), one tile each.
+// The fused stage kernel.  Grid: (ceil(nx/TX), ceil(ny/TY)), one tile each,
+// in the XCD-aware order of xcd_tile.
 template <int DIM, int P, int FLUX, int MODE, int TX, int TY>
 __global__ void __launch_bounds__(DIM == 2 ? TX * TY : TX) stage_kernel(const StageArgs A) {
   extern __shared__ double lds[];
-  stage_tile<DIM, P, FLUX, MODE, TX, TY, DIM == 2 && FLUX == FLUX_BURGERS>(A, lds, blockIdx.x * TX,
-                                                                         DIM == 2 ? blockIdx.y * TY : 0);
+  const int tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int bx = tile % gridDim.x, by = tile / gridDim.x;
+  stage_tile<DIM, P, FLUX, MODE, TX, TY, DIM == 2 && FLUX == FLUX_BURGERS>(A, lds, bx * TX, DIM == 2 ? by * TY : 0);
 }
 
 // Branch records of the stage input (Cell::branches) of every cell, folded
@@ -1144,8 +1353,8 @@ __device__ inline void step_stage(const StageArgs& A, const double* tin, const d
   }
 }
 
-// The fused step kernel.  Grid: (ceil(nx/TX), ceil(ny/TY)); StepGeom::NT
-// threads; LDS: step_lds_doubles.  A.uin = U^n, A.out = U^(n+1), two
+// The fused step kernel.  Grid: (ceil(nx/TX), ceil(ny/TY)), tiles in the
+// order of xcd_tile; StepGeom::NT threads; LDS: step_lds_doubles.  A.uin = U^n, A.out = U^(n+1), two
 // different arrays (tiles run concurrently and read U^n of their neighbours).
 template <int DIM, int P, int FLUX, int MODE, int TX, int TY>
 __global__ void __launch_bounds__(step_threads(DIM, TX, TY)) step_kernel(const StageArgs A) {
@@ -1156,7 +1365,8 @@ __global__ void __launch_bounds__(step_threads(DIM, TX, TY)) step_kernel(const S
   double* tb = ta + NL * G::A::S;
   double* tc = tb + NL * G::B::S;
   double* gx = tc + NL * G::C::S;  // gamma of the split cells of a stage (NT / 2)
-  const int ix0 = blockIdx.x * TX, iy0 = DIM == 2 ? blockIdx.y * TY : 0;
+  const int tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int ix0 = (tile % gridDim.x) * TX, iy0 = DIM == 2 ? (tile / gridDim.x) * TY : 0;
   // U^n on the tile and three rings
 #pragma unroll 1
   for (int o = threadIdx.x; o < G::A::N; o += G::NT) {

@@ -18,7 +18,7 @@ template <int FLUX, int MODE, int TX, int TY>
 hipError_t launch_tile(const StageArgs& A, hipStream_t st) {
   constexpr int NL = DGK_DIM == 1 ? DGK_P + 1 : (DGK_P + 1) * (DGK_P + 1);
   auto k = stage_kernel<DGK_DIM, DGK_P, FLUX, MODE, TX, TY>;
-  const size_t lds = sizeof(double) * (size_t)tile_lds_doubles(DGK_DIM, NL, TX, TY);
+  const size_t lds = sizeof(double) * (size_t)stage_lds_doubles(DGK_DIM, NL, FLUX, TX, TY);
   if (lds > 65536) {
     // tiles above 64 KB of LDS: raise the per-kernel limit to what this launch needs
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
@@ -80,7 +80,7 @@ template <int FLUX, int MODE, int TX, int TY>
 hipError_t launch_batch_tile(const BatchStageArgs& B, int grid, hipStream_t st) {
   constexpr int NL = DGK_DIM == 1 ? DGK_P + 1 : (DGK_P + 1) * (DGK_P + 1);
   auto k = batch_stage_kernel<DGK_DIM, DGK_P, FLUX, MODE, TX, TY>;
-  const size_t lds = sizeof(double) * (size_t)tile_lds_doubles(DGK_DIM, NL, TX, TY);
+  const size_t lds = sizeof(double) * (size_t)stage_lds_doubles(DGK_DIM, NL, FLUX, TX, TY);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -70,6 +70,79 @@ void check(int nx, int ny, int per_x, int per_y) {
       }
 }
 
+// The shared faces of a 2D tile (shares_faces): for every rotation of the
+// leftover waves each face is evaluated by exactly one thread of the face
+// phase; the slots below and above each face lie inside the tile and are no
+// corner slots (those hold no loaded state); the face's lower cell and its
+// slot agree; the face moments stay inside the LDS the launch allocates; and
+// each tile cell's four faces are the faces whose upper (-x, -y) or lower
+// (+x, +y) slot is the cell's own slot.
+template <int TX, int TY>
+void check_faces(int nl, int flux) {
+  using G = TileGeom<2, TX, TY>;
+  using FG = FaceGeom<TX, TY>;
+  constexpr int NT = TX * TY, NW = NT / 64;
+  int n = 1;
+  while (n * n < nl) ++n;
+  if (!shares_faces(2, n - 1, flux, TX, TY)) return;
+  const long long lds = stage_lds_doubles(2, nl, flux, TX, TY);
+  CHECK(lds == tile_lds_doubles(2, nl, TX, TY) + (long long)n * (FG::XS + FG::YS), "faces: LDS size");
+  auto corner = [&](int s) {
+    const int x = s % G::W, y = s / G::W;
+    return (x == 0 || x == G::W - 1) && (y == 0 || y == G::H - 1);
+  };
+  for (int rot = 0; rot < NW; ++rot) {
+    std::vector<int> cx(FG::NXF, 0), cy(FG::NYF, 0);
+    for (int t = 0; t < NT; ++t)
+      for (int k = 0; k < 4; ++k) {
+        int e;
+        if (!face_task<TX, TY>(t, rot, k, e)) continue;
+        if (k & 1) {
+          CHECK(e >= 0 && e < FG::NYF, "faces: y face %d out of range", e);
+          if (e >= 0 && e < FG::NYF) cy[e]++;
+        } else {
+          CHECK(e >= 0 && e < FG::NXF, "faces: x face %d out of range", e);
+          if (e >= 0 && e < FG::NXF) cx[e]++;
+        }
+      }
+    for (int e = 0; e < FG::NXF; ++e) CHECK(cx[e] == 1, "faces: x face %d evaluated %d times (rot %d)", e, cx[e], rot);
+    for (int e = 0; e < FG::NYF; ++e) CHECK(cy[e] == 1, "faces: y face %d evaluated %d times (rot %d)", e, cy[e], rot);
+    // the leftover rounds: whole waves (one wave each), never wave-divergent
+    for (int k = 2; k < 4; ++k)
+      for (int w = 0; w < NW; ++w) {
+        int any = 0, e;
+        for (int l = 0; l < 64; ++l) any += (face_task<TX, TY>(w * 64 + l, rot, k, e) ? 1 : 0);
+        CHECK(any == 0 || w == (k == 2 ? rot : (rot + NW / 2) % NW), "faces: round %d on wave %d", k, w);
+      }
+  }
+  const int ix0 = 3 * TX, iy0 = 5 * TY;
+  for (int axis = 0; axis < 2; ++axis)
+    for (int e = 0; e < (axis ? FG::NYF : FG::NXF); ++e) {
+      int gx, gy;
+      const int lo = face_slot<TX, TY>(axis, e, ix0, iy0, gx, gy);
+      const int hi = lo + (axis ? G::W : 1);
+      CHECK(lo >= 0 && hi < G::NS && !corner(lo) && !corner(hi), "faces: axis %d face %d slots %d %d", axis, e, lo, hi);
+      CHECK(gx == ix0 - 1 + lo % G::W && gy == iy0 - 1 + lo / G::W, "faces: lower cell of face %d", e);
+      const long long base = (long long)nl * G::S + (axis ? (long long)n * FG::XS : 0);
+      const int st = axis ? FG::YS : FG::XS;
+      CHECK(base + (long long)(n - 1) * st + e < lds, "faces: moments of face %d outside LDS", e);
+    }
+  for (int t = 0; t < NT; ++t) {
+    int sc, gx, gy, hs, hgx, hgy;
+    tile_slots<2, TX, TY>(t, ix0, iy0, sc, gx, gy, hs, hgx, hgy);
+    const int lx = t % TX, ly = t / TX, ex = ly * (TX + 1) + lx, ey = ly * TX + lx;
+    int fx, fy, s;
+    s = face_slot<TX, TY>(0, ex, ix0, iy0, fx, fy);
+    CHECK(s + 1 == sc, "faces: -x face of cell %d", t);
+    s = face_slot<TX, TY>(0, ex + 1, ix0, iy0, fx, fy);
+    CHECK(s == sc && fx == gx && fy == gy, "faces: +x face of cell %d", t);
+    s = face_slot<TX, TY>(1, ey, ix0, iy0, fx, fy);
+    CHECK(s + G::W == sc, "faces: -y face of cell %d", t);
+    s = face_slot<TX, TY>(1, ey + TX, ix0, iy0, fx, fy);
+    CHECK(s == sc && fx == gx && fy == gy, "faces: +y face of cell %d", t);
+  }
+}
+
 // The fused step kernel: tile A loads U^n on the tile and three rings (each
 // slot from the cell it stands for, wrapped or exterior); every stage's
 // output slot maps to the same mesh cell in its input tile and in tile A, its
@@ -216,6 +289,7 @@ void check_batch_class(const std::vector<BatchProblemDesc>& pd, const std::vecto
   using G = TileGeom<DIM, TX, TY>;
   const int nl = m[probs[0]].nl();
   const long long lds = tile_lds_doubles(DIM, nl, TX, TY);
+  CHECK(stage_lds_doubles(DIM, nl, m[probs[0]].flux, TX, TY) >= lds, "batch: stage LDS below the tile");
   const long long cap = batch_tile_capacity(m, probs);
   const long long total = off.back();
   std::vector<BatchTile> base, list;
@@ -318,13 +392,31 @@ int check_batch(const char* path) {
       check_batch_class<1, 64, 1>(pd, m, off, probs);
     } else {
       // the 16x16 tile where its LDS fits the 64 KB a workgroup gets by default
-      if (tile_lds_doubles(2, nl, 16, 16) * 8 <= 65536) check_batch_class<2, 16, 16>(pd, m, off, probs);
+      if (stage_lds_doubles(2, nl, c0.flux, 16, 16) * 8 <= 65536) check_batch_class<2, 16, 16>(pd, m, off, probs);
       check_batch_class<2, 8, 8>(pd, m, off, probs);
     }
   }
   CHECK(members == m.size(), "batch: %zu problems in classes, %zu given", members, m.size());
   std::printf("batch: %zu problems, %zu classes, %lld doubles\n", m.size(), classes.size(), off.back());
   return 0;
+}
+
+// xcd_tile is a bijection of [0, g) for every grid size, and each XCD's
+// workgroups take one contiguous, increasing run of tiles.
+void check_xcd_order() {
+  for (int g = 1; g <= 5000; g += (g < 300 ? 1 : 37)) {
+    std::vector<int> seen(g, 0), last(kXcds, -1);
+    for (int k = 0; k < g; ++k) {
+      const int t = xcd_tile(k, g);
+      CHECK(t >= 0 && t < g, "xcd order: tile %d of %d", t, g);
+      if (t < 0 || t >= g) continue;
+      seen[t]++;
+      const int x = k % kXcds;
+      CHECK(last[x] < 0 || t == last[x] + 1, "xcd order: XCD %d jumps from tile %d to %d (g %d)", x, last[x], t, g);
+      last[x] = t;
+    }
+    for (int t = 0; t < g; ++t) CHECK(seen[t] == 1, "xcd order: tile %d taken %d times (g %d)", t, seen[t], g);
+  }
 }
 
 int main(int argc, char** argv) {
@@ -341,12 +433,22 @@ int main(int argc, char** argv) {
   check_split<1, kStepTile1D, 1, 0>();
   static_assert(split_full(256, 512) == 0 && split_full(324, 512) == 256 && split_full(400, 512) == 400,
                 "16x16 fused step: stage 3 splits every cell, stage 2 the cells past 256, stage 1 none");
+  check_xcd_order();
   sweep_step();
   sweep<1, 256, 1>();
   sweep<1, 64, 1>();
   sweep<2, 16, 16>();
   sweep<2, 8, 8>();
   sweep<2, kAdjTileX, kAdjTileY>();  // the adjoint kernels' 2D tile
+  for (int nl : {4, 9, 16, 25})
+    for (int flux : {FLUX_LINADV, FLUX_BURGERS, FLUX_KPP}) {
+      check_faces<16, 16>(nl, flux);
+      check_faces<8, 8>(nl, flux);
+    }
+  static_assert(shares_faces(2, 2, FLUX_BURGERS, 16, 16) && shares_faces(2, 2, FLUX_KPP, 16, 16) &&
+                    !shares_faces(2, 2, FLUX_LINADV, 16, 16) && !shares_faces(2, 3, FLUX_BURGERS, 16, 16) &&
+                    !shares_faces(2, 2, FLUX_BURGERS, 8, 8) && !shares_faces(1, 2, FLUX_BURGERS, 256, 1),
+                "shared faces: 2D 16x16 tiles, p = 2, Burgers and KPP");
   std::printf("%s (%d failures)\n", failures ? "FAIL" : "ok", failures);
   return failures ? 1 : 0;
 }
