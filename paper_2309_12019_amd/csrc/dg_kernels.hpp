@@ -285,8 +285,10 @@ struct Cell {
   }
 
   // c^T B c with the sensor's quadratic form (zero entries skipped at compile time)
+  // (the first term of every sum is a product: no zero to add to)
   __device__ static inline double qform(const double (&v)[NL]) {
     double acc = 0.0;
+    bool started = false;
 #pragma unroll
     for (int i = 1; i < NL; ++i) {
       double ri = 0.0;
@@ -299,19 +301,23 @@ struct Cell {
           any = true;
         }
       }
-      if (any) acc = fma(v[i], ri, acc);
+      if (any) {
+        acc = started ? fma(v[i], ri, acc) : v[i] * ri;
+        started = true;
+      }
     }
     return acc;
   }
 
   // neighbour f continued into this cell, in this cell's basis (non-constant
-  // coefficients only): P_a(xi -/+ 2) = sum_b T[s][a][b] P_b(xi)
+  // coefficients only): P_a(xi -/+ 2) = sum_b T[s][a][b] P_b(xi).  T[s][a][a]
+  // = 1 (equal leading coefficients), so coefficient c of a row starts as
+  // the neighbour's own coefficient c, and the higher ones add to it.
   template <int F>
   __device__ static inline void candidate(const double* b, double (&cd)[NL]) {
     constexpr int si = F & 1;
     constexpr int o = off(F);
-#pragma unroll
-    for (int j = 0; j < NL; ++j) cd[j] = 0.0;
+    cd[0] = 0.0;  // the constant coefficient is not used
     if constexpr (DIM == 1 || F < 2) {
       constexpr int R = DIM == 1 ? 1 : N;
 #pragma unroll
@@ -322,7 +328,7 @@ struct Cell {
 #pragma unroll
           for (int c = 0; c <= a; ++c)
             if (TB::dg.T[si][a][c] != 0.0 && (c + N * e) != 0)
-              cd[c + N * e] = fma(TB::dg.T[si][a][c], cn, cd[c + N * e]);
+              cd[c + N * e] = c == a ? TB::dg.T[si][a][c] * cn : fma(TB::dg.T[si][a][c], cn, cd[c + N * e]);
         }
     } else {
 #pragma unroll
@@ -333,7 +339,7 @@ struct Cell {
 #pragma unroll
           for (int c = 0; c <= e; ++c)
             if (TB::dg.T[si][e][c] != 0.0 && (a + N * c) != 0)
-              cd[a + N * c] = fma(TB::dg.T[si][e][c], cn, cd[a + N * c]);
+              cd[a + N * c] = c == e ? TB::dg.T[si][e][c] * cn : fma(TB::dg.T[si][e][c], cn, cd[a + N * c]);
         }
     }
   }
@@ -472,17 +478,18 @@ struct Cell {
   // the cell below (P_i(+1) = 1).  coef(j) returns coefficient j.
   template <bool UPPER, class Coef>
   __device__ static inline void trace(int axis, Coef coef, double (&t)[DIM == 2 ? N : 1]) {
+    // (P_0 = 1 at both ends: the sum starts with the i = 0 coefficient)
     if constexpr (DIM == 1) {
-      double acc = 0.0;
+      double acc = coef(0);
 #pragma unroll
-      for (int a = 0; a < N; ++a) acc = fma(UPPER ? TB::dg.sgn[a] : 1.0, coef(a), acc);
+      for (int a = 1; a < N; ++a) acc = fma(UPPER ? TB::dg.sgn[a] : 1.0, coef(a), acc);
       t[0] = acc;
     } else {
 #pragma unroll
       for (int k = 0; k < N; ++k) {
-        double acc = 0.0;
+        double acc = coef(axis == 0 ? N * k : k);
 #pragma unroll
-        for (int i = 0; i < N; ++i)
+        for (int i = 1; i < N; ++i)
           acc = fma(UPPER ? TB::dg.sgn[i] : 1.0, coef(axis == 0 ? i + N * k : k + N * i), acc);
         t[k] = acc;
       }
@@ -664,9 +671,10 @@ struct Cell {
   template <bool XBC = false, bool FACES = true>
   __device__ static inline void residual(const StageArgs& A, const double* b, const double (&c)[NL], int ix, int iy,
                                          double (&R)[NL], double& lam) {
-#pragma unroll
-    for (int j = 0; j < NL; ++j) R[j] = 0.0;
+    // (every sum starts with a product: R is assigned, not cleared, at the
+    // first node)
     if constexpr (DIM == 1) {
+      R[0] = 0.0;
       double umax = 0.0;
 #pragma unroll
       for (int qn = 0; qn < Q; ++qn) {
@@ -682,7 +690,7 @@ struct Cell {
         }
         const double wF = TB::nd.w[qn] * F;
 #pragma unroll
-        for (int a = 1; a < N; ++a) R[a] = fma(TB::nd.D[a][qn], wF, R[a]);
+        for (int a = 1; a < N; ++a) R[a] = qn == 0 ? TB::nd.D[a][qn] * wF : fma(TB::nd.D[a][qn], wF, R[a]);
       }
       lam = FLUX == FLUX_LINADV ? fabs(A.vx) : A.anorm * umax;
     } else {
@@ -691,8 +699,11 @@ struct Cell {
       double vxl[Q], vyl[Q];
       line_velocity(A, 0, iy, vxl);
       line_velocity(A, 1, ix, vyl);
-      // int grad(phi) . F(u_h), sum factorised over x nodes
+      // int grad(phi) . F(u_h), sum factorised over x nodes.  Burgers: the
+      // node sums take u^2, and the factors v_x / 2, v_y / 2 are applied once
+      // per x node
       double umax = 0.0;
+      const double hvx = 0.5 * A.vx, hvy = 0.5 * A.vy;
 #pragma unroll
       for (int qx = 0; qx < Q; ++qx) {
         double s1[N];
@@ -716,9 +727,8 @@ struct Cell {
           } else if constexpr (FLUX == FLUX_KPP) {
             sincos_cold(u, &Fx, &Fy);
           } else {
-            const double hu2 = 0.5 * u * u;
-            Fx = A.vx * hu2;
-            Fy = A.vy * hu2;
+            Fx = u * u;
+            Fy = Fx;
             umax = fmax(umax, fabs(u));
           }
 #pragma unroll
@@ -731,14 +741,29 @@ struct Cell {
             }
           }
         }
+        if constexpr (FLUX == FLUX_BURGERS) {
+#pragma unroll
+          for (int bb = 0; bb < N; ++bb) {
+            gx[bb] *= hvx;
+            if (bb > 0) gy[bb] *= hvy;
+          }
+        }
         const double wq = TB::nd.w[qx];
 #pragma unroll
         for (int bb = 0; bb < N; ++bb)
 #pragma unroll
           for (int a = 0; a < N; ++a) {
-            double t = R[a + N * bb];
-            if (a > 0) t = fma(wq * TB::nd.D[a][qx], gx[bb], t);
-            if (bb > 0) t = fma(wq * TB::nd.L[a][qx], gy[bb], t);
+            double t = qx == 0 ? 0.0 : R[a + N * bb];
+            bool started = qx > 0;
+            if (a > 0) {
+              const double k = wq * TB::nd.D[a][qx];
+              t = started ? fma(k, gx[bb], t) : k * gx[bb];
+              started = true;
+            }
+            if (bb > 0) {
+              const double k = wq * TB::nd.L[a][qx];
+              t = started ? fma(k, gy[bb], t) : k * gy[bb];
+            }
             R[a + N * bb] = t;
           }
       }
