@@ -48,6 +48,8 @@ def workload(name):
         "rot2d_2048_p2": lambda: inputs.rot2d(2048, 2, seed=0, steps=50),
         # the rotation at a bandwidth-bound size (per-stage kernel, 9.4 M DOFs)
         "rot2d_1024_p2": lambda: inputs.rot2d(1024, 2, seed=0, steps=100),
+        # degree 3 on the per-stage kernel (16 M DOFs)
+        "rot2d_1024_p3": lambda: inputs.rot2d(1024, 3, seed=0, steps=50),
         # the sensor of Zhao et al. (Sec. 5.6) in place of eq. (sensor)
         "rot2d_256_p2_zhao": lambda: inputs.rot2d(256, 2, seed=0, steps=200, mode=inputs.MODE_ZHAO),
         # the KPP problem of Sec. 5.5 at the paper's size (128^2, P2, lambda_e = 2, t = 1)
@@ -73,7 +75,7 @@ def workload(name):
 # (rocprofv3 SQ_INSTS_VALU_{FMA,ADD,MUL,TRANS}_F64 per wave, one lane per
 # cell, FMA counted twice; profiles/stage_kernel_hbm_counters.md): the
 # per-unit figure of the arithmetic roofline.  Keyed by (dim, p, flux, mode).
-FLOPS_PER_CELL_STAGE = {(2, 2, 0, 2): 1160.0, (2, 3, 0, 2): 2376.0, (2, 2, 1, 2): 1415.0}
+FLOPS_PER_CELL_STAGE = {(2, 2, 0, 2): 1088.0, (2, 3, 0, 2): 2376.0, (2, 2, 1, 2): 1146.0}
 FP64_PEAK_TFLOPS = 78.6
 
 
