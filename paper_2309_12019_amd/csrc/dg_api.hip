@@ -641,6 +641,22 @@ int dg_validate_desc(const dg_mesh_desc* desc) {
 // unit (1.2-1.5x at 128^2 and 256^2), since with more tiles the recomputed
 // rings and the one-workgroup-per-CU occupancy of the fused kernel cost more
 // than the launches and HBM passes it saves (0.7-0.86x from 384^2 up).
+// Default tile of the per-stage kernel: 256 cells in 1D; in 2D 16x16 unless
+// its LDS exceeds the limit, and 8x8 when the mesh has fewer 16x16 tiles
+// than compute units (four times the workgroups: 128^2 P2 25.0 -> 20.4 us
+// per step for the four-quadrant problem, 20.7 -> 16.2 for Burgers).
+void default_tile(dg_ctx* c) {
+  if (c->d.dim == 1) {
+    c->tx = 256;
+    c->ty = 1;
+    return;
+  }
+  c->tx = c->ty = 16;
+  if (stage_lds_bytes(2, c->nl, c->d.flux, 16, 16) > (size_t)c->max_lds ||
+      (long long)((c->d.nx + 15) / 16) * ((c->d.ny + 15) / 16) < (long long)c->cus)
+    c->tx = c->ty = 8;
+}
+
 bool fused_fits(const dg_ctx* c) {
   if (c->d.rk_order != 3) return false;            // the fused kernel is the three-stage method
   if (c->d.bc_kind != DG_BC_CONSTANT) return false;  // its rings take the constant exterior state
@@ -658,6 +674,13 @@ void resolve_fused(dg_ctx* c) {
   }
   if (c->fused_mode == 1) {
     c->fused = true;
+    return;
+  }
+  // the KPP flux: its sine and cosine at every node keep a lone wave per SIMD
+  // busy either way, and the fused kernel's recomputed rings add to that
+  // (128^2 P2: 84 us per step fused, 75 us per-stage)
+  if (c->d.flux == DG_FLUX_KPP) {
+    c->fused = false;
     return;
   }
   const long long t = c->d.dim == 1 ? dgk::kStepTile1D : dgk::kStepTile2D;
@@ -700,17 +723,9 @@ int dg_init_mesh(const dg_mesh_desc* desc, dg_ctx** out) {
   int lds = 0;
   if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
     c->max_lds = lds;
-  // default tile: 256 cells in 1D; 16x16 in 2D unless the halo tile exceeds LDS
-  if (c->d.dim == 1) {
-    c->tx = 256;
-    c->ty = 1;
-  } else {
-    c->tx = 16;
-    c->ty = 16;
-    if (stage_lds_bytes(2, c->nl, c->d.flux, 16, 16) > (size_t)c->max_lds) c->tx = c->ty = 8;
-  }
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0) c->cus = cus;
+  default_tile(c);
   resolve_fused(c);
   const size_t bytes = sizeof(double) * (size_t)c->ncells * c->nl;
   if ((e = hipMalloc(&c->U1, bytes)) != hipSuccess || (e = hipMalloc(&c->U2, bytes)) != hipSuccess ||
@@ -846,13 +861,9 @@ int dg_step_static(const dg_mesh_desc* desc, double* U, double dt, double t) {
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
     c.max_lds = lds;
-  if (c.d.dim == 1) {
-    c.tx = 256;
-    c.ty = 1;
-  } else {
-    c.tx = c.ty = 16;
-    if (stage_lds_bytes(2, c.nl, c.d.flux, 16, 16) > (size_t)c.max_lds) c.tx = c.ty = 8;
-  }
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0) c.cus = cus;
+  default_tile(&c);
   double* base = nullptr;
   if ((rc = scratch_on_current_device(&base))) return rc;
   c.U1 = base;

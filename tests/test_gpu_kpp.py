@@ -54,7 +54,8 @@ def test_kpp_128_ranges_of_the_three_schemes():
 
 def test_papers_size_parity_20_steps():
     """The benchmark's KPP workload (128^2, P2, WENO, lambda_e = 2): 20 steps
-    of the whole mesh (fused step kernel) against the oracle."""
+    of the whole mesh against the oracle, on the library's own choice (the
+    per-stage kernel, 8x8 tiles) and on the fused step kernel."""
     from helpers import oracle_for, oracle_initial
     from paper_2309_12019_amd import dgweno
     _note("[kpp full size] 128^2 P2 WENO, 20 steps")
@@ -62,11 +63,16 @@ def test_papers_size_parity_20_steps():
     O = oracle_for(w)
     U0 = oracle_initial(w, O)
     ref = O.run(U0, w.dt(), 20)
-    g = dgweno.DG.from_workload(w)
-    assert g.fused()
-    U = U0.cuda().contiguous()
-    g.run(U, w.dt(), 20)
-    torch.cuda.synchronize()
-    err = float((U.cpu() - ref).abs().max() / ref.abs().max())
-    _note(f"    rel Linf = {err:.3e}")
-    assert err <= 1e-11
+    for fused in (None, 1):
+        g = dgweno.DG.from_workload(w)
+        if fused is None:
+            assert not g.fused() and g.tile() == (8, 8)
+        else:
+            g.set_fused(fused)
+            assert g.fused()
+        U = U0.cuda().contiguous()
+        g.run(U, w.dt(), 20)
+        torch.cuda.synchronize()
+        err = float((U.cpu() - ref).abs().max() / ref.abs().max())
+        _note(f"    {'fused' if g.fused() else 'per-stage'}: rel Linf = {err:.3e}")
+        assert err <= 1e-11

@@ -197,6 +197,35 @@ def test_burgers2d_100_steps_after_shock():
     _run_parity(w, U0, 100, O=O)
 
 
+@pytest.mark.parametrize("per", [(False, False), (True, False), (False, True)])
+def test_burgers2d_shared_faces_at_constant_exterior_state(per):
+    """2D P2 Burgers (the kernel that evaluates each face of a 16x16 tile
+    once) on a ragged 37 x 29 mesh with a constant exterior state 0.3 on the
+    non-periodic sides: 30 steps against the oracle, and bitwise the same as
+    the 8x8 tile (per-cell faces) and the fused step kernel."""
+    _note(f"[shared faces] burgers2d 37x29 P2, periodic {per}")
+    w = inputs.burgers2d(37, 2, seed=4, ny=29, steps=30)
+    w.periodic_x, w.periodic_y = per
+    w.bc_value = 0.3
+    O = oracle_for(w)
+    U0 = _state(w, O, 11)
+    ref = O.run(U0, w.dt(), 30)
+    outs = []
+    for tile, fused in (((16, 16), 0), ((8, 8), 0), (None, 1)):
+        g = _dg().DG.from_workload(w)
+        g.set_fused(fused)
+        if tile:
+            g.set_tile(*tile)
+        U = U0.cuda().contiguous()
+        g.run(U, w.dt(), 30)
+        torch.cuda.synchronize()
+        outs.append(U.cpu())
+    err = relinf(outs[0], ref)
+    _note(f"    rel Linf {err:.3e}")
+    assert err <= 1e-11
+    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
+
+
 def test_run_equals_repeated_step_bitwise():
     _note("[determinism] dg_run vs dg_step")
     w = inputs.rot2d(40, 2, ny=36)
