@@ -48,8 +48,11 @@ def test_kpp_128_ranges_of_the_three_schemes():
         assert dg.count_nonfinite(U) == 0
     assert got["DG"][0] < lo0 - 10 and got["DG"][1] > hi0 + 10
     assert got["LO"][0] >= lo0 - 1e-3 and got["LO"][1] <= hi0 + 1e-3
+    # WENO: here within the data range (the printed range overshoots it by
+    # 0.07 at the top); pinned as measured, so that an overshoot shows up
     pw = g["printed_range"]["WENO"]
-    assert got["WENO"][0] >= pw[0] - 1e-2 and got["WENO"][1] <= pw[1] + 1e-2
+    assert got["WENO"][0] >= lo0 - 1e-3 and got["WENO"][1] <= hi0 + 1e-3
+    assert pw[1] - got["WENO"][1] > 0.05
 
 
 def test_papers_size_parity_20_steps():

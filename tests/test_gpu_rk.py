@@ -213,14 +213,17 @@ def _table2_error(p, N, mode, k=3, lam=0.0):
 TABLE2 = json.load(open(os.path.join(HERE, "golden", "paper_tables.json")))["table2_burgers"]["rows"]
 
 
-@pytest.mark.parametrize("p,tol", [(1, 0.25), (2, 0.08), (3, 0.08)])
-def test_table2_on_the_gpu(p, tol):
+@pytest.mark.parametrize("p,band", [(1, (0.75, 0.90)), (2, (0.92, 1.08)), (3, (0.92, 1.08))])
+def test_table2_on_the_gpu(p, band):
     """Every row of Table 2 (Sec. 5.2, E_h = 16..2048; 512 for p = 3): the DG
-    errors within the oracle's tolerances of the printed ones and rates
-    within 0.3 of p + 1; the LO errors (global lambda = 1, as the oracle's
-    pins found) within 5 % and first order.  The p = 2 row at E_h = 16 is
-    left out, as in the oracle's pins: the paper's own rate from 16 to 32
-    cells there is 1.91, pre-asymptotic (the run here is 24 % above it)."""
+    error over the printed one within `band` and rates within 0.3 of p + 1;
+    the LO errors (global lambda = 1, as the oracle's pins found) within 5 %
+    and first order.  For p = 1 the DG errors are 0.79-0.86 of the printed
+    ones on every row, with the second- or third-order method and at CFL
+    0.05-0.3 alike: a difference in space that the paper does not specify;
+    the band pins that.  The p = 2 row at E_h = 16 is left out, as in the
+    oracle's pins: the paper's own rate from 16 to 32 cells there is 1.91,
+    pre-asymptotic (the run here is 24 % above it)."""
     sizes = [r["E_h"] for r in TABLE2 if r["p"] == p and not (p == 2 and r["E_h"] == 16)]
     dg, lo = [], []
     for N in sizes:
@@ -231,7 +234,7 @@ def test_table2_on_the_gpu(p, tol):
               f"LO {e_lo:.4e} (paper {row['LO']:.3e}, ratio {e_lo / row['LO']:.4f})")
         dg.append(e_dg)
         lo.append(e_lo)
-        assert abs(e_dg / row["DG"] - 1) < tol
+        assert band[0] < e_dg / row["DG"] < band[1]
         assert abs(e_lo / row["LO"] - 1) < 0.05
     for a, b in zip(dg, dg[1:]):
         assert abs(math.log2(a / b) - (p + 1)) < 0.3
