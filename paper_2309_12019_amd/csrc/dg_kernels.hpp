@@ -1137,13 +1137,16 @@ __device__ inline void stage_tile(const StageArgs& A, double* lds, int ix0, int 
 }
 
 // The fused stage kernel.  Grid: (ceil(nx/TX), ceil(ny/TY)), one tile each,
-// in the XCD-aware order of xcd_tile.
-template <int DIM, int P, int FLUX, int MODE, int TX, int TY>
+// in the XCD-aware order of xcd_tile.  XBC: the BC_RIEMANN exterior state
+// compiled in (2D Burgers; launched for that exterior state only, since the
+// checks cost every cell ~4 % of its instructions).
+template <int DIM, int P, int FLUX, int MODE, int TX, int TY, bool XBC = false>
 __global__ void __launch_bounds__(DIM == 2 ? TX * TY : TX) stage_kernel(const StageArgs A) {
   extern __shared__ double lds[];
   const int tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
   const int bx = tile % gridDim.x, by = tile / gridDim.x;
-  stage_tile<DIM, P, FLUX, MODE, TX, TY, DIM == 2 && FLUX == FLUX_BURGERS>(A, lds, bx * TX, DIM == 2 ? by * TY : 0);
+  stage_tile<DIM, P, FLUX, MODE, TX, TY, XBC && DIM == 2 && FLUX == FLUX_BURGERS>(A, lds, bx * TX,
+                                                                                DIM == 2 ? by * TY : 0);
 }
 
 // Branch records of the stage input (Cell::branches) of every cell, folded

@@ -14,10 +14,10 @@
 namespace dgk {
 namespace {
 
-template <int FLUX, int MODE, int TX, int TY>
+template <int FLUX, int MODE, int TX, int TY, bool XBC = false>
 hipError_t launch_tile(const StageArgs& A, hipStream_t st) {
   constexpr int NL = DGK_DIM == 1 ? DGK_P + 1 : (DGK_P + 1) * (DGK_P + 1);
-  auto k = stage_kernel<DGK_DIM, DGK_P, FLUX, MODE, TX, TY>;
+  auto k = stage_kernel<DGK_DIM, DGK_P, FLUX, MODE, TX, TY, XBC>;
   const size_t lds = sizeof(double) * (size_t)stage_lds_doubles(DGK_DIM, NL, FLUX, TX, TY);
   if (lds > 65536) {
     // tiles above 64 KB of LDS: raise the per-kernel limit to what this launch needs
@@ -37,6 +37,14 @@ hipError_t launch_stage_fm(const StageArgs& A, hipStream_t st) {
     if (A.tx == 64) return launch_tile<FLUX, MODE, 64, 1>(A, st);
     return launch_tile<FLUX, MODE, 256, 1>(A, st);
   } else {
+    // 2D Burgers: the kernel with the exact-solution exterior state only
+    // where it is needed
+    if constexpr (FLUX == FLUX_BURGERS) {
+      if (A.bc_kind == BC_RIEMANN) {
+        if (A.tx == 8) return launch_tile<FLUX, MODE, 8, 8, true>(A, st);
+        return launch_tile<FLUX, MODE, 16, 16, true>(A, st);
+      }
+    }
     if (A.tx == 8) return launch_tile<FLUX, MODE, 8, 8>(A, st);
     return launch_tile<FLUX, MODE, 16, 16>(A, st);
   }
