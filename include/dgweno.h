@@ -371,8 +371,9 @@ int dg_batch_run_sequential(dg_batch* batch, double* arena, const double* dts, i
 
 /* Schedule of class `cls` (0 <= cls < number of classes): tile shape (as in
  * dg_set_tile), persistent grid of grid_per_cu workgroups per compute unit
- * (1..64), and tile order (0: problems by decreasing size, 1: increasing,
- * 2: problems interleaved round robin). */
+ * (1..64; 0: one workgroup per tile, without the persistent loop), and tile
+ * order (0: problems by decreasing size, 1: increasing, 2: problems
+ * interleaved round robin).  DG_EINVAL outside those ranges. */
 int dg_batch_num_classes(const dg_batch* batch, int32_t* n);
 int dg_batch_set_schedule(dg_batch* batch, int32_t cls, int32_t tx, int32_t ty, int32_t grid_per_cu,
                           int32_t order);

@@ -129,6 +129,7 @@ int class_stage(dg_batch* b, Class& c, hipStream_t st, const double* uin, const 
   r.args.tx = c.tx;
   r.args.ty = c.ty;
   r.ncells = class_grid(b, c);
+  r.batch_one = c.grid_per_cu == 0;
   r.stream = st;
   r.batch.probs = b->d_probs;
   r.batch.tiles = c.d_tiles;
@@ -349,7 +350,8 @@ int dg_batch_set_schedule(dg_batch* b, int32_t cls, int32_t tx, int32_t ty, int3
   }
   if (!ok) return bfail(DG_EINVAL, "unsupported tile %dx%d", tx, ty);
   if (lds_bytes(c.dim, c.nl, c.flux, tx, ty) > (size_t)b->max_lds) return bfail(DG_EUNSUPPORTED, "tile exceeds LDS");
-  if (grid_per_cu < 1 || grid_per_cu > 64) return bfail(DG_EINVAL, "grid_per_cu must be in 1..64");
+  if (grid_per_cu < 0 || grid_per_cu > 64)
+    return bfail(DG_EINVAL, "grid_per_cu must be in 0..64 (0: one workgroup per tile)");
   if (order < 0 || order > 2) return bfail(DG_EINVAL, "order must be 0, 1 or 2");
   c.tx = tx;
   c.ty = ty;
@@ -494,7 +496,7 @@ int dg_batch_tune(dg_batch* b, double* arena, const double* dts, int32_t reps, c
         c.ty = tt.second;
         c.order = order;
         if ((rc = build_tiles(b, c))) return rc;
-        for (int g : {1, 2, 4, 8}) {
+        for (int g : {0, 1, 2, 4, 8}) {
           c.grid_per_cu = g;
           if ((rc = class_stage(b, c, st, arena, arena, b->U1, 0.0, 1.0))) return rc;  // warm-up
           (void)hipEventRecord(e0, st);

@@ -113,8 +113,9 @@ inline long long batch_tile_capacity(const std::vector<BatchMesh>& m, const std:
 
 // Workgroups of a class launch: grid_per_cu per compute unit, at most one
 // per tile, at least one.  Workgroup g walks tiles g, g + grid, g + 2 grid, ...
+// grid_per_cu = 0: one workgroup per tile (the kernel without the tile loop).
 inline int batch_grid(int grid_per_cu, int cus, long long ntiles) {
-  const long long g = (long long)grid_per_cu * cus;
+  const long long g = grid_per_cu == 0 ? ntiles : (long long)grid_per_cu * cus;
   return (int)std::max<long long>(1, std::min<long long>(g, ntiles));
 }
 

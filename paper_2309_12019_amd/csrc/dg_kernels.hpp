@@ -1445,21 +1445,33 @@ struct BatchStageArgs {
 };
 
 template <int DIM, int P, int FLUX, int MODE, int TX, int TY>
+__device__ inline void batch_tile(const BatchStageArgs& B, double* lds, int k) {
+  const BatchTile tl = B.tiles[k];
+  StageArgs A = B.probs[tl.prob].args;
+  const long long off = B.probs[tl.prob].off;
+  A.uin = B.uin + off;
+  A.un = B.un + off;
+  A.out = B.out + off;
+  A.gamma = nullptr;
+  A.a = B.a;
+  A.b = B.b;
+  A.rhs_only = 0;
+  stage_tile<DIM, P, FLUX, MODE, TX, TY>(A, lds, tl.ix0, tl.iy0);
+}
+
+// ONE: one workgroup per tile (grid = the number of tiles), no tile loop;
+// a loop makes the compiler keep the arithmetic's loop-invariant values in
+// registers across tiles (tens of VGPRs more), which this form avoids.
+template <int DIM, int P, int FLUX, int MODE, int TX, int TY, bool ONE = false>
 __global__ void __launch_bounds__(DIM == 2 ? TX * TY : TX) batch_stage_kernel(const BatchStageArgs B) {
   extern __shared__ double lds[];
-  for (int k = blockIdx.x; k < B.ntiles; k += gridDim.x) {
-    const BatchTile tl = B.tiles[k];
-    StageArgs A = B.probs[tl.prob].args;
-    const long long off = B.probs[tl.prob].off;
-    A.uin = B.uin + off;
-    A.un = B.un + off;
-    A.out = B.out + off;
-    A.gamma = nullptr;
-    A.a = B.a;
-    A.b = B.b;
-    A.rhs_only = 0;
-    stage_tile<DIM, P, FLUX, MODE, TX, TY>(A, lds, tl.ix0, tl.iy0);
-    tile_barrier();  // the next tile reuses LDS
+  if constexpr (ONE) {
+    if ((int)blockIdx.x < B.ntiles) batch_tile<DIM, P, FLUX, MODE, TX, TY>(B, lds, blockIdx.x);
+  } else {
+    for (int k = blockIdx.x; k < B.ntiles; k += gridDim.x) {
+      batch_tile<DIM, P, FLUX, MODE, TX, TY>(B, lds, k);
+      tile_barrier();  // the next tile reuses LDS
+    }
   }
 }
 

@@ -27,6 +27,7 @@ struct LaunchReq {
   long long ncells;
   hipStream_t stream;
   BatchStageArgs batch;  // LAUNCH_BATCH (tile shape in args.tx/args.ty, grid in ncells)
+  int batch_one;         // LAUNCH_BATCH: one workgroup per tile (grid = batch.ntiles)
   AdjArgs adj;           // LAUNCH_ADJ_* (tile shape in adj.s.tx/adj.s.ty)
   uint32_t* sig;         // LAUNCH_SIGNATURE: branch records [3][cells] (stage input in args.uin)
 };

@@ -84,10 +84,10 @@ hipError_t launch_step_f(int mode, const StageArgs& A, hipStream_t s) {
   }
 }
 
-template <int FLUX, int MODE, int TX, int TY>
-hipError_t launch_batch_tile(const BatchStageArgs& B, int grid, hipStream_t st) {
+template <int FLUX, int MODE, int TX, int TY, bool ONE>
+hipError_t launch_batch_tile_k(const BatchStageArgs& B, int grid, hipStream_t st) {
   constexpr int NL = DGK_DIM == 1 ? DGK_P + 1 : (DGK_P + 1) * (DGK_P + 1);
-  auto k = batch_stage_kernel<DGK_DIM, DGK_P, FLUX, MODE, TX, TY>;
+  auto k = batch_stage_kernel<DGK_DIM, DGK_P, FLUX, MODE, TX, TY, ONE>;
   const size_t lds = sizeof(double) * (size_t)stage_lds_doubles(DGK_DIM, NL, FLUX, TX, TY);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
@@ -98,15 +98,21 @@ hipError_t launch_batch_tile(const BatchStageArgs& B, int grid, hipStream_t st) 
   return hipGetLastError();
 }
 
+template <int FLUX, int MODE, int TX, int TY>
+hipError_t launch_batch_tile(const BatchStageArgs& B, int grid, bool one, hipStream_t st) {
+  if (one) return launch_batch_tile_k<FLUX, MODE, TX, TY, true>(B, grid, st);
+  return launch_batch_tile_k<FLUX, MODE, TX, TY, false>(B, grid, st);
+}
+
 template <int FLUX, int MODE>
 hipError_t launch_batch_fm(const LaunchReq* r) {
   const int grid = (int)r->ncells;
   if constexpr (DGK_DIM == 1) {
-    if (r->args.tx == 64) return launch_batch_tile<FLUX, MODE, 64, 1>(r->batch, grid, r->stream);
-    return launch_batch_tile<FLUX, MODE, 256, 1>(r->batch, grid, r->stream);
+    if (r->args.tx == 64) return launch_batch_tile<FLUX, MODE, 64, 1>(r->batch, grid, r->batch_one != 0, r->stream);
+    return launch_batch_tile<FLUX, MODE, 256, 1>(r->batch, grid, r->batch_one != 0, r->stream);
   } else {
-    if (r->args.tx == 8) return launch_batch_tile<FLUX, MODE, 8, 8>(r->batch, grid, r->stream);
-    return launch_batch_tile<FLUX, MODE, 16, 16>(r->batch, grid, r->stream);
+    if (r->args.tx == 8) return launch_batch_tile<FLUX, MODE, 8, 8>(r->batch, grid, r->batch_one != 0, r->stream);
+    return launch_batch_tile<FLUX, MODE, 16, 16>(r->batch, grid, r->batch_one != 0, r->stream);
   }
 }
 

@@ -305,7 +305,7 @@ void check_batch_class(const std::vector<BatchProblemDesc>& pd, const std::vecto
     for (auto& t : list) kl.push_back(key(t));
     std::sort(kl.begin(), kl.end());
     CHECK(kl == kb, "batch: order %d lists other tiles than order 0", order);
-    for (int g : {1, 2, 4, 8, 64}) {
+    for (int g : {0, 1, 2, 4, 8, 64}) {
       const int grid = batch_grid(g, 256, (long long)list.size());
       CHECK(grid >= 1 && grid <= (long long)std::max<size_t>(1, list.size()), "batch: grid %d", grid);
       std::vector<int> seen(list.size(), 0);
