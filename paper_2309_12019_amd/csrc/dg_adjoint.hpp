@@ -741,7 +741,8 @@ __global__ void __launch_bounds__(DIM == 2 ? TX * TY : TX) adj_sensor_kernel(con
   constexpr int NL = AC::NL, S = G::S;
   extern __shared__ double lds[];
   const StageArgs& A = Ad.s;
-  const int ix0 = blockIdx.x * TX, iy0 = DIM == 2 ? blockIdx.y * TY : 0;
+  const int tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);  // XCD-aware order
+  const int ix0 = (tile % gridDim.x) * TX, iy0 = DIM == 2 ? (tile / gridDim.x) * TY : 0;
   const int t = threadIdx.x;
   int sc, gx, gy, hs, hgx, hgy;
   const bool halo = tile_slots<DIM, TX, TY>(t, ix0, iy0, sc, gx, gy, hs, hgx, hgy);
@@ -771,7 +772,8 @@ __global__ void __launch_bounds__(DIM == 2 ? TX * TY : TX) adj_grad_kernel(const
   extern __shared__ double lds[];
   double* ldsv = lds + NL * S;
   const StageArgs& A = Ad.s;
-  const int ix0 = blockIdx.x * TX, iy0 = DIM == 2 ? blockIdx.y * TY : 0;
+  const int tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);  // XCD-aware order
+  const int ix0 = (tile % gridDim.x) * TX, iy0 = DIM == 2 ? (tile / gridDim.x) * TY : 0;
   const int t = threadIdx.x;
   int sc, gx, gy, hs, hgx, hgy;
   const bool halo = tile_slots<DIM, TX, TY>(t, ix0, iy0, sc, gx, gy, hs, hgx, hgy);
@@ -832,7 +834,8 @@ __global__ void __launch_bounds__(DIM == 2 ? TX * TY : TX) adj_grad_sensor_kerne
   extern __shared__ double lds[];
   double* ldsv = lds + NL * S;
   const StageArgs& A = Ad.s;
-  const int ix0 = blockIdx.x * TX, iy0 = DIM == 2 ? blockIdx.y * TY : 0;
+  const int tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);  // XCD-aware order
+  const int ix0 = (tile % gridDim.x) * TX, iy0 = DIM == 2 ? (tile / gridDim.x) * TY : 0;
   const int t = threadIdx.x;
   int sc, gx, gy, hs, hgx, hgy;
   const bool halo = tile_slots<DIM, TX, TY>(t, ix0, iy0, sc, gx, gy, hs, hgx, hgy);

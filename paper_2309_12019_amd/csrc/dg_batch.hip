@@ -54,7 +54,7 @@ struct Class {
   int dim, p, flux, mode, nl;
   std::vector<int> probs;     // problem indices
   // schedule
-  int tx = 0, ty = 1, grid_per_cu = 2, order = 0, branch = 0;
+  int tx = 0, ty = 1, grid_per_cu = 0, order = 0, branch = 0;  // grid_per_cu 0: one workgroup per tile
   // device tile list for the current schedule, allocated once at creation
   // with room for the longest list any supported tile shape gives
   BatchTile* d_tiles = nullptr;
