@@ -241,7 +241,8 @@ int dg_stream_copy(const double* src, double* dst, int64_t n, void* stream);
 /* Launch shape of the stage kernel: cells per workgroup, one of the compiled
  * tiles: 1D tx in {256, 64} (ty ignored), 2D (tx, ty) in {(16,16), (8,8)}.
  * The result does not depend on the tile (per-cell arithmetic is identical).
- * Default at dg_init_mesh: 256 (1D), 16x16 (2D; 8x8 if 16x16 exceeds LDS).
+ * Default at dg_init_mesh: 256 (1D), 16x16 (2D; 8x8 if 16x16 exceeds LDS or
+ * the mesh has fewer 16x16 tiles than the GPU has compute units).
  * Errors: DG_EINVAL for another shape, DG_EUNSUPPORTED if it exceeds LDS. */
 int dg_set_tile(dg_ctx* ctx, int32_t tx, int32_t ty);
 int dg_get_tile(const dg_ctx* ctx, int32_t* tx, int32_t* ty);
@@ -252,7 +253,8 @@ int dg_get_tile(const dg_ctx* ctx, int32_t* tx, int32_t* ty);
  * HBM once.  Same per-cell arithmetic as the per-stage kernel, so results are
  * bitwise the same.  Used by dg_step and dg_run.  mode: -1 automatic (default: on
  * in 1D, and in 2D for meshes of at most one 16x16 tile per compute unit,
- * where per-stage launches are latency bound), 0 off, 1 on.  Errors:
+ * where per-stage launches are latency bound, except for the KPP flux), 0
+ * off, 1 on.  Errors:
  * DG_EINVAL for another mode, DG_EUNSUPPORTED for mode 1 when the three
  * tiles exceed LDS (2D degree 4), rk_order is not 3, bc_kind is not
  * CONSTANT or the flux is Euler; in those cases the automatic mode never uses it.  dg_get_fused writes 1 if steps use it.
@@ -337,7 +339,8 @@ int dg_validate_desc(const dg_mesh_desc* desc);
  *
  * Many problems of uneven mesh size and degree advance together: problems
  * are grouped into kernel classes (dim, p, flux, mode); every RK stage of a
- * class is one persistent launch that walks the class's tile list, and a run
+ * class is one launch over the class's tile list (one workgroup per tile,
+ * or a persistent grid that walks the list), and a run
  * of N steps is one HIP graph in which the classes form independent chains on
  * up to four concurrent branches.  Each problem's arithmetic is that of the
  * single-problem path (same per-cell code, same tables), so a problem's
