@@ -160,11 +160,13 @@ StageArgs base_args(const dg_ctx* c) {
   A.bc_kind = d.bc_kind;
   A.tx = c->tx;
   A.ty = d.dim == 2 ? c->ty : 1;
+  if (d.dim == 2 && d.flux == DG_FLUX_KPP)
+    A.waves = dgk::split_waves((long long)((d.nx + 7) / 8) * ((d.ny + 7) / 8), c->cus, d.p);
   return A;
 }
 
-size_t stage_lds_bytes(int dim, int nl, int flux, int tx, int ty) {
-  return sizeof(double) * (size_t)dgk::stage_lds_doubles(dim, nl, flux, tx, dim == 2 ? ty : 1);
+size_t stage_lds_bytes(int dim, int nl, int p, int flux, int tx, int ty) {
+  return sizeof(double) * (size_t)dgk::stage_kernel_lds_doubles(dim, nl, p, flux, tx, dim == 2 ? ty : 1);
 }
 
 // one stage: out = a*un + b*(uin + dt*L(uin)), or out = L(uin) when rhs_only;
@@ -375,9 +377,9 @@ int check_tile(const dg_ctx* c, int tx, int ty) {
   if (!ok)
     return fail(DG_EINVAL, dim == 1 ? "1D tile must be 256 or 64 cells (got %d)"
                                      : "2D tile must be 16x16 or 8x8 (got %dx%d)", tx, ty);
-  if (stage_lds_bytes(dim, c->nl, c->d.flux, tx, ty) > (size_t)c->max_lds)
+  if (stage_lds_bytes(dim, c->nl, c->d.p, c->d.flux, tx, ty) > (size_t)c->max_lds)
     return fail(DG_EUNSUPPORTED, "tile %dx%d needs %zu bytes of LDS (limit %d)", tx, ty,
-                stage_lds_bytes(dim, c->nl, c->d.flux, tx, ty), c->max_lds);
+                stage_lds_bytes(dim, c->nl, c->d.p, c->d.flux, tx, ty), c->max_lds);
   return DG_OK;
 }
 
@@ -644,7 +646,10 @@ int dg_validate_desc(const dg_mesh_desc* desc) {
 // Default tile of the per-stage kernel: 256 cells in 1D; in 2D 16x16 unless
 // its LDS exceeds the limit, and 8x8 when the mesh has fewer 16x16 tiles
 // than compute units (four times the workgroups: 128^2 P2 25.0 -> 20.4 us
-// per step for the four-quadrant problem, 20.7 -> 16.2 for Burgers).
+// per step for the four-quadrant problem, 20.7 -> 16.2 for Burgers).  The
+// KPP flux takes 8x8 (its kernel of 4 to 16 waves per tile) up to two 16x16
+// tiles per compute unit: P2 stage 25.3 -> 7.9 us at 128^2, 26.1 -> 16.9 at
+// 256^2, but 50 -> 57 at 512^2, where the 16x16 kernel fills the GPU.
 void default_tile(dg_ctx* c) {
   if (c->d.dim == 1) {
     c->tx = 256;
@@ -652,8 +657,9 @@ void default_tile(dg_ctx* c) {
     return;
   }
   c->tx = c->ty = 16;
-  if (stage_lds_bytes(2, c->nl, c->d.flux, 16, 16) > (size_t)c->max_lds ||
-      (long long)((c->d.nx + 15) / 16) * ((c->d.ny + 15) / 16) < (long long)c->cus)
+  const long long t16 = (long long)((c->d.nx + 15) / 16) * ((c->d.ny + 15) / 16);
+  if (stage_lds_bytes(2, c->nl, c->d.p, c->d.flux, 16, 16) > (size_t)c->max_lds || t16 < (long long)c->cus ||
+      (c->d.flux == DG_FLUX_KPP && t16 <= 2LL * c->cus))
     c->tx = c->ty = 8;
 }
 
@@ -676,9 +682,10 @@ void resolve_fused(dg_ctx* c) {
     c->fused = true;
     return;
   }
-  // the KPP flux: its sine and cosine at every node keep a lone wave per SIMD
-  // busy either way, and the fused kernel's recomputed rings add to that
-  // (128^2 P2: 84 us per step fused, 75 us per-stage)
+  // the KPP flux: the per-stage kernel spreads the sine and cosine of every
+  // node over up to 16 waves per tile; the fused kernel evaluates them for
+  // each cell on one thread and recomputes the rings (128^2 P2: 84 us per
+  // step fused, 23 us per-stage)
   if (c->d.flux == DG_FLUX_KPP) {
     c->fused = false;
     return;

@@ -51,6 +51,7 @@ struct StageArgs {
   double q, bthr, wnb, eps, wpow, lam_over;
   double theta;                  // exponent of the Zhao et al. sensor (MODE_ZHAO)
   int tx, ty;                    // tile (one of the compiled shapes; ty = 1 in 1D)
+  int waves;                     // 2D KPP on 8x8 tiles: waves per tile (4, 8 or 16; 0: 4)
 };
 
 // Tile geometry: TX x TY cells per workgroup (TY = 1 in 1D) plus a one-cell
@@ -496,6 +497,37 @@ struct Cell {
     }
   }
 
+  // One x node line of the 2D sum factorisation: s1[bb] = sum_a c(a, bb)
+  // P_a(x_qx), and the value at node (qx, qy) from it.  coef(j) returns
+  // coefficient j.  The volume integral and the KPP node tasks of
+  // kpp_split_tile evaluate u_h at a node with these, bit for bit alike.
+  template <class Coef>
+  __device__ static inline void xline(Coef coef, int qx, double (&s1)[N]) {
+#pragma unroll
+    for (int bb = 0; bb < N; ++bb) {
+      double t = coef(N * bb);
+#pragma unroll
+      for (int a = 1; a < N; ++a) t = fma(coef(a + N * bb), TB::nd.L[a][qx], t);
+      s1[bb] = t;
+    }
+  }
+  __device__ static inline double ynode(const double (&s1)[N], int qy) {
+    double u = s1[0];
+#pragma unroll
+    for (int bb = 1; bb < N; ++bb) u = fma(s1[bb], TB::nd.L[bb][qy], u);
+    return u;
+  }
+
+  // Adds the face flux H at Gauss point r to the moments g of a 2D face
+  // (g is assigned at r = 0)
+  __device__ static inline void face_acc(int r, double H, double (&g)[N]) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      const double cw = TB::nd.w[r] * TB::nd.L[k][r];
+      g[k] = r == 0 ? cw * H : fma(cw, H, g[k]);
+    }
+  }
+
   // The two states at Gauss point r of a 2D face from the traces
   __device__ static inline void face_node(const double (&tl)[N], const double (&th)[N], int r, double& ul,
                                           double& uh) {
@@ -529,11 +561,7 @@ struct Cell {
         H = llf_kpp(axis, ul, uh);
       else
         H = llf(v[r], ul, uh);
-#pragma unroll
-      for (int k = 0; k < N; ++k) {
-        const double cw = TB::nd.w[r] * TB::nd.L[k][r];
-        g[k] = r == 0 ? cw * H : fma(cw, H, g[k]);
-      }
+      face_acc(r, H, g);
     }
   }
 
@@ -667,10 +695,12 @@ struct Cell {
   // Volume minus face terms of the weak form (R) and the cell's wave speed
   // lambda_e (before the override); the faces in the order -x, +x, -y, +y.
   // FACES = false: the volume terms only (a tile's shared faces are added
-  // by the caller, in the same order).
-  template <bool XBC = false, bool FACES = true>
+  // by the caller, in the same order).  VS > 0 (2D KPP): the flux pair at
+  // volume node (qx, qy) was evaluated beforehand, sin u at
+  // vol[(qx Q + qy) VS] and cos u at vol[(Q^2 + qx Q + qy) VS].
+  template <bool XBC = false, bool FACES = true, int VS = 0>
   __device__ static inline void residual(const StageArgs& A, const double* b, const double (&c)[NL], int ix, int iy,
-                                         double (&R)[NL], double& lam) {
+                                         double (&R)[NL], double& lam, const double* vol = nullptr) {
     // (every sum starts with a product: R is assigned, not cleared, at the
     // first node)
     if constexpr (DIM == 1) {
@@ -707,25 +737,22 @@ struct Cell {
 #pragma unroll
       for (int qx = 0; qx < Q; ++qx) {
         double s1[N];
-#pragma unroll
-        for (int bb = 0; bb < N; ++bb) {
-          double t = c[N * bb];
-#pragma unroll
-          for (int a = 1; a < N; ++a) t = fma(c[a + N * bb], TB::nd.L[a][qx], t);
-          s1[bb] = t;
-        }
+        xline([&](int j) { return c[j]; }, qx, s1);
         double gx[N], gy[N];
 #pragma unroll
         for (int qy = 0; qy < Q; ++qy) {
-          double u = s1[0];
-#pragma unroll
-          for (int bb = 1; bb < N; ++bb) u = fma(s1[bb], TB::nd.L[bb][qy], u);
+          const double u = ynode(s1, qy);
           double Fx, Fy;
           if constexpr (FLUX == FLUX_LINADV) {
             Fx = vxl[qy] * u;
             Fy = vyl[qx] * u;
           } else if constexpr (FLUX == FLUX_KPP) {
-            sincos_cold(u, &Fx, &Fy);
+            if constexpr (VS > 0) {
+              Fx = vol[(qx * Q + qy) * VS];
+              Fy = vol[(Q * Q + qx * Q + qy) * VS];
+            } else {
+              sincos_cold(u, &Fx, &Fy);
+            }
           } else {
             Fx = u * u;
             Fy = Fx;
@@ -933,6 +960,47 @@ __host__ __device__ inline bool slot_cell(const StageArgs& A, int gx, int gy, si
   }
   cell = (size_t)gy * nx + gx;
   return true;
+}
+
+// The KPP flux on 8 x 8 tiles (kpp_split_tile): 4 to 16 waves per tile.  LDS:
+// the tile, then the flux pair at every volume node of every cell (plane
+// node, sin u then cos u, 64 cells each: 2 Q^2 planes), then the LLF flux
+// at every node of every face (x faces, then y faces; per axis Q planes of
+// the 72 faces in face_slot's order).
+__host__ __device__ constexpr bool splits_nodes(int dim, int flux, int tx, int ty) {
+  return dim == 2 && flux == FLUX_KPP && tx == 8 && ty == 8;
+}
+__host__ __device__ inline int split_lds_doubles(int nl, int q) {
+  return tile_lds_doubles(2, nl, 8, 8) + 2 * q * q * 64 + 2 * 72 * q;
+}
+// Volume node task v (< 64 q^2) of kpp_split_tile: tile cell v mod 64 at
+// node (qx, qy), v / 64 = qx q + qy.  Returns the index of its sin u in the
+// node planes (cos u: + 64 q^2); slot: the cell's LDS slot.
+__host__ __device__ inline int split_vol_task(int v, int q, int& slot, int& qx, int& qy) {
+  const int lc = v & 63, node = v >> 6;
+  qx = node / q;
+  qy = node % q;
+  slot = ((lc >> 3) + 1) * 10 + (lc & 7) + 1;
+  return node * 64 + lc;
+}
+// Face node task i (< 144 q): axis, Gauss point r and face e (face_slot's
+// order); returns its index in the face node planes
+__host__ __device__ inline int split_face_task(int i, int q, int& axis, int& r, int& e) {
+  axis = i >= 72 * q;
+  const int j = i - axis * 72 * q;
+  r = j / 72;
+  e = j % 72;
+  return (axis * q + r) * 72 + e;
+}
+// Face f (0: -x, 1: +x, 2: -y, 3: +y) of tile cell lc, as a face of its axis
+__host__ __device__ inline int split_cell_face(int lc, int f) {
+  const int lx = lc % 8, ly = lc / 8;
+  return f < 2 ? ly * 9 + lx + (f & 1) : ly * 8 + lx + (f & 1) * 8;
+}
+// LDS of the per-stage kernel on this tile
+__host__ __device__ inline int stage_kernel_lds_doubles(int dim, int nl, int p, int flux, int tx, int ty) {
+  return splits_nodes(dim, flux, tx, ty) ? split_lds_doubles(nl, quad_points(dim, p, flux))
+                                         : stage_lds_doubles(dim, nl, flux, tx, ty);
 }
 
 // The slots thread t of the tile at (ix0, iy0) loads: its own cell's slot
@@ -1147,6 +1215,151 @@ __global__ void __launch_bounds__(DIM == 2 ? TX * TY : TX) stage_kernel(const St
   const int bx = tile % gridDim.x, by = tile / gridDim.x;
   stage_tile<DIM, P, FLUX, MODE, TX, TY, XBC && DIM == 2 && FLUX == FLUX_BURGERS>(A, lds, bx * TX,
                                                                                 DIM == 2 ? by * TY : 0);
+}
+
+// The per-stage KPP kernel on 8 x 8 tiles.  The sine and cosine at every
+// volume and face node dominate this stage, and a one-wave 8 x 8 tile per
+// workgroup leaves most SIMDs idle on small meshes (a 128^2 mesh is 256
+// tiles).  Here a tile has NTH / 64 waves (4, 8 or 16):
+//   * wave 0 owns the 64 cells: it loads the tile into LDS as stage_tile
+//     does, evaluates gamma_e (the sensor reads the tile only), and after
+//     the node phase sums the volume and face integrals, finishes and
+//     stores its cells;
+//   * in the node phase the waves evaluate the node fluxes: (sin u, cos u)
+//     at the Q^2 volume nodes of every cell and the LLF flux at the Q nodes
+//     of every face of the tile (each face once), into LDS.  Wave 0 takes V0
+//     rounds of volume nodes beside the sensor; the other waves take every
+//     face node, then the remaining volume nodes.
+// u_h at a node, the face traces and the fluxes are computed by the same
+// functions as in the per-cell path (xline/ynode, trace/face_node,
+// llf_kpp), and wave 0 sums them in the same order (residual with VS = 64,
+// face_acc, add_face), so the result is the same bit for bit.
+template <int P, int MODE, int V0, int NTH>
+__device__ inline void kpp_split_tile(const StageArgs& A, double* lds, int ix0, int iy0) {
+  constexpr int TX = 8, TY = 8;
+  using G = TileGeom<2, TX, TY>;
+  using C = Cell<2, P, FLUX_KPP, MODE, G::S, G::W>;
+  constexpr int NL = C::NL, N = C::N, Q = C::Q, S = G::S;
+  constexpr int NV = 64 * Q * Q;  // volume node tasks
+  constexpr int NFA = 72;         // faces per axis ((TX + 1) TY = TX (TY + 1))
+  constexpr int NFN = 2 * NFA * Q;  // face node tasks
+  static_assert(V0 >= 0 && V0 <= Q * Q, "wave 0 takes whole rounds of volume nodes");
+  static_assert(G::W == 10 && FaceGeom<TX, TY>::NXF == NFA && FaceGeom<TX, TY>::NYF == NFA,
+                "split_vol_task and split_face_task assume 8 x 8 tiles");
+  constexpr int H0 = 64;  // the first thread of the node tasks
+  static_assert(NTH % 64 == 0 && NTH > H0, "whole waves, at least one for the node tasks");
+  double* const vol = lds + NL * S;
+  double* const fnl = vol + 2 * Q * Q * 64;
+  const int nx = A.nx, ny = A.ny;
+  const int t = threadIdx.x;
+  const bool owner = t < 64;
+
+  int sc = 0, gx = 0, gy = 0;
+  double c[NL];
+  if (owner) {
+    int hs, hgx, hgy;
+    const bool halo = tile_slots<2, TX, TY>(t, ix0, iy0, sc, gx, gy, hs, hgx, hgy);
+    load_cell<2, NL>(A, gx, gy, c);
+    if (halo) load_slot<2, NL, S>(A, lds, hs, hgx, hgy);
+#pragma unroll
+    for (int j = 0; j < NL; ++j) lds[j * S + sc] = c[j];
+  }
+  tile_barrier();
+  auto vol_node = [&](int v) {
+    int slot, qx, qy;
+    const int o = split_vol_task(v, Q, slot, qx, qy);
+    double s1[N];
+    C::xline([&](int j) { return lds[j * S + slot]; }, qx, s1);
+    double Fx, Fy;
+    sincos_cold(C::ynode(s1, qy), &Fx, &Fy);
+    vol[o] = Fx;
+    vol[o + Q * Q * 64] = Fy;
+  };
+  const bool active = owner && gx < nx && gy < ny;
+  double gam = 0.0;
+  if (owner) {
+    if (active) gam = C::template gamma_of<true>(A, lds + sc, c, gx, gy);
+    for (int k = 0; k < V0; ++k) vol_node(k * 64 + t);
+  } else {
+    const int u = t - H0;
+    for (int i = u; i < NFN; i += NTH - H0) {
+      int axis, r, e;
+      const int o = split_face_task(i, Q, axis, r, e);
+      int fgx, fgy;
+      const int lo = face_slot<TX, TY>(axis, e, ix0, iy0, fgx, fgy);
+      const int hi = lo + (axis == 0 ? 1 : G::W);
+      double tl[N], th[N];
+      C::template trace<false>(axis, [&](int q) { return lds[q * S + lo]; }, tl);
+      C::template trace<true>(axis, [&](int q) { return lds[q * S + hi]; }, th);
+      double ul, uh;
+      C::face_node(tl, th, r, ul, uh);
+      fnl[o] = C::llf_kpp(axis, ul, uh);
+    }
+    for (int v = V0 * 64 + u; v < NV; v += NTH - H0) vol_node(v);
+  }
+  tile_barrier();
+  if (!active) return;
+  double R[NL], lam;
+  const int lc = t;
+  C::template residual<false, false, 64>(A, lds + sc, c, gx, gy, R, lam, vol + lc);
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    const int axis = f >> 1;
+    const int e = split_cell_face(lc, f);
+    double g[N];
+#pragma unroll
+    for (int r = 0; r < Q; ++r) C::face_acc(r, fnl[(axis * Q + r) * NFA + e], g);
+    C::add_face(f, g, R);
+  }
+  double L[NL];
+  C::finish(A, c, gam, lam, R, L);
+  const size_t cell = (size_t)gy * nx + gx;
+  if (A.gamma) A.gamma[cell] = gam;
+  double* dst = A.out + cell * NL;
+  if (A.rhs_only) {
+#pragma unroll
+    for (int j = 0; j < NL; ++j) dst[j] = L[j];
+  } else {
+    const bool comb = A.a != 0.0;
+    double un[NL];
+    if (comb) {
+#pragma unroll
+      for (int j = 0; j < NL; ++j) un[j] = A.un[cell * NL + j];
+    }
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+      double v = A.b * fma(A.dt, L[j], c[j]);
+      if (comb) v = fma(A.a, un[j], v);
+      dst[j] = v;
+    }
+  }
+}
+
+// Volume node rounds of wave 0 in kpp_split_tile with nth threads: Q^2 / 2
+// at four waves, Q^2 / 4 at eight, Q^2 / 8 at sixteen (measured at p = 2
+// with the sensor: 9.5, 8.2 and 7.8 us per stage on a 128^2 mesh, against
+// 10.4-11.0, 8.7 and 7.8 for other splits)
+__host__ __device__ constexpr int split_v0(int p, int nth) { return (p + 2) * (p + 2) * 128 / nth; }
+
+// Waves per tile of kpp_split_kernel for a mesh of `tiles` 8x8 tiles on
+// `cus` compute units: sixteen while every tile has a compute unit of its
+// own, eight up to two tiles per compute unit, else four (more workgroups
+// then share each compute unit); at most what the degree's registers allow
+// without spilling (split_max_waves: 128 VGPRs at sixteen waves, 256 at
+// eight; p = 3 needs ~200, p = 4 ~256)
+__host__ __device__ constexpr int split_max_waves(int p) { return p <= 2 ? 16 : p == 3 ? 8 : 4; }
+__host__ __device__ constexpr int split_waves(long long tiles, int cus, int p) {
+  const int w = tiles <= cus ? 16 : tiles <= 2LL * cus ? 8 : 4;
+  return w < split_max_waves(p) ? w : split_max_waves(p);
+}
+
+// Grid as for stage_kernel on 8 x 8 tiles, NTH threads.
+template <int P, int MODE, int NTH>
+__global__ void __launch_bounds__(NTH) kpp_split_kernel(const StageArgs A) {
+  extern __shared__ double lds[];
+  const int tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int bx = tile % gridDim.x, by = tile / gridDim.x;
+  kpp_split_tile<P, MODE, split_v0(P, NTH), NTH>(A, lds, bx * 8, by * 8);
 }
 
 // Branch records of the stage input (Cell::branches) of every cell, folded

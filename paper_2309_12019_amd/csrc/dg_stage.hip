@@ -31,6 +31,34 @@ hipError_t launch_tile(const StageArgs& A, hipStream_t st) {
   return hipGetLastError();
 }
 
+// the KPP flux on 8x8 tiles: NTH / 64 waves per tile (kpp_split_kernel)
+template <int MODE, int NTH>
+hipError_t launch_kpp_split_n(const StageArgs& A, hipStream_t st) {
+  constexpr int NL = (DGK_P + 1) * (DGK_P + 1);
+  auto k = kpp_split_kernel<DGK_P, MODE, NTH>;
+  const size_t lds = sizeof(double) * (size_t)split_lds_doubles(NL, quad_points(2, DGK_P, FLUX_KPP));
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  dim3 grid((A.nx + 7) / 8, (A.ny + 7) / 8);
+  hipLaunchKernelGGL(k, grid, dim3(NTH), lds, st, A);
+  return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t launch_kpp_split(const StageArgs& A, hipStream_t st) {
+  // only the thread counts this degree runs without spilling are built
+  if constexpr (split_max_waves(DGK_P) >= 16) {
+    if (A.waves == 16) return launch_kpp_split_n<MODE, 1024>(A, st);
+  }
+  if constexpr (split_max_waves(DGK_P) >= 8) {
+    if (A.waves >= 8) return launch_kpp_split_n<MODE, 512>(A, st);
+  }
+  return launch_kpp_split_n<MODE, 256>(A, st);
+}
+
 template <int FLUX, int MODE>
 hipError_t launch_stage_fm(const StageArgs& A, hipStream_t st) {
   if constexpr (DGK_DIM == 1) {
@@ -45,7 +73,11 @@ hipError_t launch_stage_fm(const StageArgs& A, hipStream_t st) {
         return launch_tile<FLUX, MODE, 16, 16, true>(A, st);
       }
     }
-    if (A.tx == 8) return launch_tile<FLUX, MODE, 8, 8>(A, st);
+    if constexpr (FLUX == FLUX_KPP) {
+      if (A.tx == 8) return launch_kpp_split<MODE>(A, st);
+    } else {
+      if (A.tx == 8) return launch_tile<FLUX, MODE, 8, 8>(A, st);
+    }
     return launch_tile<FLUX, MODE, 16, 16>(A, st);
   }
 }

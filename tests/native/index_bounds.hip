@@ -401,6 +401,68 @@ int check_batch(const char* path) {
   return 0;
 }
 
+// The KPP 8x8 kernel of four waves (kpp_split_tile) at degree p: every
+// volume node and face node task reads slots inside the tile (no corner),
+// writes its own entry of the node planes exactly once, inside LDS, and the
+// cells read back exactly the entries of their own nodes and faces.
+void check_kpp_split(int p) {
+  using G = TileGeom<2, 8, 8>;
+  const int q = quad_points(2, p, FLUX_KPP), nl = (p + 1) * (p + 1);
+  const long long tile = tile_lds_doubles(2, nl, 8, 8), lds = split_lds_doubles(nl, q);
+  CHECK(stage_kernel_lds_doubles(2, nl, p, FLUX_KPP, 8, 8) == lds &&
+            stage_kernel_lds_doubles(2, nl, p, FLUX_KPP, 16, 16) == stage_lds_doubles(2, nl, FLUX_KPP, 16, 16) &&
+            stage_kernel_lds_doubles(2, nl, p, FLUX_BURGERS, 8, 8) == stage_lds_doubles(2, nl, FLUX_BURGERS, 8, 8),
+        "kpp split: LDS size");
+  auto corner = [&](int s) {
+    const int x = s % G::W, y = s / G::W;
+    return (x == 0 || x == G::W - 1) && (y == 0 || y == G::H - 1);
+  };
+  const int nv = 64 * q * q, nfn = 144 * q;
+  std::vector<int> vw(nv, 0), fw(nfn, 0);
+  for (int v = 0; v < nv; ++v) {
+    int slot, qx, qy;
+    const int o = split_vol_task(v, q, slot, qx, qy);
+    CHECK(slot >= 0 && slot < G::NS && !corner(slot) && slot % G::W > 0 && slot % G::W <= 8 && slot / G::W > 0 &&
+              slot / G::W <= 8,
+          "kpp split: volume task %d reads slot %d outside the tile cells", v, slot);
+    CHECK(qx >= 0 && qx < q && qy >= 0 && qy < q, "kpp split: volume task %d node", v);
+    CHECK(o >= 0 && o < nv && tile + nv + o < lds, "kpp split: volume task %d entry %d", v, o);
+    if (o >= 0 && o < nv) vw[o]++;
+    // tile cell lc reads its node (qx, qy) at (qx q + qy) 64 + lc
+    const int lc = v & 63;
+    CHECK(o == (qx * q + qy) * 64 + lc && slot == ((lc / 8) + 1) * G::W + lc % 8 + 1,
+          "kpp split: volume task %d is not cell %d's node", v, lc);
+  }
+  for (int o = 0; o < nv; ++o) CHECK(vw[o] == 1, "kpp split: volume entry %d written %d times", o, vw[o]);
+  const int ix0 = 5 * 8, iy0 = 2 * 8;
+  for (int i = 0; i < nfn; ++i) {
+    int axis, r, e;
+    const int o = split_face_task(i, q, axis, r, e);
+    CHECK(axis >= 0 && axis < 2 && r >= 0 && r < q && e >= 0 && e < 72, "kpp split: face task %d", i);
+    CHECK(o >= 0 && o < nfn && tile + 2LL * nv + o < lds, "kpp split: face task %d entry %d", i, o);
+    if (o >= 0 && o < nfn) fw[o]++;
+    int gx, gy;
+    const int lo = face_slot<8, 8>(axis, e, ix0, iy0, gx, gy), hi = lo + (axis ? G::W : 1);
+    CHECK(lo >= 0 && hi < G::NS && !corner(lo) && !corner(hi), "kpp split: face %d slots %d %d", e, lo, hi);
+  }
+  for (int o = 0; o < nfn; ++o) CHECK(fw[o] == 1, "kpp split: face entry %d written %d times", o, fw[o]);
+  for (int lc = 0; lc < 64; ++lc) {
+    int sc, gx, gy, hs, hgx, hgy;
+    tile_slots<2, 8, 8>(lc, ix0, iy0, sc, gx, gy, hs, hgx, hgy);
+    for (int f = 0; f < 4; ++f) {
+      const int axis = f >> 1, e = split_cell_face(lc, f);
+      CHECK(e >= 0 && e < 72, "kpp split: face %d of cell %d", f, lc);
+      int fx, fy;
+      const int lo = face_slot<8, 8>(axis, e, ix0, iy0, fx, fy);
+      const int want = f == 0 ? sc - 1 : f == 1 ? sc : f == 2 ? sc - G::W : sc;
+      CHECK(lo == want, "kpp split: face %d of cell %d has lower slot %d, not %d", f, lc, lo, want);
+      for (int r = 0; r < q; ++r) CHECK((axis * q + r) * 72 + e < nfn, "kpp split: face read outside its planes");
+    }
+  }
+  // wave 0's volume rounds: whole rounds within the node count
+  for (int nth : {256, 512, 1024}) CHECK(split_v0(p, nth) >= 0 && split_v0(p, nth) <= q * q, "kpp split: v0");
+}
+
 // xcd_tile is a bijection of [0, g) for every grid size, and each XCD's
 // workgroups take one contiguous, increasing run of tiles.
 void check_xcd_order() {
@@ -445,6 +507,15 @@ int main(int argc, char** argv) {
       check_faces<16, 16>(nl, flux);
       check_faces<8, 8>(nl, flux);
     }
+  for (int p = 1; p <= 4; ++p) check_kpp_split(p);
+  static_assert(splits_nodes(2, FLUX_KPP, 8, 8) && !splits_nodes(2, FLUX_KPP, 16, 16) &&
+                    !splits_nodes(2, FLUX_BURGERS, 8, 8),
+                "the node split: 2D KPP on 8x8 tiles only");
+  static_assert(split_waves(256, 256, 2) == 16 && split_waves(257, 256, 2) == 8 && split_waves(512, 256, 2) == 8 &&
+                    split_waves(513, 256, 2) == 4 && split_waves(256, 256, 1) == 16 &&
+                    split_waves(256, 256, 3) == 8 && split_waves(256, 256, 4) == 4 && split_v0(2, 256) == 8 &&
+                    split_v0(2, 512) == 4 && split_v0(2, 1024) == 2,
+                "KPP split: waves per tile and wave 0's volume rounds");
   static_assert(shares_faces(2, 2, FLUX_BURGERS, 16, 16) && shares_faces(2, 2, FLUX_KPP, 16, 16) &&
                     !shares_faces(2, 2, FLUX_LINADV, 16, 16) && !shares_faces(2, 3, FLUX_BURGERS, 16, 16) &&
                     !shares_faces(2, 2, FLUX_BURGERS, 8, 8) && !shares_faces(1, 2, FLUX_BURGERS, 256, 1),

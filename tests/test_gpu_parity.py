@@ -244,14 +244,15 @@ def test_run_equals_repeated_step_bitwise():
     assert torch.equal(A, C)
 
 
-@pytest.mark.parametrize("kind", ["rot2d", "burgers2d", "adv1d"])
+@pytest.mark.parametrize("kind", ["rot2d", "burgers2d", "kpp2d", "adv1d"])
 @pytest.mark.parametrize("p", [1, 2, 3, 4])
 def test_tile_shape_independence(kind, p):
     """Per-cell arithmetic does not depend on the workgroup tile (one-wave 8x8
-    and 64-cell tiles included), on a rough state that switches the sensor on
-    and, for the rotation, with faces on which v.n changes sign (the centre of
-    rotation off the grid lines), where the LLF flux takes the quadrature
-    branch."""
+    and 64-cell tiles included; for the KPP flux the 8x8 tile is the kernel of
+    four waves that evaluates the node fluxes apart from the cells), on a
+    rough state that switches the sensor on and, for the rotation, with faces
+    on which v.n changes sign (the centre of rotation off the grid lines),
+    where the LLF flux takes the quadrature branch."""
     _note(f"[tiles] {kind} p={p}")
     w = _mesh(kind, p, 2, n1=1000, n2=(72, 40))
     if kind == "rot2d":
