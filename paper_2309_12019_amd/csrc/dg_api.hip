@@ -160,8 +160,6 @@ StageArgs base_args(const dg_ctx* c) {
   A.bc_kind = d.bc_kind;
   A.tx = c->tx;
   A.ty = d.dim == 2 ? c->ty : 1;
-  if (d.dim == 2 && d.flux == DG_FLUX_KPP)
-    A.waves = dgk::split_waves((long long)((d.nx + 7) / 8) * ((d.ny + 7) / 8), c->cus, d.p);
   return A;
 }
 
@@ -178,6 +176,8 @@ int stage(dg_ctx* c, hipStream_t st, const double* uin, const double* un, double
   r.flux = c->d.flux;
   r.mode = c->d.mode;
   r.args = base_args(c);
+  if (c->d.dim == 2 && c->d.flux == DG_FLUX_KPP)
+    r.waves = dgk::split_waves((long long)((c->d.nx + 7) / 8) * ((c->d.ny + 7) / 8), c->cus, c->d.p);
   r.args.uin = uin;
   r.args.un = un;
   r.args.out = out;

@@ -51,7 +51,6 @@ struct StageArgs {
   double q, bthr, wnb, eps, wpow, lam_over;
   double theta;                  // exponent of the Zhao et al. sensor (MODE_ZHAO)
   int tx, ty;                    // tile (one of the compiled shapes; ty = 1 in 1D)
-  int waves;                     // 2D KPP on 8x8 tiles: waves per tile (4, 8 or 16; 0: 4)
 };
 
 // Tile geometry: TX x TY cells per workgroup (TY = 1 in 1D) plus a one-cell

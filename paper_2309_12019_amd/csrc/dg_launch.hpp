@@ -22,6 +22,7 @@ struct LaunchReq {
   int kind;
   int flux, mode;
   StageArgs args;       // LAUNCH_STAGE, LAUNCH_STEP, LAUNCH_LAMBDA
+  int waves;            // LAUNCH_STAGE, 2D KPP on 8x8 tiles: waves per tile (4, 8 or 16; 0: 4)
   const double* src;    // LAUNCH_PROJECT: nodal values; LAUNCH_LAMBDA: state
   double* dst;          // LAUNCH_PROJECT: coefficients; LAUNCH_LAMBDA: block maxima
   long long ncells;

@@ -48,19 +48,19 @@ hipError_t launch_kpp_split_n(const StageArgs& A, hipStream_t st) {
 }
 
 template <int MODE>
-hipError_t launch_kpp_split(const StageArgs& A, hipStream_t st) {
+hipError_t launch_kpp_split(const StageArgs& A, hipStream_t st, int waves) {
   // only the thread counts this degree runs without spilling are built
   if constexpr (split_max_waves(DGK_P) >= 16) {
-    if (A.waves == 16) return launch_kpp_split_n<MODE, 1024>(A, st);
+    if (waves == 16) return launch_kpp_split_n<MODE, 1024>(A, st);
   }
   if constexpr (split_max_waves(DGK_P) >= 8) {
-    if (A.waves >= 8) return launch_kpp_split_n<MODE, 512>(A, st);
+    if (waves >= 8) return launch_kpp_split_n<MODE, 512>(A, st);
   }
   return launch_kpp_split_n<MODE, 256>(A, st);
 }
 
 template <int FLUX, int MODE>
-hipError_t launch_stage_fm(const StageArgs& A, hipStream_t st) {
+hipError_t launch_stage_fm(const StageArgs& A, hipStream_t st, int waves = 0) {
   if constexpr (DGK_DIM == 1) {
     if (A.tx == 64) return launch_tile<FLUX, MODE, 64, 1>(A, st);
     return launch_tile<FLUX, MODE, 256, 1>(A, st);
@@ -74,7 +74,7 @@ hipError_t launch_stage_fm(const StageArgs& A, hipStream_t st) {
       }
     }
     if constexpr (FLUX == FLUX_KPP) {
-      if (A.tx == 8) return launch_kpp_split<MODE>(A, st);
+      if (A.tx == 8) return launch_kpp_split<MODE>(A, st, waves);
     } else {
       if (A.tx == 8) return launch_tile<FLUX, MODE, 8, 8>(A, st);
     }
@@ -278,12 +278,12 @@ hipError_t launch_sig_f(const LaunchReq* r) {
 }
 
 template <int FLUX>
-hipError_t launch_stage_f(int mode, const StageArgs& A, hipStream_t s) {
+hipError_t launch_stage_f(int mode, const StageArgs& A, hipStream_t s, int waves = 0) {
   switch (mode) {
-    case MODE_DG: return launch_stage_fm<FLUX, MODE_DG>(A, s);
-    case MODE_LO: return launch_stage_fm<FLUX, MODE_LO>(A, s);
-    case MODE_ZHAO: return launch_stage_fm<FLUX, MODE_ZHAO>(A, s);
-    default: return launch_stage_fm<FLUX, MODE_WENO>(A, s);
+    case MODE_DG: return launch_stage_fm<FLUX, MODE_DG>(A, s, waves);
+    case MODE_LO: return launch_stage_fm<FLUX, MODE_LO>(A, s, waves);
+    case MODE_ZHAO: return launch_stage_fm<FLUX, MODE_ZHAO>(A, s, waves);
+    default: return launch_stage_fm<FLUX, MODE_WENO>(A, s, waves);
   }
 }
 
@@ -305,7 +305,7 @@ extern "C" hipError_t DGK_CAT(dgk_launch, DGK_DIM, DGK_P)(const LaunchReq* r) {
       }
       if (r->flux == FLUX_LINADV) return launch_stage_f<FLUX_LINADV>(r->mode, A, r->stream);
       if (r->flux == FLUX_BURGERS) return launch_stage_f<FLUX_BURGERS>(r->mode, A, r->stream);
-      if constexpr (DGK_DIM == 2) return launch_stage_f<FLUX_KPP>(r->mode, A, r->stream);
+      if constexpr (DGK_DIM == 2) return launch_stage_f<FLUX_KPP>(r->mode, A, r->stream, r->waves);
       return hipErrorInvalidValue;
     }
     case LAUNCH_STEP: {

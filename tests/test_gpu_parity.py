@@ -167,6 +167,40 @@ def test_kpp_100_steps(mode):
     _run_parity(w, oracle_initial(w, O), 100, O=O)
 
 
+@pytest.mark.parametrize("n", [37, 136, 184])
+def test_kpp_split_kernel_at_each_wave_count(n):
+    """The KPP kernel of 8x8 tiles runs 16, 8 or 4 waves per tile by the
+    number of tiles per compute unit: 37^2 (25 ragged tiles), 136^2 (289 tiles,
+    between one and two per compute unit on 256) and 184^2 (529 tiles).  At
+    each size, p = 2 WENO: 3 steps and one operator bitwise equal on 8x8 and
+    16x16 tiles, and the 8x8 operator against the oracle on the ragged mesh."""
+    dgweno = _dg()
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    tiles = ((n + 7) // 8) ** 2
+    waves = 16 if tiles <= cus else 8 if tiles <= 2 * cus else 4
+    _note(f"[kpp split] {n}^2 P2 WENO: {tiles} tiles of 8x8 on {cus} CUs -> {waves} waves per tile")
+    w = inputs.kpp2d(n, 2, steps=3)
+    g = dgweno.DG.from_workload(w)
+    U0 = g.initial_state(w)
+    gen = torch.Generator(device=U0.device).manual_seed(5)
+    U0 = U0 + 0.02 * U0.abs().max() * torch.randn(U0.shape, generator=gen, device=U0.device, dtype=U0.dtype)
+    outs = []
+    for tile in ((8, 8), (16, 16)):
+        g.set_tile(*tile)
+        U = U0.clone()
+        g.run(U, w.dt(), 3)
+        L, gam = g.rhs(U0, with_gamma=True)
+        outs.append((U, L, gam))
+    torch.cuda.synchronize()
+    for a, b in zip(outs[0], outs[1]):
+        assert torch.equal(a, b)
+    if n == 37:
+        O = oracle_for(w)
+        Lo, go = O.rhs(U0.cpu(), with_gamma=True)
+        assert relinf(outs[0][1].cpu(), Lo) <= 1e-12
+        assert float((outs[0][2].cpu() - go).abs().max()) <= 1e-12
+
+
 def test_kpp_has_no_adjoint():
     dgweno = _dg()
     w = inputs.kpp2d(16, 2, steps=1)
