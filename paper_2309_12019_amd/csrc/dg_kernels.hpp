@@ -198,8 +198,11 @@ __device__ inline double rcp(double x) {
 // general powers (cold paths: exponents other than the defaults)
 __device__ __noinline__ double pow_cold(double x, double y) { return pow(x, y); }
 // sin and cos of the KPP flux, out of line: inlined at every quadrature node
-// their argument reduction would set the register count of the whole kernel
-__device__ __noinline__ void sincos_cold(double x, double* s, double* c) { sincos(x, s, c); }
+// their argument reduction would set the register count of the whole kernel.
+// sincos_inl is the same routine inlined, for code that holds few registers
+// around the call (the node tasks of kpp_split_tile): the same results.
+__device__ inline void sincos_inl(double x, double* s, double* c) { sincos(x, s, c); }
+__device__ __noinline__ void sincos_cold(double x, double* s, double* c) { sincos_inl(x, s, c); }
 
 // sqrt(x) for x > 0: hardware estimate and one Newton correction
 __device__ inline double sqrt_pos(double x) {
@@ -424,11 +427,17 @@ struct Cell {
   // s+ = max |F'(w) . n| over w between the states, i.e. max |cos w| (x
   // faces) or |sin w| (y faces): 1 where that interval holds a peak (k pi,
   // resp. pi/2 + k pi), else the larger end value
+  template <bool INL = false>
   __device__ static inline double llf_kpp(int axis, double ul, double uh) {
     constexpr double kPi = 3.141592653589793238462643383279502884;
     double sl, cl, sh, ch;
-    sincos_cold(ul, &sl, &cl);
-    sincos_cold(uh, &sh, &ch);
+    if constexpr (INL) {
+      sincos_inl(ul, &sl, &cl);
+      sincos_inl(uh, &sh, &ch);
+    } else {
+      sincos_cold(ul, &sl, &cl);
+      sincos_cold(uh, &sh, &ch);
+    }
     const double Fl = axis == 0 ? sl : cl, Fh = axis == 0 ? sh : ch;
     const double dl = axis == 0 ? fabs(cl) : fabs(sl), dh = axis == 0 ? fabs(ch) : fabs(sh);
     const double shift = axis == 0 ? 0.0 : 0.5 * kPi;
@@ -543,7 +552,7 @@ struct Cell {
   // from the traces of the cells below (tl) and above (th) it; v as from
   // line_velocity.  XBC: where xl (xh) is set, the state below (above) at
   // point r is ext[r * S] instead (the BC_RIEMANN exterior slot).
-  template <bool XBC>
+  template <bool XBC, bool INL = false>
   __device__ static inline void face_moments(int axis, const double (&tl)[N], const double (&th)[N],
                                              const double (&v)[Q], bool xl, bool xh, const double* ext,
                                              double (&g)[N]) {
@@ -557,7 +566,7 @@ struct Cell {
       }
       double H;
       if constexpr (FLUX == FLUX_KPP)
-        H = llf_kpp(axis, ul, uh);
+        H = llf_kpp<INL>(axis, ul, uh);
       else
         H = llf(v[r], ul, uh);
       face_acc(r, H, g);
@@ -1130,7 +1139,9 @@ __device__ inline void stage_tile(const StageArgs& A, double* lds, int ix0, int 
   if constexpr (SHARE) {
     // face phase: every x face of the tile, then every y face, one per
     // thread and round (face_task); the two waves that take the faces left
-    // over change with the tile, so that no SIMD takes them on every tile
+    // over change with the tile, so that no SIMD takes them on every tile.
+    // Few registers are live here: the KPP flux takes its sine and cosine
+    // inline (16x16 P2 stage 175 -> 129 us at 1024^2)
     constexpr int NT = TX * TY, NW = NT / 64;
     static_assert(NT % 64 == 0 && FG::NXF - NT <= 64 && FG::NYF - NT <= 64, "one extra round of faces");
     auto face = [&](int axis, int e) {
@@ -1149,7 +1160,7 @@ __device__ inline void stage_tile(const StageArgs& A, double* lds, int ix0, int 
           xh = l == n - 1;
         }
       }
-      C::template face_moments<XBC>(axis, tl, th, v, xl, xh, lds + (xl ? lo : hi), g);
+      C::template face_moments<XBC, true>(axis, tl, th, v, xl, xh, lds + (xl ? lo : hi), g);
       double* dst = axis == 0 ? fxl + e : fyl + e;
 #pragma unroll
       for (int k = 0; k < N; ++k) dst[k * (axis == 0 ? FG::XS : FG::YS)] = g[k];
@@ -1232,7 +1243,10 @@ __global__ void __launch_bounds__(DIM == 2 ? TX * TY : TX) stage_kernel(const St
 // u_h at a node, the face traces and the fluxes are computed by the same
 // functions as in the per-cell path (xline/ynode, trace/face_node,
 // llf_kpp), and wave 0 sums them in the same order (residual with VS = 64,
-// face_acc, add_face), so the result is the same bit for bit.
+// face_acc, add_face), so the result is the same bit for bit.  The node
+// tasks hold few registers, so they take the sine and cosine inline
+// (sincos_inl: no call frame in scratch memory; 7.8 -> 6.3 us per stage at
+// 128^2 P2, 17.1 -> 13.1 at 256^2).
 template <int P, int MODE, int V0, int NTH>
 __device__ inline void kpp_split_tile(const StageArgs& A, double* lds, int ix0, int iy0) {
   constexpr int TX = 8, TY = 8;
@@ -1270,7 +1284,7 @@ __device__ inline void kpp_split_tile(const StageArgs& A, double* lds, int ix0, 
     double s1[N];
     C::xline([&](int j) { return lds[j * S + slot]; }, qx, s1);
     double Fx, Fy;
-    sincos_cold(C::ynode(s1, qy), &Fx, &Fy);
+    sincos_inl(C::ynode(s1, qy), &Fx, &Fy);
     vol[o] = Fx;
     vol[o + Q * Q * 64] = Fy;
   };
@@ -1292,7 +1306,7 @@ __device__ inline void kpp_split_tile(const StageArgs& A, double* lds, int ix0, 
       C::template trace<true>(axis, [&](int q) { return lds[q * S + hi]; }, th);
       double ul, uh;
       C::face_node(tl, th, r, ul, uh);
-      fnl[o] = C::llf_kpp(axis, ul, uh);
+      fnl[o] = C::template llf_kpp<true>(axis, ul, uh);
     }
     for (int v = V0 * 64 + u; v < NV; v += NTH - H0) vol_node(v);
   }
