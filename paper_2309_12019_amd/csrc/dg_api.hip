@@ -647,10 +647,10 @@ int dg_validate_desc(const dg_mesh_desc* desc) {
 // its LDS exceeds the limit, and 8x8 when the mesh has fewer 16x16 tiles
 // than compute units (four times the workgroups: 128^2 P2 25.0 -> 20.4 us
 // per step for the four-quadrant problem, 20.7 -> 16.2 for Burgers).  The
-// KPP flux takes 8x8 (its kernel of 4 to 16 waves per tile) up to three
-// 16x16 tiles per compute unit: P2 stage 25.3 -> 7.9 us at 128^2, 26.1 ->
-// 16.9 at 256^2, 38.5 -> 34.8 at 384^2, but 50 -> 57 at 512^2, where the
-// 16x16 kernel fills the GPU.
+// KPP flux takes 8x8 (its kernel of 4 to 16 waves per tile) below four
+// 16x16 tiles per compute unit: P2 stage 19.6 -> 6.4 us at 128^2, 20.2 ->
+// 13.3 at 256^2, 40.6 -> 35.6 at 448^2; at 512^2 both take 42.7 us, and
+// beyond the 16x16 kernel is faster (131 against 160 us at 1024^2).
 void default_tile(dg_ctx* c) {
   if (c->d.dim == 1) {
     c->tx = 256;
@@ -660,7 +660,7 @@ void default_tile(dg_ctx* c) {
   c->tx = c->ty = 16;
   const long long t16 = (long long)((c->d.nx + 15) / 16) * ((c->d.ny + 15) / 16);
   if (stage_lds_bytes(2, c->nl, c->d.p, c->d.flux, 16, 16) > (size_t)c->max_lds || t16 < (long long)c->cus ||
-      (c->d.flux == DG_FLUX_KPP && t16 <= 3LL * c->cus))
+      (c->d.flux == DG_FLUX_KPP && t16 < 4LL * c->cus))
     c->tx = c->ty = 8;
 }
 
@@ -686,7 +686,7 @@ void resolve_fused(dg_ctx* c) {
   // the KPP flux: the per-stage kernel spreads the sine and cosine of every
   // node over up to 16 waves per tile; the fused kernel evaluates them for
   // each cell on one thread and recomputes the rings (128^2 P2: 84 us per
-  // step fused, 23 us per-stage)
+  // step fused, 18.6 us per-stage)
   if (c->d.flux == DG_FLUX_KPP) {
     c->fused = false;
     return;

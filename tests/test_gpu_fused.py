@@ -105,11 +105,12 @@ def test_fused_automatic_choice_and_errors():
     small.set_fused(-1)
     assert small.fused()
     # the KPP flux keeps the per-stage kernel; meshes with fewer 16x16 tiles
-    # than compute units take 8x8 tiles there, and KPP meshes up to three
+    # than compute units take 8x8 tiles there, and KPP meshes below four
     # 16x16 tiles per compute unit (on the 256 compute units of the GPU)
     kpp = dgweno.DG.from_workload(inputs.kpp2d(128, 2, steps=1))
     assert not kpp.fused() and kpp.tile() == (8, 8)
     assert dgweno.DG.from_workload(inputs.kpp2d(384, 2, steps=1)).tile() == (8, 8)
+    assert dgweno.DG.from_workload(inputs.kpp2d(496, 2, steps=1)).tile() == (8, 8)
     assert dgweno.DG.from_workload(inputs.kpp2d(512, 2, steps=1)).tile() == (16, 16)
     assert dgweno.DG.from_workload(inputs.burgers2d_riemann(128, 2)).tile() == (8, 8)
     assert small.tile() == (16, 16) and large.tile() == (16, 16)
