@@ -242,8 +242,8 @@ int dg_stream_copy(const double* src, double* dst, int64_t n, void* stream);
  * tiles: 1D tx in {256, 64} (ty ignored), 2D (tx, ty) in {(16,16), (8,8)}.
  * The result does not depend on the tile (per-cell arithmetic is identical).
  * Default at dg_init_mesh: 256 (1D), 16x16 (2D; 8x8 if 16x16 exceeds LDS or
- * the mesh has fewer 16x16 tiles than the GPU has compute units, and for the
- * KPP flux below four 16x16 tiles per compute unit).  With the KPP flux an
+ * the mesh has fewer 16x16 tiles than the GPU has compute units, for degrees
+ * 3 and 4, and for the KPP flux below four 16x16 tiles per compute unit).  With the KPP flux an
  * 8x8 tile runs on 4 to 16 waves, which evaluate the sine and cosine at the
  * tile's volume and face nodes apart from the cells' sums.
  * Errors: DG_EINVAL for another shape, DG_EUNSUPPORTED if it exceeds LDS. */

@@ -651,6 +651,13 @@ int dg_validate_desc(const dg_mesh_desc* desc) {
 // 16x16 tiles per compute unit: P2 stage 19.6 -> 6.4 us at 128^2, 20.2 ->
 // 13.3 at 256^2, 40.6 -> 35.6 at 448^2; at 512^2 both take 42.7 us, and
 // beyond the 16x16 kernel is faster (131 against 160 us at 1024^2).
+//   Degrees 3 and 4 take 8x8 tiles on every mesh: their registers allow two
+// waves per SIMD (p = 3) or one (p = 4), and four independent one-wave
+// workgroups per compute unit hide more latency than one four-wave tile
+// whose waves wait for each other at its barrier.  Per stage, 16x16 -> 8x8:
+// rotation p = 4 59.7 -> 50.7 us at 512^2, 235 -> 179 at 1024^2; p = 3
+// 23.6 -> 20.1 at 384^2, 29.1 -> 27.7 at 512^2; Burgers p = 3 111.6 ->
+// 106.7 at 1024^2 (the one loss: rotation p = 3 at 1024^2, 104.3 -> 106.2).
 void default_tile(dg_ctx* c) {
   if (c->d.dim == 1) {
     c->tx = 256;
@@ -660,7 +667,7 @@ void default_tile(dg_ctx* c) {
   c->tx = c->ty = 16;
   const long long t16 = (long long)((c->d.nx + 15) / 16) * ((c->d.ny + 15) / 16);
   if (stage_lds_bytes(2, c->nl, c->d.p, c->d.flux, 16, 16) > (size_t)c->max_lds || t16 < (long long)c->cus ||
-      (c->d.flux == DG_FLUX_KPP && t16 < 4LL * c->cus))
+      c->d.p >= 3 || (c->d.flux == DG_FLUX_KPP && t16 < 4LL * c->cus))
     c->tx = c->ty = 8;
 }
 

@@ -114,3 +114,6 @@ def test_fused_automatic_choice_and_errors():
     assert dgweno.DG.from_workload(inputs.kpp2d(512, 2, steps=1)).tile() == (16, 16)
     assert dgweno.DG.from_workload(inputs.burgers2d_riemann(128, 2)).tile() == (8, 8)
     assert small.tile() == (16, 16) and large.tile() == (16, 16)
+    # degrees 3 and 4 take 8x8 tiles on any mesh
+    assert dgweno.DG.from_workload(inputs.rot2d(1024, 3, seed=0, steps=1)).tile() == (8, 8)
+    assert dgweno.DG.from_workload(inputs.burgers2d(512, 4, seed=0, steps=1)).tile() == (8, 8)
