@@ -1238,8 +1238,8 @@ __global__ void __launch_bounds__(DIM == 2 ? TX * TY : TX) stage_kernel(const St
 //   * in the node phase the waves evaluate the node fluxes: (sin u, cos u)
 //     at the Q^2 volume nodes of every cell and the LLF flux at the Q nodes
 //     of every face of the tile (each face once), into LDS.  Wave 0 takes V0
-//     rounds of volume nodes beside the sensor; the other waves take every
-//     face node, then the remaining volume nodes.
+//     rounds of volume nodes beside the sensor (split_v0); the other waves
+//     take every face node, then the remaining volume nodes.
 // u_h at a node, the face traces and the fluxes are computed by the same
 // functions as in the per-cell path (xline/ynode, trace/face_node,
 // llf_kpp), and wave 0 sums them in the same order (residual with VS = 64,
@@ -1349,10 +1349,13 @@ __device__ inline void kpp_split_tile(const StageArgs& A, double* lds, int ix0, 
 }
 
 // Volume node rounds of wave 0 in kpp_split_tile with nth threads: Q^2 / 2
-// at four waves, Q^2 / 4 at eight, Q^2 / 8 at sixteen (measured at p = 2
-// with the sensor: 9.5, 8.2 and 7.8 us per stage on a 128^2 mesh, against
-// 10.4-11.0, 8.7 and 7.8 for other splits)
-__host__ __device__ constexpr int split_v0(int p, int nth) { return (p + 2) * (p + 2) * 128 / nth; }
+// at four waves, Q^2 / 8 at eight, Q^2 / 16 at sixteen (measured at p = 2
+// with the sensor, per stage: four waves 7.24 us at 128^2 and 12.9 at 256^2
+// against 7.4-7.8 and 12.9-13.4 for 0-10 rounds; eight waves 8.42 at 176^2
+// against 8.49-8.73; sixteen 6.07 at 128^2 against 6.25-6.36)
+__host__ __device__ constexpr int split_v0(int p, int nth) {
+  return (p + 2) * (p + 2) / (nth <= 256 ? 2 : nth <= 512 ? 8 : 16);
+}
 
 // Waves per tile of kpp_split_kernel for a mesh of `tiles` 8x8 tiles on
 // `cus` compute units: sixteen while every tile has a compute unit of its

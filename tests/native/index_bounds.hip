@@ -514,7 +514,7 @@ int main(int argc, char** argv) {
   static_assert(split_waves(256, 256, 2) == 16 && split_waves(257, 256, 2) == 8 && split_waves(512, 256, 2) == 8 &&
                     split_waves(513, 256, 2) == 4 && split_waves(256, 256, 1) == 16 &&
                     split_waves(256, 256, 3) == 8 && split_waves(256, 256, 4) == 4 && split_v0(2, 256) == 8 &&
-                    split_v0(2, 512) == 4 && split_v0(2, 1024) == 2,
+                    split_v0(2, 512) == 2 && split_v0(2, 1024) == 1,
                 "KPP split: waves per tile and wave 0's volume rounds");
   static_assert(shares_faces(2, 2, FLUX_BURGERS, 16, 16) && shares_faces(2, 2, FLUX_KPP, 16, 16) &&
                     !shares_faces(2, 2, FLUX_LINADV, 16, 16) && !shares_faces(2, 3, FLUX_BURGERS, 16, 16) &&
