@@ -210,12 +210,14 @@ int dg_step_static(const dg_mesh_desc* desc, double* U, double dt, double t);
 /* nsteps SSP steps of size dt (eq. ssp, or the order rk_order selects), in
  * place on U (device): the fully discrete scheme of Sec. 2 run over a fixed
  * step, the stabilisation of Secs. 3 and 4 re-evaluated in every stage.
- * With bc_kind RIEMANN the stage launches go to the stream directly (their
- * exterior state changes with time); otherwise the stage launches (3, 2 or 6
- * per step; one fused launch per step where dg_set_fused selects it) are
- * recorded once into a HIP graph (cached for the same U, dt and chunk
- * length) and replayed on the context stream.  nsteps >= 0.  With
- * check_finite, DG_ENONFINITE if U holds NaN or Inf after the run. */
+ * The stage launches (3, 2 or 6 per step; one fused launch per step where
+ * dg_set_fused selects it) are recorded once into a HIP graph (cached for the
+ * same U, dt and chunk length) and replayed on the context stream.  With
+ * bc_kind RIEMANN the stages read their times (on which the exterior state
+ * depends) as offsets from a device copy of the context clock, which a
+ * one-thread launch sets before each replay, so the same graph serves any
+ * time.  nsteps >= 0.  With check_finite, DG_ENONFINITE if U holds NaN or Inf
+ * after the run. */
 int dg_run(dg_ctx* ctx, double* U, double dt, int32_t nsteps);
 
 /* Stable step for the fixed-step reading of "CFL" (the configurations quote

@@ -81,6 +81,8 @@ struct dg_ctx {
   double* U1 = nullptr;
   double* U2 = nullptr;
   double* U3 = nullptr;           // third stage buffer (five-stage method only)
+  double* tclock = nullptr;       // BC_RIEMANN: device copy of the time a run or step starts from; the
+                                  // stages take their times as offsets from it (graphs replay at any time)
   double t = 0.0;                 // the context's clock: time of the state dg_step/dg_run advance
   double* red = nullptr;          // per-block partial results of reductions
   size_t red_len = 0;
@@ -167,8 +169,16 @@ size_t stage_lds_bytes(int dim, int nl, int p, int flux, int tx, int ty) {
   return sizeof(double) * (size_t)dgk::stage_kernel_lds_doubles(dim, nl, p, flux, tx, dim == 2 ? ty : 1);
 }
 
+// BC_RIEMANN: the device clock := t (on st, before the stages that read it)
+int set_clock(dg_ctx* c, hipStream_t st, double t) {
+  if (!c->tclock) return DG_OK;
+  const hipError_t e = dgk_set_clock(c->tclock, t, st);
+  return e == hipSuccess ? DG_OK : hip_fail(e, "clock");
+}
+
 // one stage: out = a*un + b*(uin + dt*L(uin)), or out = L(uin) when rhs_only;
-// t is the time of uin (it enters through the BC_RIEMANN exterior state only)
+// t is the time of uin (it enters through the BC_RIEMANN exterior state only;
+// there, with the context's clock, t is the offset from the clock's time)
 int stage(dg_ctx* c, hipStream_t st, const double* uin, const double* un, double* out, double* gamma,
           double a, double b, double dt, int rhs_only, double t = 0.0) {
   LaunchReq r{};
@@ -176,8 +186,16 @@ int stage(dg_ctx* c, hipStream_t st, const double* uin, const double* un, double
   r.flux = c->d.flux;
   r.mode = c->d.mode;
   r.args = base_args(c);
-  if (c->d.dim == 2 && c->d.flux == DG_FLUX_KPP)
-    r.waves = dgk::split_waves((long long)((c->d.nx + 7) / 8) * ((c->d.ny + 7) / 8), c->cus, c->d.p);
+  r.args.tclock = c->tclock;
+  // 8x8 tiles of several waves while the mesh has no more tiles than the
+  // GPU has compute units (or, for the KPP flux, a few per compute unit)
+  if (c->d.dim == 2 && c->tx == 8) {
+    const long long t8 = (long long)((c->d.nx + 7) / 8) * ((c->d.ny + 7) / 8);
+    if (c->d.flux == DG_FLUX_KPP)
+      r.waves = dgk::split_waves(t8, c->cus, c->d.p);
+    else
+      r.waves = t8 <= (long long)c->cus ? 4 : 1;
+  }
   r.args.uin = uin;
   r.args.un = un;
   r.args.out = out;
@@ -753,6 +771,10 @@ int dg_init_mesh(const dg_mesh_desc* desc, dg_ctx** out) {
     dg_destroy(c);
     return fail(DG_ENOMEM, "reduction buffer: %s", hipGetErrorString(e));
   }
+  if (c->d.bc_kind == DG_BC_RIEMANN && (e = hipMalloc(&c->tclock, sizeof(double))) != hipSuccess) {
+    dg_destroy(c);
+    return fail(DG_ENOMEM, "clock: %s", hipGetErrorString(e));
+  }
   if ((e = hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking)) != hipSuccess) {
     dg_destroy(c);
     return hip_fail(e, "hipStreamCreate");
@@ -769,6 +791,7 @@ void dg_destroy(dg_ctx* c) {
   if (c->U1) (void)hipFree(c->U1);
   if (c->U2) (void)hipFree(c->U2);
   if (c->U3) (void)hipFree(c->U3);
+  if (c->tclock) (void)hipFree(c->tclock);
   if (c->red) (void)hipFree(c->red);
   if (c->A1) (void)hipFree(c->A1);
   if (c->A2) (void)hipFree(c->A2);
@@ -835,14 +858,17 @@ int dg_rhs(dg_ctx* c, const double* U, double* dUdt, double* gamma) {
   if (!c || !U || !dUdt) return fail(DG_EINVAL, "NULL argument");
   DeviceGuard guard(c->dev);
   if (U == dUdt) return fail(DG_EINVAL, "U and dUdt must not overlap");
-  return stage(c, c->stream, U, nullptr, dUdt, gamma, 0.0, 1.0, 0.0, 1, c->t);
+  const int rc = set_clock(c, c->stream, c->t);
+  if (rc) return rc;
+  return stage(c, c->stream, U, nullptr, dUdt, gamma, 0.0, 1.0, 0.0, 1, c->tclock ? 0.0 : c->t);
 }
 
 int dg_step(dg_ctx* c, double* U, double dt) {
   if (!c || !U) return fail(DG_EINVAL, "NULL argument");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DG_EINVAL, "dt must be finite and > 0");
   DeviceGuard guard(c->dev);
-  const int rc = rk_steps(c, c->stream, U, dt, 1, c->t);
+  int rc = set_clock(c, c->stream, c->t);
+  if (rc == DG_OK) rc = rk_steps(c, c->stream, U, dt, 1, c->tclock ? 0.0 : c->t);
   if (rc == DG_OK) c->t += dt;
   if (rc == DG_OK && c->d.check_finite) return finite_or_fail(c, U);
   return rc;
@@ -944,15 +970,10 @@ int dg_run(dg_ctx* c, double* U, double dt, int32_t nsteps) {
 
 // dg_run's steps (arguments checked by the caller)
 static int run_steps(dg_ctx* c, double* U, double dt, int32_t nsteps) {
-  if (c->d.bc_kind != DG_BC_CONSTANT) {
-    // the exterior state depends on the stage times, which a replayed graph
-    // would repeat: launch the steps directly
-    const int rc = rk_steps(c, c->stream, U, dt, nsteps, c->t);
-    if (rc == DG_OK) c->t += nsteps * dt;
-    return rc;
-  }
   // whole chunks of up to 64 steps replay one captured graph; a remainder
-  // replays a second graph of its own length (both cached per (U, dt, length))
+  // replays a second graph of its own length (both cached per (U, dt, length)).
+  // Under BC_RIEMANN the stages read their times from the device clock,
+  // set before each replay to the time that replay starts from.
   const int chunk = nsteps < 64 ? nsteps : 64;
   const int reps = nsteps / chunk, rest = nsteps % chunk;
   hipGraphExec_t exec = nullptr, tail = nullptr;
@@ -961,10 +982,12 @@ static int run_steps(dg_ctx* c, double* U, double dt, int32_t nsteps) {
   if (rc == DG_OK && rest) rc = run_graph(c, U, dt, rest, &tail);
   if (rc) return rc;
   for (int i = 0; i < reps; ++i) {
+    if ((rc = set_clock(c, c->stream, c->t + (double)i * chunk * dt))) return rc;
     hipError_t e = hipGraphLaunch(exec, c->stream);
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
   }
   if (rest) {
+    if ((rc = set_clock(c, c->stream, c->t + (double)reps * chunk * dt))) return rc;
     hipError_t e = hipGraphLaunch(tail, c->stream);
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
   }

@@ -51,6 +51,7 @@ struct StageArgs {
   double q, bthr, wnb, eps, wpow, lam_over;
   double theta;                  // exponent of the Zhao et al. sensor (MODE_ZHAO)
   int tx, ty;                    // tile (one of the compiled shapes; ty = 1 in 1D)
+  const double* tclock;          // BC_RIEMANN: if set, uin's time is *tclock + t (t an offset)
 };
 
 // Tile geometry: TX x TY cells per workgroup (TY = 1 in 1D) plus a one-cell
@@ -263,8 +264,9 @@ struct Cell {
 
   // BC_RIEMANN exterior slots: a slot outside one boundary holds, in planes
   // 0..Q-1, the exact solution at the Q Gauss points of the one face that
-  // reads it (node order of the face loop) at time A.t; a slot outside two
-  // boundaries (used by no face) holds zeros; slots inside are left alone.
+  // reads it (node order of the face loop) at uin's time (A.t, or *A.tclock
+  // + A.t); a slot outside two boundaries (used by no face) holds zeros;
+  // slots inside are left alone.
   __device__ static inline void riemann_slot(const StageArgs& A, int gx, int gy, double (&v)[NL]) {
     static_assert(Q <= NL, "the face nodes must fit the slot's planes");
     const bool ox = (unsigned)gx >= (unsigned)A.nx, oy = (unsigned)gy >= (unsigned)A.ny;
@@ -272,6 +274,7 @@ struct Cell {
 #pragma unroll
     for (int j = 0; j < NL; ++j) v[j] = 0.0;
     if (ox && oy) return;
+    const double t = A.tclock ? *A.tclock + A.t : A.t;
     const double hh = 0.5 * A.h;
 #pragma unroll
     for (int r = 0; r < Q; ++r) {
@@ -283,7 +286,7 @@ struct Cell {
         y = gy < 0 ? A.y0 : A.y0 + A.ny * A.h;
         x = fma(hh, TB::nd.x[r], A.x0 + (gx + 0.5) * A.h);
       }
-      v[r] = riemann_exact(x, y, A.t);
+      v[r] = riemann_exact(x, y, t);
     }
   }
 
@@ -1005,10 +1008,16 @@ __host__ __device__ inline int split_cell_face(int lc, int f) {
   const int lx = lc % 8, ly = lc / 8;
   return f < 2 ? ly * 9 + lx + (f & 1) : ly * 8 + lx + (f & 1) * 8;
 }
-// LDS of the per-stage kernel on this tile
+// LDS of the per-stage kernels on this tile (2D 8x8: the larger of the
+// one-wave and the four-wave kernel, roles_tile)
 __host__ __device__ inline int stage_kernel_lds_doubles(int dim, int nl, int p, int flux, int tx, int ty) {
-  return splits_nodes(dim, flux, tx, ty) ? split_lds_doubles(nl, quad_points(dim, p, flux))
-                                         : stage_lds_doubles(dim, nl, flux, tx, ty);
+  if (splits_nodes(dim, flux, tx, ty)) return split_lds_doubles(nl, quad_points(dim, p, flux));
+  const int one = stage_lds_doubles(dim, nl, flux, tx, ty);
+  if (dim == 2 && tx == 8 && ty == 8) {
+    const int four = tile_lds_doubles(2, nl, 8, 8) + face_lds_doubles(p + 1, 8, 8) + 64;
+    return four > one ? four : one;
+  }
+  return one;
 }
 
 // The slots thread t of the tile at (ix0, iy0) loads: its own cell's slot
@@ -1225,6 +1234,150 @@ __global__ void __launch_bounds__(DIM == 2 ? TX * TY : TX) stage_kernel(const St
   const int bx = tile % gridDim.x, by = tile / gridDim.x;
   stage_tile<DIM, P, FLUX, MODE, TX, TY, XBC && DIM == 2 && FLUX == FLUX_BURGERS>(A, lds, bx * TX,
                                                                                 DIM == 2 ? by * TY : 0);
+}
+
+// Small meshes on 8 x 8 tiles (the linear and Burgers fluxes): four waves
+// per tile.  With no more tiles than compute units, one-wave tiles leave
+// three of each compute unit's four SIMDs idle and every lane runs its
+// cell's whole stage as one dependent chain; here the parts of the stage
+// run side by side on the tile's four waves:
+//   * wave 0 loads the tile (as stage_tile does) and evaluates the volume
+//     terms and lambda_e of its 64 cells (residual without faces);
+//   * wave 1 evaluates gamma_e of the same cells (their coefficients read
+//     back from LDS), into LDS;
+//   * waves 2 and 3 evaluate each of the tile's 144 faces once, into LDS,
+//     as the shared-face phase of stage_tile does;
+// then, after a barrier, wave 0 adds each cell's four faces in the order of
+// the per-cell evaluation, finishes and stores: the same functions in the
+// same order as stage_tile, so the same result bit for bit.
+// XBC: the BC_RIEMANN exterior state compiled in (2D Burgers).
+constexpr int kRoleThreads = 256;
+__host__ __device__ inline int roles_lds_doubles(int nl, int n) {
+  return tile_lds_doubles(2, nl, 8, 8) + face_lds_doubles(n, 8, 8) + 64;
+}
+// Face task i (< 144) of waves 2 and 3: axis and face index (face_slot's order)
+__host__ __device__ inline void roles_face_task(int i, int& axis, int& e) {
+  axis = i >= 72;
+  e = axis ? i - 72 : i;
+}
+template <int P, int FLUX, int MODE, bool XBC>
+__device__ inline void roles_tile(const StageArgs& A, double* lds, int ix0, int iy0) {
+  constexpr int TX = 8, TY = 8;
+  using G = TileGeom<2, TX, TY>;
+  using C = Cell<2, P, FLUX, MODE, G::S, G::W>;
+  using FG = FaceGeom<TX, TY>;
+  constexpr int NL = C::NL, N = C::N, S = G::S;
+  static_assert(FLUX == FLUX_LINADV || FLUX == FLUX_BURGERS, "the KPP flux has kpp_split_tile");
+  static_assert(FG::NXF == 72 && FG::NYF == 72, "roles_face_task assumes 8 x 8 tiles");
+  double* const fxl = lds + NL * S;      // x faces
+  double* const fyl = fxl + N * FG::XS;  // y faces
+  double* const gaml = fyl + N * FG::YS;  // gamma_e of the tile's cells
+  const int nx = A.nx, ny = A.ny;
+  const int t = threadIdx.x;
+  const int lc = t & 63, w = t >> 6;
+  int sc, gx, gy, hs, hgx, hgy;
+  const bool halo = tile_slots<2, TX, TY>(lc, ix0, iy0, sc, gx, gy, hs, hgx, hgy);
+  const bool active = gx < nx && gy < ny;
+  bool xbc = false;  // exterior slots from the exact solution (BC_RIEMANN)
+  if constexpr (XBC) xbc = A.bc_kind == BC_RIEMANN;
+  double c[NL];
+  if (w == 0) {
+    load_cell<2, NL>(A, gx, gy, c);
+    if constexpr (XBC) {
+      if (xbc) {
+        C::riemann_slot(A, gx, gy, c);
+        if (halo) {
+          double v[NL];
+          load_cell<2, NL>(A, hgx, hgy, v);
+          C::riemann_slot(A, hgx, hgy, v);
+#pragma unroll
+          for (int j = 0; j < NL; ++j) lds[j * S + hs] = v[j];
+        }
+      }
+    }
+    if (!xbc && halo) load_slot<2, NL, S>(A, lds, hs, hgx, hgy);
+#pragma unroll
+    for (int j = 0; j < NL; ++j) lds[j * S + sc] = c[j];
+  }
+  tile_barrier();
+  double R[NL], lam = 0.0;
+  if (w == 0) {
+    if (active) C::template residual<false, false>(A, lds + sc, c, gx, gy, R, lam);
+  } else if (w == 1) {
+    if (active) {
+      double cc[NL];
+#pragma unroll
+      for (int j = 0; j < NL; ++j) cc[j] = lds[j * S + sc];
+      gaml[lc] = C::template gamma_of<true>(A, lds + sc, cc, gx, gy);
+    }
+  } else {
+    for (int i = t - 128; i < FG::NXF + FG::NYF; i += kRoleThreads - 128) {
+      int axis, e;
+      roles_face_task(i, axis, e);
+      int fgx, fgy;
+      const int lo = face_slot<TX, TY>(axis, e, ix0, iy0, fgx, fgy);
+      const int hi = lo + (axis == 0 ? 1 : G::W);
+      double tl[N], th[N], v[C::Q], g[N];
+      C::template trace<false>(axis, [&](int q) { return lds[q * S + lo]; }, tl);
+      C::template trace<true>(axis, [&](int q) { return lds[q * S + hi]; }, th);
+      C::line_velocity(A, axis, axis == 0 ? fgy : fgx, v);
+      bool xl = false, xh = false;
+      if constexpr (XBC) {
+        if (xbc) {
+          const int l = axis == 0 ? fgx : fgy, n = axis == 0 ? nx : ny;
+          xl = l == -1;
+          xh = l == n - 1;
+        }
+      }
+      C::template face_moments<XBC>(axis, tl, th, v, xl, xh, lds + (xl ? lo : hi), g);
+      double* dst = axis == 0 ? fxl + e : fyl + e;
+#pragma unroll
+      for (int k = 0; k < N; ++k) dst[k * (axis == 0 ? FG::XS : FG::YS)] = g[k];
+    }
+  }
+  tile_barrier();
+  if (w != 0 || !active) return;
+  const int lx = lc % TX, ly = lc / TX;
+  const int ex = ly * (TX + 1) + lx, ey = ly * TX + lx;
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    const double* src = f < 2 ? fxl + ex + (f & 1) : fyl + ey + (f & 1) * TX;
+    double g[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) g[k] = src[k * (f < 2 ? FG::XS : FG::YS)];
+    C::add_face(f, g, R);
+  }
+  double L[NL];
+  C::finish(A, c, gaml[lc], lam, R, L);
+  const size_t cell = (size_t)gy * nx + gx;
+  if (A.gamma) A.gamma[cell] = gaml[lc];
+  double* dst = A.out + cell * NL;
+  if (A.rhs_only) {
+#pragma unroll
+    for (int j = 0; j < NL; ++j) dst[j] = L[j];
+  } else {
+    const bool comb = A.a != 0.0;
+    double un[NL];
+    if (comb) {
+#pragma unroll
+      for (int j = 0; j < NL; ++j) un[j] = A.un[cell * NL + j];
+    }
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+      double v = A.b * fma(A.dt, L[j], c[j]);
+      if (comb) v = fma(A.a, un[j], v);
+      dst[j] = v;
+    }
+  }
+}
+
+// Grid as for stage_kernel on 8 x 8 tiles, kRoleThreads threads.
+template <int P, int FLUX, int MODE, bool XBC>
+__global__ void __launch_bounds__(kRoleThreads) roles_kernel(const StageArgs A) {
+  extern __shared__ double lds[];
+  const int tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int bx = tile % gridDim.x, by = tile / gridDim.x;
+  roles_tile<P, FLUX, MODE, XBC && FLUX == FLUX_BURGERS>(A, lds, bx * 8, by * 8);
 }
 
 // The per-stage KPP kernel on 8 x 8 tiles.  The sine and cosine at every

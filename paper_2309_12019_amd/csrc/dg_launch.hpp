@@ -22,7 +22,8 @@ struct LaunchReq {
   int kind;
   int flux, mode;
   StageArgs args;       // LAUNCH_STAGE, LAUNCH_STEP, LAUNCH_LAMBDA
-  int waves;            // LAUNCH_STAGE, 2D KPP on 8x8 tiles: waves per tile (4, 8 or 16; 0: 4)
+  int waves;            // LAUNCH_STAGE, 2D on 8x8 tiles: waves per tile (KPP: 4, 8 or 16, 0: 4;
+                        // linear and Burgers: 4 for roles_kernel, else one)
   const double* src;    // LAUNCH_PROJECT: nodal values; LAUNCH_LAMBDA: state
   double* dst;          // LAUNCH_PROJECT: coefficients; LAUNCH_LAMBDA: block maxima
   long long ncells;
@@ -48,6 +49,9 @@ hipError_t dgk_launch_2_3(const dgk::LaunchReq*);
 hipError_t dgk_launch_2_4(const dgk::LaunchReq*);
 // dg_util.hip: partial[b] = non-finite entries of U[0..n) in block b's share
 hipError_t dgk_count_nonfinite(const double* U, long long n, double* partial, int nblocks, hipStream_t st);
+// dg_util.hip: clock[0] = t (one thread, on the stream: stage kernels read
+// the BC_RIEMANN clock from device memory, so captured graphs replay at any time)
+hipError_t dgk_set_clock(double* clock, double t, hipStream_t st);
 // dg_util.hip: dst[0..n) = src[0..n)
 hipError_t dgk_stream_copy(const double* src, double* dst, long long n, hipStream_t st);
 }

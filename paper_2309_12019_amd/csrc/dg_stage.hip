@@ -59,6 +59,17 @@ hipError_t launch_kpp_split(const StageArgs& A, hipStream_t st, int waves) {
   return launch_kpp_split_n<MODE, 256>(A, st);
 }
 
+// linear and Burgers fluxes on 8x8 tiles, four waves per tile (roles_kernel)
+template <int FLUX, int MODE, bool XBC>
+hipError_t launch_roles(const StageArgs& A, hipStream_t st) {
+  constexpr int NL = (DGK_P + 1) * (DGK_P + 1);
+  auto k = roles_kernel<DGK_P, FLUX, MODE, XBC>;
+  const size_t lds = sizeof(double) * (size_t)roles_lds_doubles(NL, DGK_P + 1);
+  dim3 grid((A.nx + 7) / 8, (A.ny + 7) / 8);
+  hipLaunchKernelGGL(k, grid, dim3(kRoleThreads), lds, st, A);
+  return hipGetLastError();
+}
+
 template <int FLUX, int MODE>
 hipError_t launch_stage_fm(const StageArgs& A, hipStream_t st, int waves = 0) {
   if constexpr (DGK_DIM == 1) {
@@ -66,17 +77,23 @@ hipError_t launch_stage_fm(const StageArgs& A, hipStream_t st, int waves = 0) {
     return launch_tile<FLUX, MODE, 256, 1>(A, st);
   } else {
     // 2D Burgers: the kernel with the exact-solution exterior state only
-    // where it is needed
+    // where it is needed; 8x8 tiles of four waves on small meshes (waves = 4)
     if constexpr (FLUX == FLUX_BURGERS) {
       if (A.bc_kind == BC_RIEMANN) {
-        if (A.tx == 8) return launch_tile<FLUX, MODE, 8, 8, true>(A, st);
+        if (A.tx == 8) {
+          if (waves == 4) return launch_roles<FLUX, MODE, true>(A, st);
+          return launch_tile<FLUX, MODE, 8, 8, true>(A, st);
+        }
         return launch_tile<FLUX, MODE, 16, 16, true>(A, st);
       }
     }
     if constexpr (FLUX == FLUX_KPP) {
       if (A.tx == 8) return launch_kpp_split<MODE>(A, st, waves);
     } else {
-      if (A.tx == 8) return launch_tile<FLUX, MODE, 8, 8>(A, st);
+      if (A.tx == 8) {
+        if (waves == 4) return launch_roles<FLUX, MODE, false>(A, st);
+        return launch_tile<FLUX, MODE, 8, 8>(A, st);
+      }
     }
     return launch_tile<FLUX, MODE, 16, 16>(A, st);
   }
@@ -303,8 +320,8 @@ extern "C" hipError_t DGK_CAT(dgk_launch, DGK_DIM, DGK_P)(const LaunchReq* r) {
         if constexpr (DGK_DIM == 1) return launch_euler(r->mode, A, r->stream);
         return hipErrorInvalidValue;
       }
-      if (r->flux == FLUX_LINADV) return launch_stage_f<FLUX_LINADV>(r->mode, A, r->stream);
-      if (r->flux == FLUX_BURGERS) return launch_stage_f<FLUX_BURGERS>(r->mode, A, r->stream);
+      if (r->flux == FLUX_LINADV) return launch_stage_f<FLUX_LINADV>(r->mode, A, r->stream, r->waves);
+      if (r->flux == FLUX_BURGERS) return launch_stage_f<FLUX_BURGERS>(r->mode, A, r->stream, r->waves);
       if constexpr (DGK_DIM == 2) return launch_stage_f<FLUX_KPP>(r->mode, A, r->stream, r->waves);
       return hipErrorInvalidValue;
     }

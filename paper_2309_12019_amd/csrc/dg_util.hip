@@ -44,6 +44,17 @@ __global__ void __launch_bounds__(256) copy1_kernel(const double* __restrict__ s
 }  // namespace
 }  // namespace dgk
 
+namespace dgk {
+__global__ void __launch_bounds__(64) set_clock_kernel(double* clock, double t) {
+  if (threadIdx.x == 0) clock[0] = t;
+}
+}  // namespace dgk
+
+extern "C" hipError_t dgk_set_clock(double* clock, double t, hipStream_t st) {
+  hipLaunchKernelGGL(dgk::set_clock_kernel, dim3(1), dim3(64), 0, st, clock, t);
+  return hipGetLastError();
+}
+
 extern "C" hipError_t dgk_count_nonfinite(const double* U, long long n, double* partial, int nblocks,
                                           hipStream_t st) {
   hipLaunchKernelGGL(dgk::count_nonfinite_kernel, dim3(nblocks), dim3(256), 0, st, U, n, partial);

@@ -411,7 +411,8 @@ void check_kpp_split(int p) {
   const long long tile = tile_lds_doubles(2, nl, 8, 8), lds = split_lds_doubles(nl, q);
   CHECK(stage_kernel_lds_doubles(2, nl, p, FLUX_KPP, 8, 8) == lds &&
             stage_kernel_lds_doubles(2, nl, p, FLUX_KPP, 16, 16) == stage_lds_doubles(2, nl, FLUX_KPP, 16, 16) &&
-            stage_kernel_lds_doubles(2, nl, p, FLUX_BURGERS, 8, 8) == stage_lds_doubles(2, nl, FLUX_BURGERS, 8, 8),
+            stage_kernel_lds_doubles(2, nl, p, FLUX_BURGERS, 16, 16) == stage_lds_doubles(2, nl, FLUX_BURGERS, 16, 16) &&
+            stage_kernel_lds_doubles(2, nl, p, FLUX_BURGERS, 8, 8) >= stage_lds_doubles(2, nl, FLUX_BURGERS, 8, 8),
         "kpp split: LDS size");
   auto corner = [&](int s) {
     const int x = s % G::W, y = s / G::W;
@@ -463,6 +464,52 @@ void check_kpp_split(int p) {
   for (int nth : {256, 512, 1024}) CHECK(split_v0(p, nth) >= 0 && split_v0(p, nth) <= q * q, "kpp split: v0");
 }
 
+// The four-wave 8x8 kernel (roles_tile) at nl coefficients: its face tasks
+// cover each of the tile's 144 faces once, read slots inside the tile (no
+// corner) and write moments inside LDS; each cell reads back the moments of
+// its own four faces; the gamma exchange fits after the faces.
+void check_roles(int nl) {
+  using G = TileGeom<2, 8, 8>;
+  using FG = FaceGeom<8, 8>;
+  int n = 1;
+  while (n * n < nl) ++n;
+  const long long lds = roles_lds_doubles(nl, n);
+  CHECK(lds == tile_lds_doubles(2, nl, 8, 8) + (long long)n * (FG::XS + FG::YS) + 64, "roles: LDS size");
+  for (int flux : {FLUX_LINADV, FLUX_BURGERS})
+    CHECK(stage_kernel_lds_doubles(2, nl, n - 1, flux, 8, 8) >= lds, "roles: the API's LDS bound");
+  auto corner = [&](int s) {
+    const int x = s % G::W, y = s / G::W;
+    return (x == 0 || x == G::W - 1) && (y == 0 || y == G::H - 1);
+  };
+  std::vector<int> cx(FG::NXF, 0), cy(FG::NYF, 0);
+  const int ix0 = 2 * 8, iy0 = 7 * 8;
+  for (int t = 128; t < kRoleThreads; ++t)
+    for (int i = t - 128; i < FG::NXF + FG::NYF; i += kRoleThreads - 128) {
+      int axis, e;
+      roles_face_task(i, axis, e);
+      CHECK(axis >= 0 && axis < 2 && e >= 0 && e < (axis ? FG::NYF : FG::NXF), "roles: face task %d", i);
+      if (axis == 0 && e >= 0 && e < FG::NXF) cx[e]++;
+      if (axis == 1 && e >= 0 && e < FG::NYF) cy[e]++;
+      int gx, gy;
+      const int lo = face_slot<8, 8>(axis, e, ix0, iy0, gx, gy), hi = lo + (axis ? G::W : 1);
+      CHECK(lo >= 0 && hi < G::NS && !corner(lo) && !corner(hi), "roles: face %d slots %d %d", e, lo, hi);
+      const long long base = (long long)nl * G::S + (axis ? (long long)n * FG::XS : 0);
+      CHECK(base + (long long)(n - 1) * (axis ? FG::YS : FG::XS) + e < lds - 64, "roles: moments of face %d", e);
+    }
+  for (int e = 0; e < FG::NXF; ++e) CHECK(cx[e] == 1, "roles: x face %d evaluated %d times", e, cx[e]);
+  for (int e = 0; e < FG::NYF; ++e) CHECK(cy[e] == 1, "roles: y face %d evaluated %d times", e, cy[e]);
+  for (int lc = 0; lc < 64; ++lc) {
+    int sc, gx, gy, hs, hgx, hgy;
+    tile_slots<2, 8, 8>(lc, ix0, iy0, sc, gx, gy, hs, hgx, hgy);
+    const int lx = lc % 8, ly = lc / 8, ex = ly * 9 + lx, ey = ly * 8 + lx;
+    int fx, fy;
+    const int s0 = face_slot<8, 8>(0, ex, ix0, iy0, fx, fy), s1 = face_slot<8, 8>(0, ex + 1, ix0, iy0, fx, fy);
+    const int s2 = face_slot<8, 8>(1, ey, ix0, iy0, fx, fy), s3 = face_slot<8, 8>(1, ey + 8, ix0, iy0, fx, fy);
+    CHECK(s0 + 1 == sc && s1 == sc && s2 + G::W == sc && s3 == sc, "roles: faces of cell %d", lc);
+    CHECK((long long)nl * G::S + (long long)n * (FG::XS + FG::YS) + lc < lds, "roles: gamma slot of cell %d", lc);
+  }
+}
+
 // xcd_tile is a bijection of [0, g) for every grid size, and each XCD's
 // workgroups take one contiguous, increasing run of tiles.
 void check_xcd_order() {
@@ -508,6 +555,7 @@ int main(int argc, char** argv) {
       check_faces<8, 8>(nl, flux);
     }
   for (int p = 1; p <= 4; ++p) check_kpp_split(p);
+  for (int nl : {4, 9, 16, 25}) check_roles(nl);
   static_assert(splits_nodes(2, FLUX_KPP, 8, 8) && !splits_nodes(2, FLUX_KPP, 16, 16) &&
                     !splits_nodes(2, FLUX_BURGERS, 8, 8),
                 "the node split: 2D KPP on 8x8 tiles only");

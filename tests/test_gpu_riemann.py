@@ -86,6 +86,28 @@ def test_100_steps_parity(k, t0):
     assert abs(g.time() - (t0 + 100 * w.dt())) <= 1e-15 * 100
 
 
+def test_graph_replays_follow_the_clock():
+    """dg_run replays captured graphs (64 steps, then the remainder) whose
+    stages read their times from the context's device clock: two runs of 70
+    steps (each one replay of the 64-step graph and one of 6) from t = 0.02
+    against 140 oracle steps, and the clock after them."""
+    _note("[riemann graphs] 40^2 P2 WENO, 2 x 70 steps from t = 0.02")
+    w = inputs.burgers2d_riemann(40, 2, steps=140)
+    O = oracle_for(w)
+    U0 = oracle_initial(w, O)
+    ref = O.run(U0, w.dt(), 140, 0.02)
+    g = _dg().DG.from_workload(w)
+    g.set_time(0.02)
+    U = U0.cuda().contiguous()
+    g.run(U, w.dt(), 70)
+    g.run(U, w.dt(), 70)
+    torch.cuda.synchronize()
+    err = relinf(U.cpu(), ref)
+    _note(f"    rel Linf = {err:.3e}")
+    assert err <= 1e-11
+    assert abs(g.time() - (0.02 + 140 * w.dt())) <= 1e-15 * 140
+
+
 def test_refusals():
     dgweno = _dg()
     w = inputs.burgers2d_riemann(32, 2, steps=1)
