@@ -187,14 +187,16 @@ int stage(dg_ctx* c, hipStream_t st, const double* uin, const double* un, double
   r.mode = c->d.mode;
   r.args = base_args(c);
   r.args.tclock = c->tclock;
-  // 8x8 tiles of several waves while the mesh has no more tiles than the
-  // GPU has compute units (or, for the KPP flux, a few per compute unit)
+  // 8x8 tiles of several waves on meshes of a few tiles per compute unit:
+  // the KPP flux by split_waves; the others four waves up to three tiles
+  // per compute unit (per step, 192^2 P2 rotation 17.1 -> 15.7 us at 2.25
+  // tiles per CU, but 256^2 20.4 -> 23.1 at four)
   if (c->d.dim == 2 && c->tx == 8) {
     const long long t8 = (long long)((c->d.nx + 7) / 8) * ((c->d.ny + 7) / 8);
     if (c->d.flux == DG_FLUX_KPP)
       r.waves = dgk::split_waves(t8, c->cus, c->d.p);
     else
-      r.waves = t8 <= (long long)c->cus ? 4 : 1;
+      r.waves = t8 <= 3LL * c->cus ? 4 : 1;
   }
   r.args.uin = uin;
   r.args.un = un;
