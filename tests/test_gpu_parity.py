@@ -310,6 +310,31 @@ def test_tile_shape_independence(kind, p):
         assert torch.equal(U, outs[0][0]) and torch.equal(L, outs[0][1])
 
 
+@pytest.mark.parametrize("kind", ["rot2d", "burgers2d"])
+def test_one_wave_and_four_wave_tiles_at_a_larger_mesh(kind):
+    """232^2 cells: 841 8x8 tiles, more than three per compute unit on 256,
+    so 8x8 runs the one-wave tile kernel there (small meshes take the
+    four-wave tile); 3 steps and one operator on 8x8 and 16x16 tiles, P2
+    WENO on a rough state, bitwise equal."""
+    _note(f"[tiles 232^2] {kind}")
+    w = _mesh(kind, 2, 2, n2=(232, 232))
+    if kind == "rot2d":
+        w.cy = 0.4537
+    g = _dg().DG.from_workload(w)
+    g.set_fused(0)
+    U0 = g.initial_state(w)
+    gen = torch.Generator(device=U0.device).manual_seed(9)
+    U0 = U0 + 0.02 * U0.abs().max() * torch.randn(U0.shape, generator=gen, device=U0.device, dtype=U0.dtype)
+    outs = []
+    for tile in ((8, 8), (16, 16)):
+        g.set_tile(*tile)
+        U = U0.clone()
+        g.run(U, w.dt(), 3)
+        outs.append((U, g.rhs(U0)))
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+
+
 def test_stable_dt_and_finite_check():
     _note("[stable dt]")
     w = inputs.burgers2d(48, 2, ny=40, steps=1)
