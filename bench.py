@@ -75,7 +75,7 @@ def workload(name):
 # (rocprofv3 SQ_INSTS_VALU_{FMA,ADD,MUL,TRANS}_F64 per wave, one lane per
 # cell, FMA counted twice; profiles/stage_kernel_hbm_counters.md): the
 # per-unit figure of the arithmetic roofline.  Keyed by (dim, p, flux, mode).
-FLOPS_PER_CELL_STAGE = {(2, 2, 0, 2): 1088.0, (2, 3, 0, 2): 2261.0, (2, 2, 1, 2): 1146.0}
+FLOPS_PER_CELL_STAGE = {(2, 2, 0, 2): 1088.0, (2, 3, 0, 2): 2261.0, (2, 2, 1, 2): 1146.0, (1, 2, 3, 2): 849.0}
 FP64_PEAK_TFLOPS = 78.6
 
 
@@ -499,7 +499,8 @@ def fused_roofline(w, wname, sec, steps):
     return {"bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": ach / FP64_PEAK_TFLOPS if ach else None,
             "traffic": traffic_for(wname + ":step"),
-            "kernel": f"step_kernel<{w.dim},{w.p},{w.flux},{w.mode}> (fused SSP-RK3 step)",
+            "kernel": (f"euler_step_kernel<{w.p},{w.mode}>" if w.flux == 3 else
+                       f"step_kernel<{w.dim},{w.p},{w.flux},{w.mode}>") + " (fused SSP-RK3 step)",
             "flops_per_launch": flops, "avg_launch_us": avg * 1e6,
             "hbm_bytes_per_launch": 16.0 * w.ndof,
             "hbm_frac": 16.0 * w.ndof / avg / 1e9 / HBM_PEAK_GBS}

@@ -256,13 +256,16 @@ int dg_get_tile(const dg_ctx* ctx, int32_t* tx, int32_t* ty);
  * loads U^n on itself and three rings of cells around it and evaluates the
  * stages on shrinking rings in LDS, so one step moves U^n and U^(n+1) through
  * HBM once.  Same per-cell arithmetic as the per-stage kernel, so results are
- * bitwise the same.  Used by dg_step and dg_run.  mode: -1 automatic (default: on
- * in 1D, and in 2D for meshes of at most one 16x16 tile per compute unit,
- * where per-stage launches are latency bound, except for the KPP flux), 0
- * off, 1 on.  Errors:
+ * bitwise the same.  The Euler system has a step kernel of its own (three
+ * components per cell, walls handled by the cell code).  Used by dg_step and
+ * dg_run.  mode: -1 automatic (default: on in 1D (for the Euler system up
+ * to four 256-cell tiles per compute unit), and in 2D for meshes of at most
+ * one 16x16 tile per compute unit, where per-stage launches are latency
+ * bound, except for the KPP flux), 0 off, 1 on.  Errors:
  * DG_EINVAL for another mode, DG_EUNSUPPORTED for mode 1 when the three
- * tiles exceed LDS (2D degree 4), rk_order is not 3, bc_kind is not
- * CONSTANT or the flux is Euler; in those cases the automatic mode never uses it.  dg_get_fused writes 1 if steps use it.
+ * tiles exceed LDS (2D degree 4), rk_order is not 3 or bc_kind is not
+ * CONSTANT; in those cases the automatic mode never uses it.  dg_get_fused
+ * writes 1 if steps use it.
  * Mode 0 also makes the adjoint (below) launch its two passes of every stage
  * separately instead of sharing launches between consecutive stages; the
  * result is bitwise the same either way. */

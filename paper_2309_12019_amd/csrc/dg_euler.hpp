@@ -172,6 +172,116 @@ __global__ void __launch_bounds__(TX) euler_stage_kernel(const StageArgs A) {
   euler_stage_tile<P, MODE, TX>(A, lds, blockIdx.x * TX);
 }
 
+// The fused SSP-RK3 step of the Euler system: all three stages of a step in
+// one launch, as the scalar step kernel does.  A tile of kEulerStepTile cells
+// loads U^n on itself and three cells each side (tile A), evaluates stage 1
+// on the tile and two cells each side (tile B), stage 2 on one cell each
+// side (tile C) and stage 3 on the tile, straight to HBM; U^n for the RK
+// combinations comes from tile A.  The cell arithmetic is EulerCell's and
+// the combination the per-stage kernel's, in the same order, so the result
+// is the same bit for bit.  Slots outside a wall hold the constant exterior
+// state: the cell code reads them and discards what it read (the wall takes
+// the mirror state, the sensor ignores the missing neighbour), so they need
+// only be finite.  In 1D the rings cost 6 cells in 256 and a step moves U^n
+// and U^(n+1) through HBM once (16 B per DOF instead of 64).
+constexpr int kEulerStepTile = 256;
+constexpr int kEulerStepThreads = 320;  // stage 1 covers 260 cells in one round
+__host__ __device__ inline int euler_step_lds_doubles(int p) {
+  constexpr int T = kEulerStepTile;
+  return 3 * (p + 1) * (((T + 6) | 1) + ((T + 4) | 1) + ((T + 2) | 1));
+}
+
+// One stage of the fused Euler step: output cells o < nout at mesh x index
+// gx0 + o, from the input tile tin (interior width TXI, slots TXI + 2; cell o
+// at slot o + 1) and U^n in tile A (cell o at slot o + aoff).  LAST: store
+// the tile's own in-mesh cells to A.out, else every slot of tout.
+template <int P, int MODE, int TXI, bool LAST>
+__device__ inline void euler_fused_stage(const StageArgs& A, const double* tin, const double* ta, int aoff,
+                                         double* tout, int nout, int gx0, double a, double b) {
+  using E = EulerCell<P, MODE, TXI>;
+  using C = typename E::C;
+  constexpr int N = E::N, NLE = 3 * N, S = E::S;
+  constexpr int SA = (kEulerStepTile + 6) | 1;
+  constexpr int SO = (TXI + 2 - 2) | 1;  // output tile: two slots fewer
+  for (int o = threadIdx.x; o < nout; o += kEulerStepThreads) {
+    const int gx = gx0 + o;
+    int wx, wy;
+    if (!step_cell<1>(A, gx, 0, wx, wy) || (LAST && gx >= A.nx)) {
+      if constexpr (!LAST) {
+#pragma unroll
+        for (int j = 0; j < NLE; ++j) tout[j * SO + o] = j == 0 ? A.bc : 0.0;
+      }
+      continue;
+    }
+    const double* bs = tin + (o + 1);
+    double c[3][N], rho[N];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int q = 0; q < N; ++q) c[k][q] = bs[(k * N + q) * S];
+#pragma unroll
+    for (int q = 0; q < N; ++q) rho[q] = c[0][q];
+    const double gam = C::template gamma_of<true>(A, bs, rho, wx, 0);
+    double R[3][N], lam;
+    E::residual(A, bs, c, wx, R, lam);
+    double out[NLE];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      double L[N];
+      C::finish(A, c[k], gam, lam, R[k], L);
+#pragma unroll
+      for (int q = 0; q < N; ++q) out[k * N + q] = b * fma(A.dt, L[q], c[k][q]);
+    }
+    if (a != 0.0) {
+#pragma unroll
+      for (int j = 0; j < NLE; ++j) out[j] = fma(a, ta[j * SA + o + aoff], out[j]);
+    }
+    if constexpr (LAST) {
+      double* dst = A.out + (size_t)wx * NLE;
+#pragma unroll
+      for (int j = 0; j < NLE; ++j) dst[j] = out[j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < NLE; ++j) tout[j * SO + o] = out[j];
+    }
+  }
+}
+
+// Grid: ceil(nx / kEulerStepTile) tiles, kEulerStepThreads threads, LDS
+// euler_step_lds_doubles(P).  A.uin = U^n, A.out = U^(n+1), two different
+// arrays (tiles run concurrently and read U^n of their neighbours).
+template <int P, int MODE>
+__global__ void __launch_bounds__(kEulerStepThreads) euler_step_kernel(const StageArgs A) {
+  constexpr int T = kEulerStepTile, NLE = 3 * (P + 1);
+  constexpr int SA = (T + 6) | 1, SB = (T + 4) | 1;
+  extern __shared__ double lds[];
+  double* const ta = lds;
+  double* const tb = ta + NLE * SA;
+  double* const tc = tb + NLE * SB;
+  const int ix0 = xcd_tile(blockIdx.x, gridDim.x) * T;
+  // U^n on the tile and three cells each side
+  for (int o = threadIdx.x; o < T + 6; o += kEulerStepThreads) {
+    int wx, wy;
+    double v[NLE];
+    if (step_cell<1>(A, ix0 - 3 + o, 0, wx, wy)) {
+      const double* src = A.uin + (size_t)wx * NLE;
+#pragma unroll
+      for (int j = 0; j < NLE; ++j) v[j] = src[j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < NLE; ++j) v[j] = j == 0 ? A.bc : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < NLE; ++j) ta[j * SA + o] = v[j];
+  }
+  tile_barrier();
+  euler_fused_stage<P, MODE, T + 4, false>(A, ta, ta, 1, tb, T + 4, ix0 - 2, 0.0, 1.0);
+  tile_barrier();
+  euler_fused_stage<P, MODE, T + 2, false>(A, tb, ta, 2, tc, T + 2, ix0 - 1, 0.75, 0.25);
+  tile_barrier();
+  euler_fused_stage<P, MODE, T, true>(A, tc, ta, 3, nullptr, T, ix0, 1.0 / 3.0, 2.0 / 3.0);
+}
+
 // Per-block maximum of lambda_e = max over the volume nodes of |v| + c.
 template <int P>
 __global__ void __launch_bounds__(256) euler_lambda_kernel(const StageArgs A, const double* __restrict__ U,

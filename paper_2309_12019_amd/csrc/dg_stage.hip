@@ -246,6 +246,29 @@ hipError_t launch_euler_m(const StageArgs& A, hipStream_t st) {
   return launch_euler_tile<MODE, 256>(A, st);
 }
 
+// the fused SSP-RK3 step of the Euler system (euler_step_kernel)
+template <int MODE>
+hipError_t launch_euler_step_m(const StageArgs& A, hipStream_t st) {
+  auto k = euler_step_kernel<DGK_P, MODE>;
+  const size_t lds = sizeof(double) * (size_t)euler_step_lds_doubles(DGK_P);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k, dim3((A.nx + kEulerStepTile - 1) / kEulerStepTile), dim3(kEulerStepThreads), lds, st, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_euler_step(int mode, const StageArgs& A, hipStream_t s) {
+  switch (mode) {
+    case MODE_DG: return launch_euler_step_m<MODE_DG>(A, s);
+    case MODE_LO: return launch_euler_step_m<MODE_LO>(A, s);
+    case MODE_ZHAO: return launch_euler_step_m<MODE_ZHAO>(A, s);
+    default: return launch_euler_step_m<MODE_WENO>(A, s);
+  }
+}
+
 hipError_t launch_euler(int mode, const StageArgs& A, hipStream_t s) {
   switch (mode) {
     case MODE_DG: return launch_euler_m<MODE_DG>(A, s);
@@ -326,6 +349,9 @@ extern "C" hipError_t DGK_CAT(dgk_launch, DGK_DIM, DGK_P)(const LaunchReq* r) {
       return hipErrorInvalidValue;
     }
     case LAUNCH_STEP: {
+      if constexpr (DGK_DIM == 1) {
+        if (r->flux == FLUX_EULER) return launch_euler_step(r->mode, A, r->stream);
+      }
       if (r->flux == FLUX_LINADV) return launch_step_f<FLUX_LINADV>(r->mode, A, r->stream);
       if (r->flux == FLUX_BURGERS) return launch_step_f<FLUX_BURGERS>(r->mode, A, r->stream);
       if constexpr (DGK_DIM == 2) return launch_step_f<FLUX_KPP>(r->mode, A, r->stream);

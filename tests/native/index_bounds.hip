@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../paper_2309_12019_amd/csrc/dg_batch_plan.hpp"
+#include "../../paper_2309_12019_amd/csrc/dg_euler.hpp"
 #include "../../paper_2309_12019_amd/csrc/dg_launch.hpp"
 
 using namespace dgk;
@@ -510,6 +511,49 @@ void check_roles(int nl) {
   }
 }
 
+// The fused Euler step (euler_step_kernel) on an nx-cell mesh: the loads of
+// tile A read cells inside the mesh, every stage reads its input slots and
+// U^n slots inside their tiles and writes inside its output tile, the three
+// tiles fit the LDS size, and the last stage writes each mesh cell once.
+void check_euler_step(int nx, int per, int p) {
+  constexpr int T = kEulerStepTile;
+  const int nle = 3 * (p + 1);
+  const long long sa = (T + 6) | 1, sb = (T + 4) | 1, sc = (T + 2) | 1;
+  CHECK(euler_step_lds_doubles(p) == nle * (sa + sb + sc), "euler step: LDS size");
+  StageArgs A{};
+  A.nx = nx;
+  A.ny = 1;
+  A.per_x = per;
+  std::vector<int> written(nx, 0);
+  const int tiles = (nx + T - 1) / T;
+  for (int k = 0; k < tiles; ++k) {
+    const int ix0 = xcd_tile(k, tiles) * T;
+    for (int o = 0; o < T + 6; ++o) {
+      int wx, wy;
+      if (step_cell<1>(A, ix0 - 3 + o, 0, wx, wy)) CHECK(wx >= 0 && wx < nx, "euler step: load of cell %d", wx);
+    }
+    // stages: (input interior width, output cells, first x, U^n offset)
+    const int txi[3] = {T + 4, T + 2, T}, gx0[3] = {ix0 - 2, ix0 - 1, ix0}, aoff[3] = {1, 2, 3};
+    for (int st = 0; st < 3; ++st) {
+      const int nout = txi[st];
+      for (int t = 0; t < kEulerStepThreads; ++t)
+        for (int o = t; o < nout; o += kEulerStepThreads) {
+          const int gx = gx0[st] + o;
+          CHECK(o + 2 < txi[st] + 2, "euler step: stage %d input slots of cell %d", st, o);  // o - 1 + 1 .. o + 1 + 1
+          CHECK(o + aoff[st] < T + 6, "euler step: U^n slot of cell %d", o);
+          if (st < 2) CHECK(o < ((txi[st]) | 1), "euler step: output slot %d", o);
+          int wx, wy;
+          const bool in = step_cell<1>(A, gx, 0, wx, wy);
+          if (st == 2 && in && gx < nx) {
+            CHECK(wx == gx, "euler step: last stage cell %d wrapped", gx);
+            if (wx >= 0 && wx < nx) written[wx]++;
+          }
+        }
+    }
+  }
+  for (int e = 0; e < nx; ++e) CHECK(written[e] == 1, "euler step: cell %d written %d times (nx %d)", e, written[e], nx);
+}
+
 // xcd_tile is a bijection of [0, g) for every grid size, and each XCD's
 // workgroups take one contiguous, increasing run of tiles.
 void check_xcd_order() {
@@ -556,6 +600,9 @@ int main(int argc, char** argv) {
     }
   for (int p = 1; p <= 4; ++p) check_kpp_split(p);
   for (int nl : {4, 9, 16, 25}) check_roles(nl);
+  for (int nx : {1, 2, 3, 128, 255, 256, 257, 600, 4096 + 17})
+    for (int per : {0, 1})
+      for (int p = 1; p <= 4; ++p) check_euler_step(nx, per, p);
   static_assert(splits_nodes(2, FLUX_KPP, 8, 8) && !splits_nodes(2, FLUX_KPP, 16, 16) &&
                     !splits_nodes(2, FLUX_BURGERS, 8, 8),
                 "the node split: 2D KPP on 8x8 tiles only");

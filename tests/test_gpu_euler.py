@@ -101,13 +101,18 @@ def test_sod_100_steps(p, mode):
     U0 = O.project(w.ic)
     ref = O.run(U0, w.dt(), 100)
     g = _dg().DG.from_workload(w)
-    assert not g.fused()
-    U = U0.reshape(128, -1).cuda().contiguous()
-    g.run(U, w.dt(), 100)
-    torch.cuda.synchronize()
-    err = relinf(U.cpu().reshape(ref.shape), ref)
-    _note(f"    rel Linf = {err:.3e}")
-    assert err <= 1e-11
+    assert g.fused()                          # small 1D meshes: the fused step kernel by default
+    outs = []
+    for fused in (1, 0):
+        g.set_fused(fused)
+        U = U0.reshape(128, -1).cuda().contiguous()
+        g.run(U, w.dt(), 100)
+        torch.cuda.synchronize()
+        err = relinf(U.cpu().reshape(ref.shape), ref)
+        _note(f"    {'fused' if fused else 'per-stage'}: rel Linf = {err:.3e}")
+        assert err <= 1e-11
+        outs.append(U)
+    assert torch.equal(outs[0], outs[1])
 
 
 def test_stable_dt_matches_the_oracle():
@@ -125,8 +130,6 @@ def test_refusals():
     w = _workload(64, 2, inputs.MODE_WENO)
     g = dgweno.DG.from_workload(w)
     U = g.initial_state(w)
-    with pytest.raises(dgweno.DGError):
-        g.set_fused(1)
     with pytest.raises(dgweno.DGError):
         g.rhs_vjp(U, U.clone())
     with pytest.raises(dgweno.DGError):
@@ -238,12 +241,38 @@ def test_tile_shape_independence(p):
     out = []
     for tx in (256, 64):
         g = _dg().DG.from_workload(w)
+        g.set_fused(0)
         g.set_tile(tx)
         U = g.initial_state(w)
         g.run(U, w.dt(), 20)
         torch.cuda.synchronize()
         out.append(U.cpu())
     assert torch.equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("n,periodic,p,mode", [(1, False, 2, inputs.MODE_WENO), (2, False, 2, inputs.MODE_WENO),
+                                                (3, True, 2, inputs.MODE_WENO), (257, False, 2, inputs.MODE_WENO),
+                                                (600, True, 1, inputs.MODE_WENO), (600, False, 3, inputs.MODE_LO),
+                                                (600, True, 4, inputs.MODE_ZHAO), (600, False, 2, inputs.MODE_DG)])
+def test_fused_step_equals_stage_launches(n, periodic, p, mode):
+    """The fused Euler step (three stages in one launch on a tile with three
+    rings) against three stage launches: bitwise equal after 30 steps, with
+    walls and periodic meshes, ragged tiles, a single cell, every degree and
+    mode."""
+    _note(f"[euler fused] n={n} periodic={periodic} P{p} mode={mode}")
+    w = _workload(n, p, mode, periodic)
+    if n < 8:
+        w.ic = _density_wave_at_rest
+    outs = []
+    for fused in (1, 0):
+        g = _dg().DG.from_workload(w)
+        g.set_fused(fused)
+        assert g.fused() == bool(fused)
+        U = g.initial_state(w)
+        g.run(U, w.dt(), 30)
+        torch.cuda.synchronize()
+        outs.append(U)
+    assert torch.equal(outs[0], outs[1])
 
 
 def test_full_size_parity():
@@ -256,7 +285,7 @@ def test_full_size_parity():
     O = _oracle(w)
     U0 = O.project(w.ic)
     g = _dg().DG.from_workload(w)
-    assert g.tile() == (256, 1)
+    assert g.tile() == (256, 1) and not g.fused()   # 4096 tiles: the per-stage kernel
     Ug = g.initial_state(w)
     torch.cuda.synchronize()
     assert relinf(Ug.cpu().reshape(U0.shape), U0) <= 1e-13
