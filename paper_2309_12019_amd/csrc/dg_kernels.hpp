@@ -1237,8 +1237,8 @@ __global__ void __launch_bounds__(DIM == 2 ? TX * TY : TX) stage_kernel(const St
 }
 
 // Small meshes on 8 x 8 tiles (the linear and Burgers fluxes): four waves
-// per tile.  With no more tiles than compute units, one-wave tiles leave
-// three of each compute unit's four SIMDs idle and every lane runs its
+// per tile.  With few tiles per compute unit (the library takes this kernel
+// up to three), one-wave tiles leave SIMDs idle and every lane runs its
 // cell's whole stage as one dependent chain; here the parts of the stage
 // run side by side on the tile's four waves:
 //   * wave 0 loads the tile (as stage_tile does) and evaluates the volume
