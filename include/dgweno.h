@@ -261,7 +261,8 @@ int dg_get_tile(const dg_ctx* ctx, int32_t* tx, int32_t* ty);
  * dg_run.  mode: -1 automatic (default: on in 1D (for the Euler system up
  * to four 256-cell tiles per compute unit), and in 2D for meshes of at most
  * one 16x16 tile per compute unit, where per-stage launches are latency
- * bound, except for the KPP flux), 0 off, 1 on.  Errors:
+ * bound, and of at most four for degree 1 and for degree-2 Burgers, except
+ * for the KPP flux), 0 off, 1 on.  Errors:
  * DG_EINVAL for another mode, DG_EUNSUPPORTED for mode 1 when the three
  * tiles exceed LDS (2D degree 4), rk_order is not 3 or bc_kind is not
  * CONSTANT; in those cases the automatic mode never uses it.  dg_get_fused
@@ -271,6 +272,17 @@ int dg_get_tile(const dg_ctx* ctx, int32_t* tx, int32_t* ty);
  * result is bitwise the same either way. */
 int dg_set_fused(dg_ctx* ctx, int32_t mode);
 int dg_get_fused(const dg_ctx* ctx, int32_t* active);
+
+/* Launch shape of the fused step kernel (eq. (ssp)): 1D 256 cells (ty
+ * ignored); 2D 16 columns of 16 or 8 rows, (tx, ty) in {(16,16), (16,8)}.
+ * The result does not depend on it (per-cell arithmetic is identical).
+ * Default, chosen per mesh until set: 16x8 on 2D meshes of at most a quarter
+ * as many 16x16 tiles as the GPU has compute units, or of more than one per
+ * compute unit up to degree 2; else 16x16.  Takes effect while steps use the
+ * fused kernel.
+ * Errors: DG_EINVAL for another shape. */
+int dg_set_step_tile(dg_ctx* ctx, int32_t tx, int32_t ty);
+int dg_get_step_tile(const dg_ctx* ctx, int32_t* tx, int32_t* ty);
 
 /* Replace the stream the context queues work on. */
 int dg_set_stream(dg_ctx* ctx, void* stream);

@@ -76,6 +76,8 @@ struct dg_ctx {
   int cus = 256;
   int fused_mode = -1;   // fused step kernel: -1 automatic, 0 off, 1 on
   bool fused = false;    // whether steps use the fused kernel
+  int sty = dgk::kStepTile2D;  // 2D fused step tile: 16 columns of sty rows (16 or 8)
+  bool sty_set = false;        // sty set by dg_set_step_tile (else chosen per mesh)
   double h = 0;
   hipStream_t stream = nullptr;
   hipStream_t capture = nullptr;  // private stream used only to record graphs
@@ -241,6 +243,8 @@ int step_fused(dg_ctx* c, hipStream_t st, const double* Un, double* Uout, double
   r.args.un = Un;
   r.args.out = Uout;
   r.args.dt = dt;
+  r.args.tx = c->d.dim == 1 ? dgk::kStepTile1D : dgk::kStepTile2D;
+  r.args.ty = c->d.dim == 1 ? 1 : c->sty;
   r.stream = st;
   hipError_t e = c->launch(&r);
   if (e != hipSuccess) return hip_fail(e, "step kernel launch");
@@ -697,13 +701,35 @@ bool fused_fits(const dg_ctx* c) {
   if (c->d.bc_kind != DG_BC_CONSTANT) return false;  // its rings take the constant exterior state
   if (c->d.flux == DG_FLUX_EULER)                    // the Euler system's own step kernel
     return sizeof(double) * (size_t)dgk::euler_step_lds_doubles(c->d.p) <= (size_t)c->max_lds;
-  if (c->d.dim == 2 && c->d.p == 4) return false;  // not built (its tiles exceed LDS)
+  if (c->d.dim == 2 && c->d.p == 4) return false;  // not built (its 16x16 tiles exceed LDS)
   const int tx = c->d.dim == 1 ? dgk::kStepTile1D : dgk::kStepTile2D;
-  const int ty = c->d.dim == 1 ? 1 : dgk::kStepTile2D;
+  const int ty = c->d.dim == 1 ? 1 : dgk::kStepTile2D;  // the larger of the two 2D tiles
   return sizeof(double) * (size_t)dgk::step_lds_doubles(c->d.dim, c->nl, tx, ty) <= (size_t)c->max_lds;
 }
 
+long long step_tiles16(const dg_ctx* c) {
+  return (long long)((c->d.nx + 15) / 16) * ((c->d.ny + 15) / 16);
+}
+
+// The 2D fused step tile.  16x8 tiles (up to two workgroups of four waves per
+// compute unit up to P2) spread a small mesh over more compute units and,
+// past one 16x16 tile per compute unit, fill the GPU in finer steps; between
+// a quarter of and one 16x16 tile per compute unit, 16x16 tiles (one
+// workgroup of eight waves per compute unit, fewer ring cells per output
+// cell) are faster, and so they are at P3 on larger meshes (94 KB of LDS
+// leave one four-wave 16x8 workgroup per compute unit).  Measured per step
+// (WENO, rotation / Burgers), 16x16 -> 16x8: P2 128^2 12.0 -> 10.5 / 13.4 ->
+// 11.2 us; 256^2 13.8 -> 15.1 / 15.4 -> 16.9; 384^2 35.0 -> 32.1 / 39.9 ->
+// 31.6; 512^2 48.2 -> 47.6 / 54.4 -> 47.6; P3 128^2 21.1 -> 16.7 / 22.9 ->
+// 18.1; P3 384^2 63.1 -> 79.0 (rotation).
+void resolve_step_tile(dg_ctx* c) {
+  if (c->d.dim != 2 || c->sty_set) return;
+  const long long t16 = step_tiles16(c), cus = c->cus;
+  c->sty = (4 * t16 <= cus || (t16 > cus && c->d.p <= 2)) ? dgk::kStepTile2DHalf : dgk::kStepTile2D;
+}
+
 void resolve_fused(dg_ctx* c) {
+  resolve_step_tile(c);
   if (c->fused_mode == 0 || !fused_fits(c)) {
     c->fused = false;
     return;
@@ -728,9 +754,21 @@ void resolve_fused(dg_ctx* c) {
     c->fused = (c->d.nx + dgk::kEulerStepTile - 1) / dgk::kEulerStepTile <= 4LL * c->cus;
     return;
   }
-  const long long t = c->d.dim == 1 ? dgk::kStepTile1D : dgk::kStepTile2D;
-  const long long tiles = c->d.dim == 1 ? (c->d.nx + t - 1) / t : ((c->d.nx + t - 1) / t) * ((c->d.ny + t - 1) / t);
-  c->fused = c->d.dim == 1 || tiles <= (long long)c->cus;
+  // 2D: up to one 16x16 tile per compute unit the per-stage launches are
+  // latency-bound and the fused step wins (up to 1.5x); beyond, the
+  // per-stage kernel streams, and the fused kernel's recomputed rings cost
+  // about what its saved traffic gains.  On 16x8 tiles it still wins or ties
+  // up to four 16x16 tiles per compute unit for P1 and for P2 Burgers (per step, per-stage ->
+  // fused: P1 rotation 384^2 16.7 -> 15.0 us, 512^2 22.0 -> 22.2; P2 Burgers
+  // 384^2 35.2 -> 31.6, 448^2 42.9 -> 40.6, 512^2 49.7 -> 47.6), but not for
+  // P2 rotation (384^2 31.7 -> 32.1, 448^2 38.9 -> 41.8) or P3 (384^2 58.6
+  // -> 63.1 on 16x16).
+  if (c->d.dim == 1) {
+    c->fused = true;
+    return;
+  }
+  const long long t16 = step_tiles16(c), cus = c->cus;
+  c->fused = t16 <= cus || (t16 <= 4 * cus && (c->d.p == 1 || (c->d.p == 2 && c->d.flux == DG_FLUX_BURGERS)));
 }
 
 int dg_init_mesh(const dg_mesh_desc* desc, dg_ctx** out) {
@@ -1136,6 +1174,28 @@ int dg_set_fused(dg_ctx* c, int32_t mode) {
   c->fused_mode = mode;
   resolve_fused(c);
   drop_graphs(c);
+  return DG_OK;
+}
+
+int dg_set_step_tile(dg_ctx* c, int32_t tx, int32_t ty) {
+  if (!c) return fail(DG_EINVAL, "ctx is NULL");
+  if (c->d.dim == 1) {
+    if (tx != dgk::kStepTile1D) return fail(DG_EINVAL, "1D step tile must be %d cells (got %d)", dgk::kStepTile1D, tx);
+    return DG_OK;
+  }
+  if (tx != dgk::kStepTile2D || (ty != dgk::kStepTile2D && ty != dgk::kStepTile2DHalf))
+    return fail(DG_EINVAL, "2D step tile must be 16x16 or 16x8 (got %dx%d)", tx, ty);
+  c->sty = ty;
+  c->sty_set = true;
+  drop_graphs(c);
+  return DG_OK;
+}
+
+int dg_get_step_tile(const dg_ctx* c, int32_t* tx, int32_t* ty) {
+  if (!c) return fail(DG_EINVAL, "ctx is NULL");
+  const bool d1 = c->d.dim == 1;
+  if (tx) *tx = d1 ? (c->d.flux == DG_FLUX_EULER ? dgk::kEulerStepTile : dgk::kStepTile1D) : dgk::kStepTile2D;
+  if (ty) *ty = d1 ? 1 : c->sty;
   return DG_OK;
 }
 

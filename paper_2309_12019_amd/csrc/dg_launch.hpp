@@ -9,9 +9,11 @@ enum LaunchKind { LAUNCH_STAGE = 0, LAUNCH_PROJECT = 1, LAUNCH_LAMBDA = 2, LAUNC
                   LAUNCH_ADJ_SENSOR = 4, LAUNCH_ADJ_GRAD = 5, LAUNCH_STEP = 6, LAUNCH_ADJ_GRAD_SENSOR = 7,
                   LAUNCH_SIGNATURE = 8 };
 
-// the fused step kernel's tiles
+// the fused step kernel's tiles: 256 cells in 1D; in 2D 16 columns of
+// kStepTile2D or kStepTile2DHalf rows (LAUNCH_STEP: args.ty)
 constexpr int kStepTile1D = 256;
 constexpr int kStepTile2D = 16;
+constexpr int kStepTile2DHalf = 8;
 // the adjoint kernels' 2D tile (rows of 32 cells: longer contiguous runs of
 // the cell-major state than 16x16 for the same 256 threads); 1D adjoint
 // launches use the stage kernel's tile

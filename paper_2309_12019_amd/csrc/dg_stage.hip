@@ -99,8 +99,8 @@ hipError_t launch_stage_fm(const StageArgs& A, hipStream_t st, int waves = 0) {
   }
 }
 
-template <int FLUX, int MODE>
-hipError_t launch_step_fm(const StageArgs& A, hipStream_t st) {
+template <int FLUX, int MODE, int TY>
+hipError_t launch_step_fmt(const StageArgs& A, hipStream_t st) {
   if constexpr (DGK_DIM == 2 && DGK_P == 4) {
     // the three tiles (242 KB) exceed the LDS of a workgroup: not built (the
     // library never selects the fused step here)
@@ -108,7 +108,6 @@ hipError_t launch_step_fm(const StageArgs& A, hipStream_t st) {
   } else {
     constexpr int NL = DGK_DIM == 1 ? DGK_P + 1 : (DGK_P + 1) * (DGK_P + 1);
     constexpr int TX = DGK_DIM == 1 ? kStepTile1D : kStepTile2D;
-    constexpr int TY = DGK_DIM == 1 ? 1 : kStepTile2D;
     using G = StepGeom<DGK_DIM, TX, TY>;
     auto k = step_kernel<DGK_DIM, DGK_P, FLUX, MODE, TX, TY>;
     const size_t lds = sizeof(double) * (size_t)step_lds_doubles(DGK_DIM, NL, TX, TY);
@@ -120,6 +119,17 @@ hipError_t launch_step_fm(const StageArgs& A, hipStream_t st) {
     dim3 grid((A.nx + TX - 1) / TX, DGK_DIM == 2 ? (A.ny + TY - 1) / TY : 1);
     hipLaunchKernelGGL(k, grid, dim3(G::NT), lds, st, A);
     return hipGetLastError();
+  }
+}
+
+// 2D: A.ty = kStepTile2D or kStepTile2DHalf rows per tile
+template <int FLUX, int MODE>
+hipError_t launch_step_fm(const StageArgs& A, hipStream_t st) {
+  if constexpr (DGK_DIM == 1) {
+    return launch_step_fmt<FLUX, MODE, 1>(A, st);
+  } else {
+    if (A.ty == kStepTile2DHalf) return launch_step_fmt<FLUX, MODE, kStepTile2DHalf>(A, st);
+    return launch_step_fmt<FLUX, MODE, kStepTile2D>(A, st);
   }
 }
 

@@ -72,6 +72,9 @@ EXPORTS = {
     "dg_set_tile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
     "dg_set_fused": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "dg_get_fused": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
+    "dg_set_step_tile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
+    "dg_get_step_tile": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_int32)]),
     "dg_get_tile": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_int32)]),
     "dg_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
@@ -319,6 +322,15 @@ class DG:
     def tile(self) -> Tuple[int, int]:
         a, b = ctypes.c_int32(), ctypes.c_int32()
         _check(self.lib.dg_get_tile(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def set_step_tile(self, tx: int, ty: int = 1) -> None:
+        """Fused step kernel's tile (dg_set_step_tile): 2D 16x16 or 16x8."""
+        _check(self.lib.dg_set_step_tile(self.h, int(tx), int(ty)))
+
+    def step_tile(self) -> Tuple[int, int]:
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        _check(self.lib.dg_get_step_tile(self.h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
 
     def initial_state(self, w, on_device: bool = False) -> torch.Tensor:

@@ -264,7 +264,10 @@ void sweep_step() {
       check_step<1, kStepTile1D, 1>(nx, 1, px, 0);
       for (int ny : sizes)
         for (int py = 0; py < 2; ++py)
-          if ((size_t)nx * ny <= 600 * 600) check_step<2, kStepTile2D, kStepTile2D>(nx, ny, px, py);
+          if ((size_t)nx * ny <= 600 * 600) {
+            check_step<2, kStepTile2D, kStepTile2D>(nx, ny, px, py);
+            check_step<2, kStepTile2D, kStepTile2DHalf>(nx, ny, px, py);
+          }
     }
 }
 
@@ -581,11 +584,16 @@ int main(int argc, char** argv) {
   check_split<2, kStepTile2D, kStepTile2D, 2>();
   check_split<2, kStepTile2D, kStepTile2D, 1>();
   check_split<2, kStepTile2D, kStepTile2D, 0>();
+  check_split<2, kStepTile2D, kStepTile2DHalf, 2>();
+  check_split<2, kStepTile2D, kStepTile2DHalf, 1>();
+  check_split<2, kStepTile2D, kStepTile2DHalf, 0>();
   check_split<1, kStepTile1D, 1, 2>();
   check_split<1, kStepTile1D, 1, 1>();
   check_split<1, kStepTile1D, 1, 0>();
   static_assert(split_full(256, 512) == 0 && split_full(324, 512) == 256 && split_full(400, 512) == 400,
                 "16x16 fused step: stage 3 splits every cell, stage 2 the cells past 256, stage 1 none");
+  static_assert(split_full(128, 256) == 0 && split_full(180, 256) == 128 && split_full(240, 256) == 240,
+                "16x8 fused step: stage 3 splits every cell, stage 2 the cells past 128, stage 1 none");
   check_xcd_order();
   sweep_step();
   sweep<1, 256, 1>();

@@ -75,24 +75,36 @@ def test_fused_equals_per_stage_bitwise(name, make, mode):
     U0 = _rough(w, g)
     dt = w.dt()
     res = []
-    for fused in (0, 1):
+    # per-stage, then the fused kernel on each of its tiles (2D: 16x16, 16x8)
+    runs = [(0, None)] + ([(1, 16), (1, 8)] if w.dim == 2 else [(1, None)])
+    for fused, sty in runs:
         g.set_fused(fused)
         assert g.fused() == bool(fused)
+        if sty is not None:
+            g.set_step_tile(16, sty)
+            assert g.step_tile() == (16, sty)
         U = U0.clone()
         g.step(U, dt)            # one step (odd count: ends with the copy back)
         g.run(U, dt, 6)          # graph replay, even count
         g.run(U, dt, 3)          # graph replay, odd count
         torch.cuda.synchronize()
         res.append(U)
-    assert torch.equal(res[0], res[1])
+    for r in res[1:]:
+        assert torch.equal(res[0], r)
 
 
 def test_fused_automatic_choice_and_errors():
     dgweno = _dg()
     small = dgweno.DG.from_workload(inputs.rot2d(256, 2, seed=0))
     assert small.fused()                      # 256 tiles: latency-bound size
-    large = dgweno.DG.from_workload(inputs.burgers2d(512, 2, seed=0, steps=1))
-    assert not large.fused()                  # 1024 tiles: bandwidth-bound size
+    large = dgweno.DG.from_workload(inputs.burgers2d(1024, 2, seed=0, steps=1))
+    assert not large.fused()                  # 4096 tiles: bandwidth-bound size
+    # up to four 16x16 tiles per compute unit: fused for P1 and P2 Burgers
+    assert dgweno.DG.from_workload(inputs.burgers2d(512, 2, seed=0, steps=1)).fused()
+    assert dgweno.DG.from_workload(inputs.rot2d(512, 1, seed=0, steps=1)).fused()
+    assert not dgweno.DG.from_workload(inputs.rot2d(384, 2, seed=0, steps=1)).fused()
+    assert not dgweno.DG.from_workload(inputs.burgers2d(384, 3, seed=0, steps=1)).fused()
+    assert not dgweno.DG.from_workload(inputs.burgers2d(640, 2, seed=0, steps=1)).fused()
     assert dgweno.DG.from_workload(inputs.adv1d(1 << 20, 2)).fused()
     p4 = dgweno.DG.from_workload(inputs.rot2d(32, 4, seed=0))
     assert not p4.fused()                     # three degree-4 tiles exceed LDS
@@ -114,6 +126,27 @@ def test_fused_automatic_choice_and_errors():
     assert dgweno.DG.from_workload(inputs.kpp2d(512, 2, steps=1)).tile() == (16, 16)
     assert dgweno.DG.from_workload(inputs.burgers2d_riemann(128, 2)).tile() == (8, 8)
     assert small.tile() == (16, 16) and large.tile() == (16, 16)
+    # the fused step's tile: 16x8 up to a quarter of and past one 16x16 tile
+    # per compute unit, 16x16 in between; dg_set_step_tile fixes it
+    assert small.step_tile() == (16, 16)
+    mid = dgweno.DG.from_workload(inputs.rot2d(128, 2, seed=0))
+    assert mid.fused() and mid.step_tile() == (16, 8)
+    assert dgweno.DG.from_workload(inputs.rot2d(192, 2, seed=0)).step_tile() == (16, 16)
+    assert large.step_tile() == (16, 8)
+    assert dgweno.DG.from_workload(inputs.rot2d(384, 3, seed=0, steps=1)).step_tile() == (16, 16)
+    assert dgweno.DG.from_workload(inputs.rot2d(128, 3, seed=0, steps=1)).step_tile() == (16, 8)
+    mid.set_step_tile(16, 16)
+    assert mid.step_tile() == (16, 16)
+    mid.set_fused(-1)
+    assert mid.step_tile() == (16, 16)        # kept once set
+    for bad in ((16, 4), (8, 8), (8, 16), (32, 8)):
+        with pytest.raises(dgweno.DGError):
+            mid.set_step_tile(*bad)
+    one_d = dgweno.DG.from_workload(inputs.adv1d(1000, 2))
+    assert one_d.step_tile() == (256, 1)
+    one_d.set_step_tile(256)
+    with pytest.raises(dgweno.DGError):
+        one_d.set_step_tile(64)
     # degrees 3 and 4 take 8x8 tiles on any mesh
     assert dgweno.DG.from_workload(inputs.rot2d(1024, 3, seed=0, steps=1)).tile() == (8, 8)
     assert dgweno.DG.from_workload(inputs.burgers2d(512, 4, seed=0, steps=1)).tile() == (8, 8)
