@@ -290,9 +290,42 @@ struct Cell {
     }
   }
 
-  // c^T B c with the sensor's quadratic form (zero entries skipped at compile time)
-  // (the first term of every sum is a product: no zero to add to)
+  // whether the sensor's B is diagonal (up to P2), and whether i is the
+  // first index of the group of diagonal entries equal to B[i][i]
+  __host__ __device__ static constexpr bool sn_diagonal() {
+    for (int i = 0; i < NL; ++i)
+      for (int j = 0; j < NL; ++j)
+        if (i != j && TB::sn.B[i][j] != 0.0) return false;
+    return true;
+  }
+  __host__ __device__ static constexpr bool sn_group_head(int i) {
+    for (int j = 1; j < i; ++j)
+      if (TB::sn.B[j][j] == TB::sn.B[i][i]) return false;
+    return TB::sn.B[i][i] != 0.0;
+  }
+
+  // v^T B v with the sensor's quadratic form over the non-constant
+  // coefficients, zero entries skipped at compile time (the first term of
+  // every sum is a product: no zero to add to).  A diagonal B takes equal
+  // entries once, B_g times the sum of v_i^2 over the group g (in 2D the
+  // axis swap maps B to itself, so its entries come in pairs).
   __device__ static inline double qform(const double (&v)[NL]) {
+    if constexpr (sn_diagonal()) {
+      double acc = 0.0;
+      bool started = false;
+#pragma unroll
+      for (int i = 1; i < NL; ++i) {
+        if (sn_group_head(i)) {
+          double sq = v[i] * v[i];
+#pragma unroll
+          for (int j = i + 1; j < NL; ++j)
+            if (TB::sn.B[j][j] == TB::sn.B[i][i]) sq = fma(v[j], v[j], sq);
+          acc = started ? fma(TB::sn.B[i][i], sq, acc) : TB::sn.B[i][i] * sq;
+          started = true;
+        }
+      }
+      return acc;
+    }
     double acc = 0.0;
     bool started = false;
 #pragma unroll
@@ -456,8 +489,9 @@ struct Cell {
     if constexpr (FLUX == FLUX_LINADV) {
       return fma(-0.5 * fabs(v), uh - ul, (0.5 * v) * (ul + uh));
     } else {
-      const double sp = fabs(v) * fmax(fabs(ul), fabs(uh));
-      return fma(-0.5 * sp, uh - ul, (0.25 * v) * fma(ul, ul, uh * uh));
+      // -0.5 |v| is exact: the product equals -0.5 (|v| max) bit for bit
+      const double nsp = (-0.5 * fabs(v)) * fmax(fabs(ul), fabs(uh));
+      return fma(nsp, uh - ul, (0.25 * v) * fma(ul, ul, uh * uh));
     }
   }
 
