@@ -75,7 +75,7 @@ def workload(name):
 # (rocprofv3 SQ_INSTS_VALU_{FMA,ADD,MUL,TRANS}_F64 per wave, one lane per
 # cell, FMA counted twice; profiles/stage_kernel_hbm_counters.md): the
 # per-unit figure of the arithmetic roofline.  Keyed by (dim, p, flux, mode).
-FLOPS_PER_CELL_STAGE = {(2, 2, 0, 2): 1088.0, (2, 3, 0, 2): 2261.0, (2, 2, 1, 2): 1146.0, (1, 2, 3, 2): 849.0}
+FLOPS_PER_CELL_STAGE = {(2, 2, 0, 2): 1070.0, (2, 3, 0, 2): 2260.0, (2, 2, 1, 2): 1120.0, (1, 2, 3, 2): 849.0}
 FP64_PEAK_TFLOPS = 78.6
 
 
@@ -143,7 +143,8 @@ def time_gpu(w, steps, warmup, fused=None, g=None, U0=None):
     bad = g.count_nonfinite(U)
     if bad:
         raise RuntimeError(f"{bad} non-finite values after the timed run")
-    return dict(wall=wall, event_ms=ev_ms, ndof=w.ndof, steps=steps, tile=g.tile(), fused=g.fused(), dt=dt)
+    return dict(wall=wall, event_ms=ev_ms, ndof=w.ndof, steps=steps, tile=g.tile(), fused=g.fused(), dt=dt,
+                step_tile=g.step_tile())
 
 
 def cpu_model():
@@ -455,7 +456,27 @@ def copy_probe(mib):
     print(json.dumps({"copy_probe_bytes": n * 8, "copies": 3}), flush=True)
 
 
-def stage_roofline(w, wname, sec, launches, copy_gbs=None):
+def stage_kernel_name(w, tile):
+    """The per-stage kernel the library launches for this workload and tile
+    (2D 8x8: KPP spreads each tile over several waves; the other fluxes take
+    four-wave tiles up to three 8x8 tiles per compute unit)."""
+    if w.flux == 3:
+        return f"euler_stage_kernel<{w.p},{w.mode}>"
+    if w.dim == 1:
+        return f"stage_kernel<1,{w.p},{w.flux},{w.mode},{tile[0]},1>"
+    tx, ty = tile
+    if (tx, ty) == (8, 8):
+        if w.flux == 2:
+            return f"kpp_split_kernel<{w.p},{w.mode}> (8x8)"
+        import torch
+        cus = torch.cuda.get_device_properties(0).multi_processor_count
+        t8 = ((w.nx + 7) // 8) * ((w.ny + 7) // 8)
+        if t8 <= 3 * cus:
+            return f"roles_kernel<{w.p},{w.flux},{w.mode}> (8x8, four waves)"
+    return f"stage_kernel<{w.dim},{w.p},{w.flux},{w.mode},{tx},{ty}>"
+
+
+def stage_roofline(w, wname, sec, launches, copy_gbs=None, tile=(16, 16)):
     """HBM roofline of the per-stage kernel over `launches` launches taking
     `sec` in all: algorithmic bytes per launch (16 B per DOF for the first
     stage, 24 B for the others: 64/3 B on average for SSP-RK3) over the
@@ -468,9 +489,7 @@ def stage_roofline(w, wname, sec, launches, copy_gbs=None):
     key = (w.dim, w.p, w.flux, w.mode)
     roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": ach / HBM_PEAK_GBS, "traffic": traffic_for(wname),
-            "kernel": (f"euler_stage_kernel<{w.p},{w.mode}>" if w.flux == 3 else
-                       f"stage_kernel<{w.dim},{w.p},{w.flux},{w.mode},16,16>" if w.dim == 2 else
-                       f"stage_kernel<1,{w.p},{w.flux},{w.mode},256,1>"),
+            "kernel": stage_kernel_name(w, tile),
             "bytes_per_dof": bpd, "bytes_per_launch": bpd * w.ndof, "avg_launch_us": avg * 1e6}
     if copy_gbs:
         roof["frac_of_measured_copy"] = ach / copy_gbs
@@ -487,7 +506,7 @@ def stage_roofline(w, wname, sec, launches, copy_gbs=None):
     return roof
 
 
-def fused_roofline(w, wname, sec, steps):
+def fused_roofline(w, wname, sec, steps, step_tile=None):
     """The fused step kernel (one launch per step: U^n in, U^(n+1) out, three
     stages of arithmetic): FP64 rate from the per-stage kernel's executed
     flops per cell (recomputed rings not counted) against the FP64 vector
@@ -500,7 +519,9 @@ def fused_roofline(w, wname, sec, steps):
             "frac": ach / FP64_PEAK_TFLOPS if ach else None,
             "traffic": traffic_for(wname + ":step"),
             "kernel": (f"euler_step_kernel<{w.p},{w.mode}>" if w.flux == 3 else
-                       f"step_kernel<{w.dim},{w.p},{w.flux},{w.mode}>") + " (fused SSP-RK3 step)",
+                       f"step_kernel<{w.dim},{w.p},{w.flux},{w.mode}" +
+                       (f",{step_tile[0]},{step_tile[1]}>" if step_tile and w.dim == 2 else ">")) +
+                      " (fused SSP-RK3 step)",
             "flops_per_launch": flops, "avg_launch_us": avg * 1e6,
             "hbm_bytes_per_launch": 16.0 * w.ndof,
             "hbm_frac": 16.0 * w.ndof / avg / 1e9 / HBM_PEAK_GBS}
@@ -547,9 +568,9 @@ def main():
     sec = r["event_ms"] / 1e3
     dof_rate = STAGES_PER_STEP[w.rk_order] * w.ndof * args.steps / sec
     if r["fused"]:
-        roof = fused_roofline(w, args.workload, sec, args.steps)
+        roof = fused_roofline(w, args.workload, sec, args.steps, r["step_tile"])
     else:
-        roof = stage_roofline(w, args.workload, sec, LAUNCHES_PER_STEP[w.rk_order] * args.steps, cgbs)
+        roof = stage_roofline(w, args.workload, sec, LAUNCHES_PER_STEP[w.rk_order] * args.steps, cgbs, r["tile"])
     del g, U0
     torch.cuda.empty_cache()
     line = {
@@ -588,12 +609,14 @@ def main():
               "rk_order": ko, "fused_step": re_["fused"], "tile": list(re_["tile"]),
               "us_per_step": s_ / k * 1e6, "avg_launch_us": s_ / launches * 1e6}
         if re_["fused"]:
-            ex["roofline"] = fused_roofline(we, name, s_, k)
+            ex["step_tile"] = list(re_["step_tile"])
+            ex["roofline"] = fused_roofline(we, name, s_, k, re_["step_tile"])
             rs = time_gpu(we, k, 5, fused=0, g=ge, U0=Ue)
-            ex["per_stage"] = stage_roofline(we, name, rs["event_ms"] / 1e3, LAUNCHES_PER_STEP[ko] * k, cgbs)
+            ex["per_stage"] = stage_roofline(we, name, rs["event_ms"] / 1e3, LAUNCHES_PER_STEP[ko] * k, cgbs,
+                                             rs["tile"])
             ex["per_stage"]["value"] = STAGES_PER_STEP[ko] * we.ndof * k / (rs["event_ms"] / 1e3)
         else:
-            ex["roofline"] = stage_roofline(we, name, s_, launches, cgbs)
+            ex["roofline"] = stage_roofline(we, name, s_, launches, cgbs, re_["tile"])
         extra[name] = ex
         del ge, Ue
         torch.cuda.empty_cache()
