@@ -737,6 +737,44 @@ struct Cell {
     }
   }
 
+  // g[bb] = sum_q w_q T_bb(x_q) f_q over the Q Gauss nodes of a line, T_bb
+  // = P_bb (DER = false) or P_bb' (DER = true, bb >= 1), with the mirror
+  // symmetry of the rule: T_bb(-x) = +/- T_bb(x), so f enters as the sum
+  // or the difference of each node pair (the first term of each sum a
+  // product; terms with a zero table entry dropped at compile time)
+  template <bool DER>
+  __device__ static inline void line_moments(const double (&f)[Q], double (&g)[N]) {
+    constexpr int H = Q / 2;
+    double sp[H + 1], dp[H + 1];
+#pragma unroll
+    for (int r = 0; r < H; ++r) {
+      sp[r] = f[r] + f[Q - 1 - r];
+      dp[r] = f[r] - f[Q - 1 - r];
+    }
+    if constexpr (Q % 2 == 1) {
+      sp[H] = f[H];
+      dp[H] = 0.0;  // odd functions vanish at the middle node (not used)
+    }
+#pragma unroll
+    for (int bb = DER ? 1 : 0; bb < N; ++bb) {
+      // parity of T_bb: even for P_bb with bb even, for P_bb' with bb odd
+      const bool even = DER ? (bb % 2 == 1) : (bb % 2 == 0);
+      const int nr = even ? (Q + 1) / 2 : H;
+      double acc = 0.0;
+      bool started = false;
+#pragma unroll
+      for (int r = 0; r < nr; ++r) {
+        const double k = TB::nd.w[r] * (DER ? TB::nd.D[bb][r] : TB::nd.L[bb][r]);
+        if (k != 0.0) {
+          const double v = even ? sp[r] : dp[r];
+          acc = started ? fma(k, v, acc) : k * v;
+          started = true;
+        }
+      }
+      g[bb] = acc;
+    }
+  }
+
   // Volume minus face terms of the weak form (R) and the cell's wave speed
   // lambda_e (before the override); the faces in the order -x, +x, -y, +y.
   // FACES = false: the volume terms only (a tile's shared faces are added
@@ -783,36 +821,41 @@ struct Cell {
       for (int qx = 0; qx < Q; ++qx) {
         double s1[N];
         xline([&](int j) { return c[j]; }, qx, s1);
-        double gx[N], gy[N];
+        // the flux at the Q nodes of this x node's line
+        constexpr bool SAMEF = FLUX == FLUX_BURGERS;  // Fy = Fx (u^2)
+        double fx[Q], fy[SAMEF ? 1 : Q];
 #pragma unroll
         for (int qy = 0; qy < Q; ++qy) {
           const double u = ynode(s1, qy);
-          double Fx, Fy;
           if constexpr (FLUX == FLUX_LINADV) {
-            Fx = vxl[qy] * u;
-            Fy = vyl[qx] * u;
+            fx[qy] = vxl[qy] * u;
+            fy[qy] = vyl[qx] * u;
           } else if constexpr (FLUX == FLUX_KPP) {
             if constexpr (VS > 0) {
-              Fx = vol[(qx * Q + qy) * VS];
-              Fy = vol[(Q * Q + qx * Q + qy) * VS];
+              fx[qy] = vol[(qx * Q + qy) * VS];
+              fy[qy] = vol[(Q * Q + qx * Q + qy) * VS];
             } else {
-              sincos_cold(u, &Fx, &Fy);
+              double sn, cs;  // (scalars: the call does not pin the arrays to memory)
+              sincos_cold(u, &sn, &cs);
+              fx[qy] = sn;
+              fy[qy] = cs;
             }
           } else {
-            Fx = u * u;
-            Fy = Fx;
+            fx[qy] = u * u;
             umax = fmax(umax, fabs(u));
           }
-#pragma unroll
-          for (int bb = 0; bb < N; ++bb) {
-            const double cxw = TB::nd.w[qy] * TB::nd.L[bb][qy];
-            gx[bb] = qy == 0 ? cxw * Fx : fma(cxw, Fx, gx[bb]);
-            if (bb > 0) {
-              const double cyw = TB::nd.w[qy] * TB::nd.D[bb][qy];
-              gy[bb] = qy == 0 ? cyw * Fy : fma(cyw, Fy, gy[bb]);
-            }
-          }
         }
+        // gx[bb] = sum_qy w L_bb F_x, gy[bb] = sum_qy w P_bb' F_y over the
+        // line, folded over mirrored node pairs (qy, Q-1-qy): the Gauss
+        // nodes and weights are symmetric and P_bb has the parity of bb, so
+        // even functions take the pair's sum and odd ones its difference
+        // (the middle node of an odd rule only the even ones)
+        double gx[N], gy[N];
+        line_moments<false>(fx, gx);
+        if constexpr (SAMEF)
+          line_moments<true>(fx, gy);
+        else
+          line_moments<true>(fy, gy);
         if constexpr (FLUX == FLUX_BURGERS) {
 #pragma unroll
           for (int bb = 0; bb < N; ++bb) {
