@@ -742,8 +742,20 @@ struct Cell {
   // symmetry of the rule: T_bb(-x) = +/- T_bb(x), so f enters as the sum
   // or the difference of each node pair (the first term of each sum a
   // product; terms with a zero table entry dropped at compile time)
+  __host__ __device__ static constexpr bool nodes_mirrored() {
+    for (int r = 0; r < Q; ++r) {
+      const int m = Q - 1 - r;
+      if (TB::nd.x[r] != -TB::nd.x[m] || TB::nd.w[r] != TB::nd.w[m]) return false;
+      for (int k = 0; k < N; ++k) {
+        const double sg = k % 2 ? -1.0 : 1.0;
+        if (TB::nd.L[k][r] != sg * TB::nd.L[k][m] || TB::nd.D[k][r] != -sg * TB::nd.D[k][m]) return false;
+      }
+    }
+    return true;
+  }
   template <bool DER>
   __device__ static inline void line_moments(const double (&f)[Q], double (&g)[N]) {
+    static_assert(nodes_mirrored(), "the Gauss tables must be mirror-symmetric bit for bit");
     constexpr int H = Q / 2;
     double sp[H + 1], dp[H + 1];
 #pragma unroll
