@@ -127,7 +127,7 @@ struct AdjCell {
 
   // g = (2/h) Mhat^-1 v
   __device__ static inline void scale_g(const StageArgs& A, const double (&v)[NL], double (&g)[NL]) {
-    const double g2h = 2.0 / A.h;
+    const double g2h = A.g2h;
 #pragma unroll
     for (int j = 0; j < NL; ++j) {
       const int a = j % N, bb = j / N;
@@ -427,7 +427,7 @@ struct AdjCell {
   __device__ static inline void face2d(const StageArgs& A, const double* b, const double* bv, const double (&c)[NL],
                                        const double (&g)[NL], const double (&vxl)[Q], const double (&vyl)[Q],
                                        double (&G)[NL]) {
-    const double g2h = 2.0 / A.h;
+    const double g2h = A.g2h;
     constexpr int axis = F >> 1;
     constexpr bool plus = F & 1;
     const double s = plus ? 1.0 : -1.0;
@@ -497,7 +497,7 @@ struct AdjCell {
     const double hh = 0.5 * A.h;
     const double xc = A.x0 + (ix + 0.5) * A.h;
     const double yc = DIM == 2 ? A.y0 + (iy + 0.5) * A.h : 0.0;
-    const double g2h = 2.0 / A.h;
+    const double g2h = A.g2h;
 
     // ---- volume: sum_q w_q (grad g . F'(u_q)) phi(q); for the Burgers flux
     // the same node values give lambda_e and its node (the order and the

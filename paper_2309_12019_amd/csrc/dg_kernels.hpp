@@ -52,6 +52,7 @@ struct StageArgs {
   double theta;                  // exponent of the Zhao et al. sensor (MODE_ZHAO)
   int tx, ty;                    // tile (one of the compiled shapes; ty = 1 in 1D)
   const double* tclock;          // BC_RIEMANN: if set, uin's time is *tclock + t (t an offset)
+  double g2h;                    // 2 / h, formed on the host (the same correctly rounded quotient)
 };
 
 // Tile geometry: TX x TY cells per workgroup (TY = 1 in 1D) plus a one-cell
@@ -1015,7 +1016,7 @@ struct Cell {
                                        const double (&R)[NL], double (&L)[NL]) {
     if (A.lam_over > 0.0) lam = A.lam_over;
     const double kd = gam * lam * (1.0 / P);
-    const double g2h = 2.0 / A.h;
+    const double g2h = A.g2h;
     if constexpr (DIM == 1) {
 #pragma unroll
       for (int a = 0; a < N; ++a) {
