@@ -564,15 +564,9 @@ struct Cell {
     return u;
   }
 
-  // Adds the face flux H at Gauss point r to the moments g of a 2D face
-  // (g is assigned at r = 0)
-  __device__ static inline void face_acc(int r, double H, double (&g)[N]) {
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-      const double cw = TB::nd.w[r] * TB::nd.L[k][r];
-      g[k] = r == 0 ? cw * H : fma(cw, H, g[k]);
-    }
-  }
+  // The moments g[k] = sum_r w_r P_k(x_r) H_r of a 2D face from the face
+  // flux at its Q Gauss points (line_moments: mirrored node pairs)
+  __device__ static inline void face_sum(const double (&H)[Q], double (&g)[N]) { line_moments<false>(H, g); }
 
   // The two states at Gauss point r of a 2D face from the traces
   __device__ static inline void face_node(const double (&tl)[N], const double (&th)[N], int r, double& ul,
@@ -594,6 +588,7 @@ struct Cell {
   __device__ static inline void face_moments(int axis, const double (&tl)[N], const double (&th)[N],
                                              const double (&v)[Q], bool xl, bool xh, const double* ext,
                                              double (&g)[N]) {
+    double H[Q];
 #pragma unroll
     for (int r = 0; r < Q; ++r) {
       double ul, uh;
@@ -602,13 +597,12 @@ struct Cell {
         if (xl) ul = ext[r * S];
         if (xh) uh = ext[r * S];
       }
-      double H;
       if constexpr (FLUX == FLUX_KPP)
-        H = llf_kpp<INL>(axis, ul, uh);
+        H[r] = llf_kpp<INL>(axis, ul, uh);
       else
-        H = llf(v[r], ul, uh);
-      face_acc(r, H, g);
+        H[r] = llf(v[r], ul, uh);
     }
+    face_sum(H, g);
   }
 
   // Adds face f's term - int_f phi H(u^-, u^+, n) to R from the face's
@@ -756,6 +750,10 @@ struct Cell {
   }
   template <bool DER>
   __device__ static inline void line_moments(const double (&f)[Q], double (&g)[N]) {
+    // the pair sums stay plain adds: fused with the products that form f
+    // (as the compiler may choose, kernel by kernel) they would round
+    // differently in different kernels
+#pragma clang fp contract(off)
     static_assert(nodes_mirrored(), "the Gauss tables must be mirror-symmetric bit for bit");
     constexpr int H = Q / 2;
     double sp[H + 1], dp[H + 1];
@@ -1486,7 +1484,7 @@ __global__ void __launch_bounds__(kRoleThreads) roles_kernel(const StageArgs A) 
 // u_h at a node, the face traces and the fluxes are computed by the same
 // functions as in the per-cell path (xline/ynode, trace/face_node,
 // llf_kpp), and wave 0 sums them in the same order (residual with VS = 64,
-// face_acc, add_face), so the result is the same bit for bit.  The node
+// face_sum, add_face), so the result is the same bit for bit.  The node
 // tasks hold few registers, so they take the sine and cosine inline
 // (sincos_inl: no call frame in scratch memory; 7.8 -> 6.3 us per stage at
 // 128^2 P2, 17.1 -> 13.1 at 256^2).
@@ -1562,9 +1560,10 @@ __device__ inline void kpp_split_tile(const StageArgs& A, double* lds, int ix0, 
   for (int f = 0; f < 4; ++f) {
     const int axis = f >> 1;
     const int e = split_cell_face(lc, f);
-    double g[N];
+    double H[Q], g[N];
 #pragma unroll
-    for (int r = 0; r < Q; ++r) C::face_acc(r, fnl[(axis * Q + r) * NFA + e], g);
+    for (int r = 0; r < Q; ++r) H[r] = fnl[(axis * Q + r) * NFA + e];
+    C::face_sum(H, g);
     C::add_face(f, g, R);
   }
   double L[NL];
