@@ -278,8 +278,8 @@ int dg_get_fused(const dg_ctx* ctx, int32_t* active);
  * The result does not depend on it (per-cell arithmetic is identical).
  * Default, chosen per mesh until set: 16x8 on 2D meshes of at most a quarter
  * as many 16x16 tiles as the GPU has compute units, or of more than one per
- * compute unit up to degree 2; else 16x16.  Takes effect while steps use the
- * fused kernel.
+ * compute unit at degree 2 (at degree 1: up to three); else 16x16.  Takes
+ * effect while steps use the fused kernel.
  * Errors: DG_EINVAL for another shape. */
 int dg_set_step_tile(dg_ctx* ctx, int32_t tx, int32_t ty);
 int dg_get_step_tile(const dg_ctx* ctx, int32_t* tx, int32_t* ty);

@@ -722,11 +722,15 @@ long long step_tiles16(const dg_ctx* c) {
 // (WENO, rotation / Burgers), 16x16 -> 16x8: P2 128^2 12.0 -> 10.5 / 13.4 ->
 // 11.2 us; 256^2 13.8 -> 15.1 / 15.4 -> 16.9; 384^2 35.0 -> 32.1 / 39.9 ->
 // 31.6; 512^2 48.2 -> 47.6 / 54.4 -> 47.6; P3 128^2 21.1 -> 16.7 / 22.9 ->
-// 18.1; P3 384^2 63.1 -> 79.0 (rotation).
+// 18.1; P3 384^2 63.1 -> 79.0 (rotation).  At P1 a 16x16 tile needs only
+// 39 KB and is not held to one workgroup per compute unit: 16x8 wins at
+// 384^2 (15.9 -> 15.0) but not at 512^2 (20.9 -> 22.2), so P1 keeps 16x16
+// from three 16x16 tiles per compute unit on.
 void resolve_step_tile(dg_ctx* c) {
   if (c->d.dim != 2 || c->sty_set) return;
   const long long t16 = step_tiles16(c), cus = c->cus;
-  c->sty = (4 * t16 <= cus || (t16 > cus && c->d.p <= 2)) ? dgk::kStepTile2DHalf : dgk::kStepTile2D;
+  const bool beyond = t16 > cus && (c->d.p == 2 || (c->d.p == 1 && t16 <= 3 * cus));
+  c->sty = (4 * t16 <= cus || beyond) ? dgk::kStepTile2DHalf : dgk::kStepTile2D;
 }
 
 void resolve_fused(dg_ctx* c) {
@@ -758,9 +762,10 @@ void resolve_fused(dg_ctx* c) {
   // 2D: up to one 16x16 tile per compute unit the per-stage launches are
   // latency-bound and the fused step wins (up to 1.5x); beyond, the
   // per-stage kernel streams, and the fused kernel's recomputed rings cost
-  // about what its saved traffic gains.  On 16x8 tiles it still wins or ties
-  // up to four 16x16 tiles per compute unit for P1 and for P2 Burgers (per step, per-stage ->
-  // fused: P1 rotation 384^2 16.7 -> 15.0 us, 512^2 22.0 -> 22.2; P2 Burgers
+  // about what its saved traffic gains.  On the tile resolve_step_tile picks
+  // it still wins up to four 16x16 tiles per compute unit for P1 and for P2
+  // Burgers (per step, per-stage ->
+  // fused: P1 rotation 384^2 16.7 -> 15.0 us, 512^2 22.0 -> 20.9; P2 Burgers
   // 384^2 35.2 -> 31.6, 448^2 42.9 -> 40.6, 512^2 49.7 -> 47.6), but not for
   // P2 rotation (384^2 31.7 -> 32.1, 448^2 38.9 -> 41.8) or P3 (384^2 58.6
   // -> 63.1 on 16x16).

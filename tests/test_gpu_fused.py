@@ -134,6 +134,8 @@ def test_fused_automatic_choice_and_errors():
     assert dgweno.DG.from_workload(inputs.rot2d(192, 2, seed=0)).step_tile() == (16, 16)
     assert large.step_tile() == (16, 8)
     assert dgweno.DG.from_workload(inputs.rot2d(384, 3, seed=0, steps=1)).step_tile() == (16, 16)
+    assert dgweno.DG.from_workload(inputs.rot2d(384, 1, seed=0, steps=1)).step_tile() == (16, 8)
+    assert dgweno.DG.from_workload(inputs.rot2d(512, 1, seed=0, steps=1)).step_tile() == (16, 16)
     assert dgweno.DG.from_workload(inputs.rot2d(128, 3, seed=0, steps=1)).step_tile() == (16, 8)
     mid.set_step_tile(16, 16)
     assert mid.step_tile() == (16, 16)
