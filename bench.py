@@ -75,7 +75,7 @@ def workload(name):
 # (rocprofv3 SQ_INSTS_VALU_{FMA,ADD,MUL,TRANS}_F64 per wave, one lane per
 # cell, FMA counted twice; profiles/stage_kernel_hbm_counters.md): the
 # per-unit figure of the arithmetic roofline.  Keyed by (dim, p, flux, mode).
-FLOPS_PER_CELL_STAGE = {(2, 2, 0, 2): 1002.0, (2, 3, 0, 2): 2118.0, (2, 2, 1, 2): 1038.0, (1, 2, 3, 2): 835.0}
+FLOPS_PER_CELL_STAGE = {(2, 2, 0, 2): 990.0, (2, 3, 0, 2): 2118.0, (2, 2, 1, 2): 1026.0, (1, 2, 3, 2): 832.0}
 FP64_PEAK_TFLOPS = 78.6
 
 

@@ -147,6 +147,7 @@ StageArgs base_args(const dg_ctx* c) {
   A.per_y = d.dim == 2 && d.periodic_y != 0;
   A.h = c->h;
   A.g2h = 2.0 / c->h;
+  dgk::stage_lfac(d.dim, d.p, A.g2h, A.lfac);
   A.x0 = d.x0;
   A.y0 = d.dim == 2 ? d.y0 : 0.0;
   A.vx = d.vel_x;

@@ -171,6 +171,7 @@ StageArgs args_of(const dg_mesh_desc& d) {
   A.per_y = d.dim == 2 && d.periodic_y != 0;
   A.h = (d.x1 - d.x0) / d.nx;
   A.g2h = 2.0 / A.h;
+  dgk::stage_lfac(d.dim, d.p, A.g2h, A.lfac);
   A.x0 = d.x0;
   A.y0 = d.dim == 2 ? d.y0 : 0.0;
   A.vx = d.vel_x;

@@ -53,7 +53,27 @@ struct StageArgs {
   int tx, ty;                    // tile (one of the compiled shapes; ty = 1 in 1D)
   const double* tclock;          // BC_RIEMANN: if set, uin's time is *tclock + t (t an offset)
   double g2h;                    // 2 / h, formed on the host (the same correctly rounded quotient)
+  double lfac[25];               // (2/h) minv_a minv_b per coefficient a + (p+1) b (1D: (2/h) minv_a),
+                                 // formed on the host in the same order (stage_lfac)
 };
+
+// The factors of the mass inverse and 2/h that turn a cell's weak-form sums
+// into dU/dt, per coefficient, in the order the kernels multiplied them.
+template <int P>
+inline void stage_lfac_p(int dim, double g2h, double* lf) {
+  constexpr DegTab<P> t = make_deg<P>();
+  constexpr int N = P + 1;
+  for (int bb = 0; bb < (dim == 2 ? N : 1); ++bb)
+    for (int a = 0; a < N; ++a) lf[a + N * bb] = dim == 2 ? (g2h * t.minv[a]) * t.minv[bb] : g2h * t.minv[a];
+}
+inline void stage_lfac(int dim, int p, double g2h, double* lf) {
+  switch (p) {
+    case 1: stage_lfac_p<1>(dim, g2h, lf); break;
+    case 2: stage_lfac_p<2>(dim, g2h, lf); break;
+    case 3: stage_lfac_p<3>(dim, g2h, lf); break;
+    default: stage_lfac_p<4>(dim, g2h, lf); break;
+  }
+}
 
 // Tile geometry: TX x TY cells per workgroup (TY = 1 in 1D) plus a one-cell
 // face halo.  LDS holds the tile coefficient-major: plane j (one per basis
@@ -1008,13 +1028,23 @@ struct Cell {
     }
   }
 
+  // (2/h) minv_a minv_b (1D: (2/h) minv_a): up to P2 the host's product
+  // (the same value; saves the multiplications in every thread), from P3 on
+  // formed here (read from the arguments, its 16-25 values cost the P3 and
+  // P4 kernels registers)
+  __device__ static inline double lfac(const StageArgs& A, int a, int bb) {
+    if constexpr (P <= 2)
+      return A.lfac[a + N * bb];
+    else
+      return DIM == 2 ? A.g2h * TB::dg.minv[a] * TB::dg.minv[bb] : A.g2h * TB::dg.minv[a];
+  }
+
   // Dissipation gamma nu int grad(phi).grad(u_h) and M^-1:
   // L = (2/h) Mhat^-1 [ vol - face - (gamma lambda / p) Khat c ]
   __device__ static inline void finish(const StageArgs& A, const double (&c)[NL], double gam, double lam,
                                        const double (&R)[NL], double (&L)[NL]) {
     if (A.lam_over > 0.0) lam = A.lam_over;
     const double kd = gam * lam * (1.0 / P);
-    const double g2h = A.g2h;
     if constexpr (DIM == 1) {
 #pragma unroll
       for (int a = 0; a < N; ++a) {
@@ -1022,7 +1052,7 @@ struct Cell {
 #pragma unroll
         for (int a2 = 0; a2 < N; ++a2)
           if (TB::dg.S[a][a2] != 0.0) kc = fma(TB::dg.S[a][a2], c[a2], kc);
-        L[a] = (g2h * TB::dg.minv[a]) * fma(-kd, kc, R[a]);
+        L[a] = lfac(A, a, 0) * fma(-kd, kc, R[a]);
       }
     } else {
 #pragma unroll
@@ -1036,7 +1066,7 @@ struct Cell {
 #pragma unroll
           for (int b2 = 0; b2 < N; ++b2)
             if (TB::dg.S[bb][b2] != 0.0) kc = fma(TB::dg.S[bb][b2] * TB::dg.mhat[a], c[a + N * b2], kc);
-          L[a + N * bb] = (g2h * TB::dg.minv[a] * TB::dg.minv[bb]) * fma(-kd, kc, R[a + N * bb]);
+          L[a + N * bb] = lfac(A, a, bb) * fma(-kd, kc, R[a + N * bb]);
         }
     }
   }
